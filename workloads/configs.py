@@ -1,0 +1,209 @@
+"""Seeded synthetic workloads.
+
+The paper's phantoms come from CT Hounsfield units and Monte Carlo data that
+are not available (Sec. 4); these stand-ins keep the paper's structure (water
+boxes, heterogeneous slabs, mixture fractions per voxel, Gaussian pencil
+beams with 1% energy spread, Sec. 4) at the sizes of the benchmark workloads:
+
+  c1  2D water 64x64 cells of 1 mm, 70 MeV beam (sigma 3 mm) along +x,
+      P_7 (64 moments), 100 energy steps, fixed rank 10, FP64
+  c2  2D 200x200 cells of 0.5 mm, water with a 10 mm bone slab (1.85 g/cm^3)
+      and a 20 mm lung slab (0.26 g/cm^3), boundary voxels 50/50 mixtures,
+      150 MeV beam (sigma 4 mm), P_21 (484 moments), 300 steps, adaptive rank
+      (relative tail 1e-4, r <= 40)
+  c3  3D 128^3 cells of 1 mm, density from a seeded Gaussian random field
+      (correlation length 8 mm) mapped to water/bone/air mixtures with
+      densities 0.2..1.9, 150 MeV beam (sigma 5 mm), P_15 (256 moments),
+      fixed rank 30, 250 steps, mixed precision
+  c4  c3's phantom with 64 beams: energies U[70, 230] MeV, axial angles
+      U[0, 2 pi), spot sigma U[3, 6] mm, adaptive ranks in [10, 50]
+  c5  c2's phantom with 9 beams of 100 + 10 b MeV at 40 b degrees aimed at the
+      centre (adjoint workload)
+
+Every random draw uses numpy's PCG64 with the stated seed.  Nothing here
+implements any part of the transport method.
+"""
+from __future__ import annotations
+
+import functools
+import hashlib
+import math
+
+import numpy as np
+from scipy.special import ndtr
+
+from . import materials as M
+from .problem import Beam, Grid, Materials, Options, Problem
+
+
+@functools.lru_cache(maxsize=16)
+def _tables(names: tuple, n_leg: int):
+    mats = [M.BASE_MATERIALS[n] for n in names]
+    return M.build_tables(mats, n_leg)
+
+
+def make_materials(names, w, pn_degree):
+    e, S, T, G0, dG = _tables(tuple(names), pn_degree + 2)
+    return Materials(tuple(names), np.ascontiguousarray(w, dtype=np.float64),
+                     e.copy(), S.copy(), T.copy(), G0.copy(), dG.copy())
+
+
+def sha256(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+# ---------------------------------------------------------------- phantoms
+
+def water_box(grid: Grid, density=1.0):
+    return np.full((1, grid.n), density, dtype=np.float64)
+
+
+def slab_phantom(grid: Grid, slabs, background="water", bg_density=1.0):
+    """Slabs along x: list of (name, density, x0, x1) in cm.  Each voxel's
+    partial density is the volume-fraction-weighted density of what covers it."""
+    names = [background] + [s[0] for s in slabs]
+    uniq = list(dict.fromkeys(names))
+    w = np.zeros((len(uniq), grid.nz, grid.ny, grid.nx))
+    x_lo = np.arange(grid.nx) * grid.dx
+    x_hi = x_lo + grid.dx
+    covered = np.zeros(grid.nx)
+    for name, rho, a, b in slabs:
+        frac = np.clip(np.minimum(x_hi, b) - np.maximum(x_lo, a), 0.0, None) / grid.dx
+        w[uniq.index(name)] += rho * frac[None, None, :]
+        covered += frac
+    w[uniq.index(background)] += bg_density * (1.0 - covered)[None, None, :]
+    w[np.abs(w) < 1e-12] = 0.0
+    return tuple(uniq), w.reshape(len(uniq), -1)
+
+
+def gaussian_random_field(shape, spacing, corr_len, seed):
+    """Periodic Gaussian random field with covariance exp(-d^2/(2 l^2)),
+    normalised to zero mean and unit variance (FFT filter of white noise)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    white = rng.standard_normal(shape)
+    ks = [2.0 * math.pi * np.fft.fftfreq(n, d=spacing) for n in shape]
+    K2 = sum(np.meshgrid(*[k**2 for k in ks], indexing="ij"))
+    filt = np.exp(-0.25 * K2 * corr_len**2)
+    g = np.real(np.fft.ifftn(np.fft.fftn(white) * filt))
+    g -= g.mean()
+    g /= g.std()
+    return g
+
+
+def random_phantom(grid: Grid, seed=3, corr_len=0.8, rho_min=0.2, rho_max=1.9):
+    """Water/bone/air mixtures: rho = rho_min + (rho_max - rho_min) Phi(g);
+    rho <= 1 mixes air (0.0012) and water by volume, rho > 1 water and bone
+    (rho_max)."""
+    shape = (grid.nz, grid.ny, grid.nx)
+    g = gaussian_random_field(shape, grid.dx, corr_len, seed)
+    rho = rho_min + (rho_max - rho_min) * ndtr(g)
+    rho = rho.ravel()
+    rho_air, rho_w, rho_b = M.AIR.density, 1.0, rho_max
+    w = np.zeros((3, grid.n))  # water, bone, air
+    lo = rho <= 1.0
+    fw = (rho[lo] - rho_air) / (rho_w - rho_air)
+    w[0, lo] = fw * rho_w
+    w[2, lo] = (1.0 - fw) * rho_air
+    hi = ~lo
+    fb = (rho[hi] - rho_w) / (rho_b - rho_w)
+    w[0, hi] = (1.0 - fb) * rho_w
+    w[1, hi] = fb * rho_b
+    return ("water", "bone", "air"), w
+
+
+# ---------------------------------------------------------------- configs
+
+def beam_along_x(E0, spot_sigma, y0, z0=0.0, weight=1.0):
+    return Beam(E0=E0, sigma_E=0.01 * E0, spot_sigma=spot_sigma, weight=weight,
+                pos=(0.0, y0, z0), dir=(1.0, 0.0, 0.0))
+
+
+def c1(**opt) -> Problem:
+    grid = Grid(64, 64, 1, 0.1, 0.1, 0.1)
+    o = Options(pn_degree=7, n_steps=100, rank_mode="fixed", r=10, precision="fp64").with_(**opt)
+    mats = make_materials(("water",), water_box(grid), o.pn_degree)
+    return Problem(grid, mats, [beam_along_x(70.0, 0.3, 3.2)], o, name="c1")
+
+
+def c2(**opt) -> Problem:
+    grid = Grid(200, 200, 1, 0.05, 0.05, 0.05)
+    o = Options(pn_degree=21, n_steps=300, rank_mode="adaptive", r=40, r_min=2, r_max=40,
+                trunc_tol=1e-4, precision="fp64").with_(**opt)
+    names, w = slab_phantom(grid, [("bone", 1.85, 3.025, 4.025), ("lung", 0.26, 5.025, 7.025)])
+    mats = make_materials(names, w, o.pn_degree)
+    return Problem(grid, mats, [beam_along_x(150.0, 0.4, 5.0)], o, name="c2")
+
+
+def c3(**opt) -> Problem:
+    grid = Grid(128, 128, 128, 0.1, 0.1, 0.1)
+    o = Options(pn_degree=15, n_steps=250, rank_mode="fixed", r=30, r_max=30,
+                precision="mixed").with_(**opt)
+    names, w = random_phantom(grid, seed=3)
+    mats = make_materials(names, w, o.pn_degree)
+    return Problem(grid, mats, [beam_along_x(150.0, 0.5, 6.4, 6.4)], o, name="c3",
+                   meta={"phantom_sha256": sha256(w)})
+
+
+def aimed_beam(E0, spot, angle, center, radius):
+    d = (math.cos(angle), math.sin(angle), 0.0)
+    pos = (center[0] - radius * d[0], center[1] - radius * d[1], center[2])
+    return Beam(E0=E0, sigma_E=0.01 * E0, spot_sigma=spot, pos=pos, dir=d)
+
+
+def c4(n_beams=64, **opt) -> Problem:
+    p = c3(**opt)
+    rng = np.random.Generator(np.random.PCG64(4))
+    E = rng.uniform(70.0, 230.0, n_beams)
+    ang = rng.uniform(0.0, 2.0 * math.pi, n_beams)
+    spot = rng.uniform(0.3, 0.6, n_beams)
+    c = (6.4, 6.4, 6.4)
+    beams = [aimed_beam(E[b], spot[b], ang[b], c, 10.0) for b in range(n_beams)]
+    o = p.options.with_(rank_mode="adaptive", r=10, r_min=10, r_max=50, trunc_tol=1e-4).with_(**opt)
+    return Problem(p.grid, p.materials, beams, o, name="c4", meta=p.meta)
+
+
+def c5(**opt) -> Problem:
+    p = c2(**opt)
+    c = (5.0, 5.0, 0.0)
+    beams = [aimed_beam(100.0 + 10.0 * b, 0.4, math.radians(40.0 * b), c, 6.0) for b in range(9)]
+    return Problem(p.grid, p.materials, beams, p.options, name="c5")
+
+
+CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+
+
+# ---------------------------------------------------------------- small cases
+
+def small_2d(nx=16, ny=12, N=3, E0=30.0, n_steps=12, spot=0.15, mats="water", r=6,
+             seed=None, dx=0.05, **opt) -> Problem:
+    """Small 2D case for tests: either water, or (mats="slab") water/bone/lung
+    slabs, or (mats="random") a seeded random water/bone/air field."""
+    grid = Grid(nx, ny, 1, dx, dx, dx)
+    o = Options(pn_degree=N, n_steps=n_steps, rank_mode="fixed", r=r, r_max=max(r, 2),
+                precision="fp64").with_(**opt)
+    if mats == "water":
+        names, w = ("water",), water_box(grid)
+    elif mats == "slab":
+        L = nx * dx
+        names, w = slab_phantom(grid, [("bone", 1.85, 0.30 * L, 0.45 * L),
+                                       ("lung", 0.26, 0.60 * L, 0.80 * L)])
+    elif mats == "random":
+        names, w = random_phantom(grid, seed=0 if seed is None else seed, corr_len=4 * dx)
+    else:
+        raise ValueError(mats)
+    m = make_materials(names, w, o.pn_degree)
+    return Problem(grid, m, [beam_along_x(E0, spot, 0.5 * ny * dx + 0.013)], o, name="small_2d")
+
+
+def small_3d(n=8, N=3, E0=25.0, n_steps=8, spot=0.15, mats="random", r=6, dx=0.05,
+             **opt) -> Problem:
+    grid = Grid(n, n, n, dx, dx, dx)
+    o = Options(pn_degree=N, n_steps=n_steps, rank_mode="fixed", r=r, r_max=max(r, 2),
+                precision="fp64").with_(**opt)
+    if mats == "water":
+        names, w = ("water",), water_box(grid)
+    else:
+        names, w = random_phantom(grid, seed=1, corr_len=3 * dx)
+    m = make_materials(names, w, o.pn_degree)
+    c = 0.5 * n * dx
+    return Problem(grid, m, [beam_along_x(E0, spot, c + 0.011, c - 0.007)], o, name="small_3d")
