@@ -1,0 +1,194 @@
+/*
+ * dlra.h -- C ABI of the MI355X dynamical low-rank proton transport library.
+ *
+ * The library advances the collided proton flux of a pencil beam through a
+ * voxel phantom with the rank-adaptive augmented basis-update & Galerkin
+ * integrator (paper Sec. 2.2, eq. KLS), energy acting as pseudo-time
+ * (Sec. 3.3), and feeds it with the uncollided flux of a ray tracer
+ * (Sec. 3.2).  One context holds one beam.  All compute runs in HIP kernels
+ * on the stream given at initialisation.
+ *
+ * Conventions
+ *   - Cells are ordered x fastest: cell = (k*ny + j)*nx + i (Sec. 3.3.2).
+ *   - Units: cm, MeV, g/cm^3.  Deposited energy is MeV/cm^3 per source proton
+ *     (per cm of depth out of plane in 2D).
+ *   - Host arrays passed in are copied during the call; the caller may free
+ *     them afterwards.  Device memory: the caller owns the workspace passed to
+ *     dlra_init and every device output buffer; the library never allocates
+ *     device memory and keeps pointers into the workspace until dlra_destroy.
+ *   - Calls enqueue work on the context's stream and return without waiting,
+ *     unless stated otherwise.  Calls on one context must not overlap;
+ *     different contexts are independent.
+ *   - Every call returns DLRA_OK (0) or a negative error code; the message of
+ *     the last error on the calling thread is available from dlra_last_error.
+ *     Invalid arguments are rejected before anything is enqueued.
+ */
+#ifndef DLRA_H
+#define DLRA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DLRA_OK = 0,
+  DLRA_E_INVALID = -1,   /* bad argument, size or pointer; nothing enqueued */
+  DLRA_E_NOMEM = -2,     /* workspace smaller than dlra_workspace_size */
+  DLRA_E_HIP = -3,       /* a HIP runtime call failed */
+  DLRA_E_NUMERIC = -4,   /* non-finite value detected in the low-rank state */
+  DLRA_E_CFL = -5,       /* RK4 substeps needed exceed the configured maximum */
+  DLRA_E_RANK = -6,      /* rank outside [1, r_max] */
+  DLRA_E_STATE = -7      /* call out of order (e.g. step before raytrace) */
+};
+
+enum { DLRA_RANK_FIXED = 0, DLRA_RANK_ADAPTIVE = 1 };
+enum { DLRA_FP64 = 0, DLRA_MIXED = 1 };
+
+/* Structured grid (Sec. 3.3.2).  nz == 1 selects the 2D problem (streaming in
+ * x and y only).  Spacings in cm. */
+typedef struct {
+  int nx, ny, nz;
+  double dx, dy, dz;
+} dlra_grid;
+
+/* Mixture model (Sec. 2.1, eq. mixXS): per-voxel partial densities of n_mat
+ * base materials and per-material energy tables, interpolated linearly in E.
+ *   w   [n_mat][n_cells]     partial density of material i in the cell, g/cm^3
+ *   e   [n_e]                ascending table energies, MeV
+ *   S   [n_mat][n_e]         mass stopping power, MeV cm^2/g
+ *   T   [n_mat][n_e]         mass straggling coefficient, MeV^2 cm^2/g
+ *   dG  [n_mat][n_e][n_leg]  G_0 - G_l of the Legendre moments
+ *                            G_l = 2 pi int P_l(mu) Sigma_s dmu (Sec. 3.3.1),
+ *                            cm^2/g; n_leg >= pn_degree + 2, dG[..][..][0] = 0.
+ * The transport-corrected operator only uses differences of moments
+ * (Sec. 3.3.1, extended transport correction), hence this form. */
+typedef struct {
+  int n_mat;
+  int n_e;
+  int n_leg;
+  const double *w;
+  const double *e;
+  const double *S;
+  const double *T;
+  const double *dG;
+} dlra_materials;
+
+/* Pencil beam (Sec. 4): Gaussian energy spectrum N(E0, sigma_E) and Gaussian
+ * lateral profile of standard deviation spot_sigma around the axis through
+ * pos along the unit vector dir. */
+typedef struct {
+  double E0, sigma_E, spot_sigma, weight;
+  double pos[3];
+  double dir[3];
+} dlra_beam;
+
+/* Method options.
+ *   pn_degree     N of the real spherical-harmonics expansion, m = (N+1)^2
+ *   n_steps       uniform energy steps on [e_cut, E0 + e_max_sigmas*sigma_E]
+ *   rank_mode     DLRA_RANK_FIXED (rank r) or DLRA_RANK_ADAPTIVE
+ *                 (relative L1 singular-value tail <= trunc_tol, rank clamped
+ *                 to [r_min, r_max], initial rank r_min) (Sec. 2.2)
+ *   precision     DLRA_FP64, or DLRA_MIXED: FP32 storage, stencil and
+ *                 projections with FP32 accumulation; QR, SVD and the rank
+ *                 decisions in FP64
+ *   aug_tol       drop tolerance of basis augmentation, relative to ||K||_F
+ *   floor_tol     singular values <= floor_tol * sigma_1 keep no direction;
+ *                 their slots are filled from the previous basis
+ *   fill_tol      acceptance threshold of filler directions
+ *   nu_max        CFL number of the RK4 substep rule (0: 0.45 in 2D, 0.35 in 3D)
+ *   n_sub_max     upper bound on RK4 substeps per energy step (DLRA_E_CFL)
+ *   ray_h_max     maximal Crank-Nicolson step of the ray tracer, cm (Sec. 3.2)
+ *   n_groups      DG energy groups of the ray tracer (Sec. 3.2)
+ *   beam_cut_sigmas  rays are traced for cells within this many spot sigmas */
+typedef struct {
+  int pn_degree;
+  int n_steps;
+  int rank_mode;
+  int r, r_min, r_max;
+  int precision;
+  int n_groups;
+  int n_sub_max;
+  double e_cut;
+  double e_max_sigmas;
+  double trunc_tol;
+  double aug_tol;
+  double floor_tol;
+  double fill_tol;
+  double nu_max;
+  double ray_h_max;
+  double beam_cut_sigmas;
+} dlra_options;
+
+typedef struct dlra_ctx dlra_ctx;
+
+/* Bytes of device workspace dlra_init needs for this grid, material count
+ * and options. */
+int dlra_workspace_size(const dlra_grid *grid, int n_mat, const dlra_options *opt,
+                        size_t *bytes);
+
+/* Validates the problem, copies the tables to the device, builds the P_N
+ * streaming matrices A_d = int m m^T Omega_d and their eigen-split A_d^{+-}
+ * (Sec. 3.3.1-3.3.2), the per-step coefficients at E_{k+1/2}, the RK4
+ * substep counts and the initial low-rank state (S = 0).
+ *   workspace   device memory of at least dlra_workspace_size bytes, 256-byte
+ *               aligned, owned by the caller and kept until dlra_destroy
+ *   stream      hipStream_t to enqueue on (NULL: the null stream)
+ * On success *out receives the context.  Synchronises the stream once. */
+int dlra_init(const dlra_grid *grid, const dlra_materials *mat, const dlra_beam *beam,
+              const dlra_options *opt, void *workspace, size_t workspace_bytes,
+              void *stream, dlra_ctx **out);
+
+/* Ray tracer for the uncollided flux (Sec. 3.2): for every cell within
+ * beam_cut_sigmas of the beam axis marches a DG-in-energy / Crank-Nicolson
+ * ray from the domain entry to the cell centre and stores the step-averaged
+ * uncollided flux of every energy step and the uncollided deposited energy.
+ * Must precede the first dlra_step. */
+int uncollided_raytrace(dlra_ctx *ctx);
+
+/* One energy (pseudo-time) step k -> k+1 of the collided flux (Sec. 3.3.3):
+ * streaming by the augmented BUG integrator with RK4 substeps (eq. KLS),
+ * collided self-scattering (implicit Euler L-step), uncollided in-scattering
+ * (explicit Euler K, L, S steps), rank truncation, and accumulation of the
+ * collided deposited energy.
+ *   rank_out  nullable host pointer; if given, receives the rank after the
+ *             step, and the call synchronises the stream and reports
+ *             DLRA_E_NUMERIC / DLRA_E_RANK raised by the step's kernels. */
+int dlra_step(dlra_ctx *ctx, int *rank_out);
+
+/* Deposited energy into the caller's device buffer dose[n_cells] (FP64):
+ *   flags bit 0  add the uncollided part, bit 1  add the collided part,
+ *   bit 2  divide by the local density (dose per mass).  dose is overwritten. */
+int dose_deposit(dlra_ctx *ctx, double *dose, int flags);
+
+/* Test and checkpoint access (host buffers, FP64, synchronous).
+ *   dlra_get_state: U [n_cells][r] row-major, S [r][r], V [m][r]; *rank and
+ *                   *step receive the current rank and energy-step index;
+ *                   any of U, S, V may be NULL (then only sizes are returned).
+ *   dlra_set_state: replaces the state by (U, S, V) of rank r at step index
+ *                   step (0 <= step <= n_steps); the collided dose is kept. */
+int dlra_get_state(dlra_ctx *ctx, double *U, double *S, double *V, int *rank, int *step);
+int dlra_set_state(dlra_ctx *ctx, const double *U, const double *S, const double *V,
+                   int rank, int step);
+
+/* Uncollided tables after uncollided_raytrace, host FP64:
+ *   psibar [n_steps][n_cells] step-averaged uncollided flux, Du [n_cells]. */
+int dlra_get_uncollided(dlra_ctx *ctx, double *psibar, double *Du);
+
+/* Number of RK4 substeps of energy step k (host-side, from dlra_init). */
+int dlra_substeps(dlra_ctx *ctx, int k, int *n_sub);
+
+/* Waits for the context's stream. */
+int dlra_sync(dlra_ctx *ctx);
+
+/* Releases the context (not the caller's workspace). */
+void dlra_destroy(dlra_ctx *ctx);
+
+/* Message of the last failed call on the calling thread. */
+const char *dlra_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DLRA_H */

@@ -1,0 +1,241 @@
+"""ctypes binding of libdlra.so (argument marshalling only).
+
+Every computation runs in the HIP library; PyTorch provides the device
+workspace and the stream.  Importing this module does not need a GPU; creating
+a solver does, and fails loudly when the library or the GPU is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdlra.so")
+
+DLRA_OK = 0
+ERRORS = {-1: "DLRA_E_INVALID", -2: "DLRA_E_NOMEM", -3: "DLRA_E_HIP", -4: "DLRA_E_NUMERIC",
+          -5: "DLRA_E_CFL", -6: "DLRA_E_RANK", -7: "DLRA_E_STATE"}
+RANK_FIXED, RANK_ADAPTIVE = 0, 1
+FP64, MIXED = 0, 1
+DOSE_UNCOLLIDED, DOSE_COLLIDED, DOSE_PER_MASS = 1, 2, 4
+
+EXPORTS = ["dlra_workspace_size", "dlra_init", "uncollided_raytrace", "dlra_step",
+           "dose_deposit", "dlra_get_state", "dlra_set_state", "dlra_get_uncollided",
+           "dlra_substeps", "dlra_sync", "dlra_destroy", "dlra_last_error"]
+
+
+class DlraError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+
+
+class Materials(C.Structure):
+    _fields_ = [("n_mat", C.c_int), ("n_e", C.c_int), ("n_leg", C.c_int),
+                ("w", C.POINTER(C.c_double)), ("e", C.POINTER(C.c_double)),
+                ("S", C.POINTER(C.c_double)), ("T", C.POINTER(C.c_double)),
+                ("dG", C.POINTER(C.c_double))]
+
+
+class Beam(C.Structure):
+    _fields_ = [("E0", C.c_double), ("sigma_E", C.c_double), ("spot_sigma", C.c_double),
+                ("weight", C.c_double), ("pos", C.c_double * 3), ("dir", C.c_double * 3)]
+
+
+class Options(C.Structure):
+    _fields_ = [("pn_degree", C.c_int), ("n_steps", C.c_int), ("rank_mode", C.c_int),
+                ("r", C.c_int), ("r_min", C.c_int), ("r_max", C.c_int),
+                ("precision", C.c_int), ("n_groups", C.c_int), ("n_sub_max", C.c_int),
+                ("e_cut", C.c_double), ("e_max_sigmas", C.c_double),
+                ("trunc_tol", C.c_double), ("aug_tol", C.c_double),
+                ("floor_tol", C.c_double), ("fill_tol", C.c_double),
+                ("nu_max", C.c_double), ("ray_h_max", C.c_double),
+                ("beam_cut_sigmas", C.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdlra.so; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2508_04484_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    P, I, D, V = C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_void_p
+    lib.dlra_workspace_size.argtypes = [C.POINTER(Grid), I, C.POINTER(Options),
+                                        C.POINTER(C.c_size_t)]
+    lib.dlra_init.argtypes = [C.POINTER(Grid), C.POINTER(Materials), C.POINTER(Beam),
+                              C.POINTER(Options), V, C.c_size_t, V, C.POINTER(P)]
+    lib.uncollided_raytrace.argtypes = [P]
+    lib.dlra_step.argtypes = [P, C.POINTER(I)]
+    lib.dose_deposit.argtypes = [P, V, I]
+    lib.dlra_get_state.argtypes = [P, D, D, D, C.POINTER(I), C.POINTER(I)]
+    lib.dlra_set_state.argtypes = [P, D, D, D, I, I]
+    lib.dlra_get_uncollided.argtypes = [P, D, D]
+    lib.dlra_substeps.argtypes = [P, I, C.POINTER(I)]
+    lib.dlra_sync.argtypes = [P]
+    lib.dlra_destroy.argtypes = [P]
+    lib.dlra_destroy.restype = None
+    lib.dlra_last_error.restype = C.c_char_p
+    for name in EXPORTS[:-2]:
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def check(rc: int):
+    if rc != DLRA_OK:
+        raise DlraError(rc, load().dlra_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_grid(g) -> Grid:
+    return Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz)
+
+
+def make_options(o) -> Options:
+    return Options(o.pn_degree, o.n_steps,
+                   RANK_FIXED if o.rank_mode == "fixed" else RANK_ADAPTIVE,
+                   o.r, o.r_min, o.r_max, FP64 if o.precision == "fp64" else MIXED,
+                   o.n_groups, getattr(o, "n_sub_max", 0), o.e_cut, o.e_max_sigmas,
+                   o.trunc_tol, o.aug_tol, o.floor_tol, o.fill_tol, o.nu_max, o.ray_h_max,
+                   o.beam_cut_sigmas)
+
+
+def make_beam(b) -> Beam:
+    return Beam(b.E0, b.sigma_E, b.spot_sigma, b.weight, (C.c_double * 3)(*b.pos),
+                (C.c_double * 3)(*b.dir))
+
+
+def workspace_size(problem) -> int:
+    lib = load()
+    out = C.c_size_t(0)
+    check(lib.dlra_workspace_size(C.byref(make_grid(problem.grid)), problem.materials.n_mat,
+                                  C.byref(make_options(problem.options)), C.byref(out)))
+    return int(out.value)
+
+
+class BeamSolver:
+    """One pencil beam of a problem on the current CUDA (HIP) device.
+
+    Usage: s = BeamSolver(problem, b); s.raytrace(); s.run(); dose = s.dose()."""
+
+    def __init__(self, problem, beam_index: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("BeamSolver needs a GPU (torch.cuda.is_available() is False)")
+        self.lib = load()
+        self.problem = problem
+        self.beam = problem.beams[beam_index]
+        self.torch = torch
+        size = workspace_size(problem)
+        self._ws = torch.empty(size + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        mat = problem.materials
+        self._arrays = [np.ascontiguousarray(a, dtype=np.float64)
+                        for a in (mat.w, mat.e, mat.S, mat.T, mat.dG)]
+        w, e, S, T, dG = self._arrays
+        m = Materials(mat.n_mat, e.size, dG.shape[-1], _dptr(w), _dptr(e), _dptr(S), _dptr(T),
+                      _dptr(dG))
+        ctx = C.c_void_p(0)
+        check(self.lib.dlra_init(C.byref(make_grid(problem.grid)), C.byref(m),
+                                 C.byref(make_beam(self.beam)),
+                                 C.byref(make_options(problem.options)),
+                                 C.c_void_p(self._ws_ptr), C.c_size_t(size),
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
+        self.ctx = ctx
+        self.n = problem.grid.n
+        self.m = problem.m
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.dlra_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def raytrace(self):
+        check(self.lib.uncollided_raytrace(self.ctx))
+
+    def step(self, sync: bool = False):
+        if sync:
+            r = C.c_int(0)
+            check(self.lib.dlra_step(self.ctx, C.byref(r)))
+            return r.value
+        check(self.lib.dlra_step(self.ctx, None))
+        return None
+
+    def run(self, n_steps=None):
+        n_steps = self.problem.options.n_steps if n_steps is None else n_steps
+        for _ in range(n_steps):
+            self.step()
+        self.sync()
+
+    def sync(self):
+        check(self.lib.dlra_sync(self.ctx))
+
+    def dose(self, flags=DOSE_UNCOLLIDED | DOSE_COLLIDED):
+        out = self.torch.empty(self.n, dtype=self.torch.float64, device="cuda")
+        check(self.lib.dose_deposit(self.ctx, C.c_void_p(out.data_ptr()), flags))
+        self.sync()
+        return out
+
+    def substeps(self, k):
+        v = C.c_int(0)
+        check(self.lib.dlra_substeps(self.ctx, k, C.byref(v)))
+        return v.value
+
+    def state(self):
+        r, k = C.c_int(0), C.c_int(0)
+        check(self.lib.dlra_get_state(self.ctx, None, None, None, C.byref(r), C.byref(k)))
+        U = np.zeros((self.n, r.value))
+        S = np.zeros((r.value, r.value))
+        V = np.zeros((self.m, r.value))
+        check(self.lib.dlra_get_state(self.ctx, _dptr(U), _dptr(S), _dptr(V), C.byref(r),
+                                      C.byref(k)))
+        return U, S, V, k.value
+
+    def set_state(self, U, S, V, step):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        check(self.lib.dlra_set_state(self.ctx, _dptr(U), _dptr(S), _dptr(V), U.shape[1], step))
+
+    def uncollided(self):
+        ps = np.zeros((self.problem.options.n_steps, self.n))
+        Du = np.zeros(self.n)
+        check(self.lib.dlra_get_uncollided(self.ctx, _dptr(ps), _dptr(Du)))
+        return ps, Du
+
+
+def solve(problem, n_steps=None):
+    """Deposited energy of all beams (weighted sum), torch float64 on the GPU."""
+    total = None
+    for b in range(len(problem.beams)):
+        s = BeamSolver(problem, b)
+        s.raytrace()
+        s.run(n_steps)
+        d = s.dose() * problem.beams[b].weight
+        total = d if total is None else total + d
+        s.close()
+    return total

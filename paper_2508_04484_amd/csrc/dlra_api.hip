@@ -1,0 +1,940 @@
+// C ABI and host orchestration of one energy step (see include/dlra.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dlra.h"
+#include "kernels.hpp"
+#include "setup.hpp"
+
+using namespace dlra;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw HipError(std::string(#call) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxRank = 50;      // 2 r_max <= 100 columns in the small kernels
+constexpr int kPartialBlocks = 240;
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// ------------------------------------------------------------------ workspace plan
+struct Plan {
+  size_t bytes = 0;
+  size_t take(size_t b) {
+    size_t off = bytes;
+    bytes += align256(b);
+    return off;
+  }
+  // offsets
+  size_t w_t, w_d, s, tall[4], psibar, dose_c, dose_u, Apm, AV, stepS, stepA, stepG, minstop;
+  size_t S, V, Vn, Bm, Cm, Sh, Pp, Qp, Sp, G1, G2, Wg, T1, T2, Lm, L0, La, Lb, Mi, H, Cg, dc,
+      tmp, work, partial, ctl;
+  size_t rt_diag, rt_up, rt_lo, rt_mass, rt_c0, rt_g0, rt_sw, rt_stopw, rt_rows, rt_f,
+      rt_scratch;
+  size_t partial_elems = 0;
+};
+
+struct Dims {
+  int n, dim, ndk, N, m, n_mat, R, P, ld, n_steps, G, ng_step, max_rows;
+  size_t tsize;
+};
+
+bool make_dims(const dlra_grid *g, int n_mat, const dlra_options *o, Dims &d, std::string &err) {
+  if (!g || !o) {
+    err = "null grid or options";
+    return false;
+  }
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0)) {
+    err = "grid sizes and spacings must be positive";
+    return false;
+  }
+  if (n_mat < 1 || n_mat > kMaxMat) {
+    err = "n_mat must be in [1, 8]";
+    return false;
+  }
+  if (o->pn_degree < 0 || o->pn_degree > 40) {
+    err = "pn_degree must be in [0, 40]";
+    return false;
+  }
+  if (o->n_steps < 1) {
+    err = "n_steps must be >= 1";
+    return false;
+  }
+  if (o->precision != DLRA_FP64 && o->precision != DLRA_MIXED) {
+    err = "precision must be DLRA_FP64 or DLRA_MIXED";
+    return false;
+  }
+  if (o->rank_mode != DLRA_RANK_FIXED && o->rank_mode != DLRA_RANK_ADAPTIVE) {
+    err = "rank_mode must be DLRA_RANK_FIXED or DLRA_RANK_ADAPTIVE";
+    return false;
+  }
+  d.N = o->pn_degree;
+  d.m = (d.N + 1) * (d.N + 1);
+  d.R = o->rank_mode == DLRA_RANK_FIXED ? o->r : o->r_max;
+  int r0 = o->rank_mode == DLRA_RANK_FIXED ? o->r : o->r_min;
+  if (d.R < 1 || d.R > kMaxRank || r0 < 1 || r0 > d.R || d.R > d.m) {
+    err = "ranks must satisfy 1 <= r (r_min) <= r_max <= min(50, (N+1)^2)";
+    return false;
+  }
+  if (o->rank_mode == DLRA_RANK_ADAPTIVE && o->r_min > o->r_max) {
+    err = "r_min > r_max";
+    return false;
+  }
+  if (o->n_groups < 4 || o->n_groups > 4096) {
+    err = "n_groups must be in [4, 4096]";
+    return false;
+  }
+  long long n = (long long)g->nx * g->ny * g->nz;
+  if (n > (1LL << 30)) {
+    err = "too many cells";
+    return false;
+  }
+  d.n = int(n);
+  d.dim = g->nz == 1 ? 2 : 3;
+  d.ndk = 2 * d.dim;
+  d.n_mat = n_mat;
+  d.P = 2 * d.R;
+  d.ld = (d.n + 63) / 64 * 64;
+  d.n_steps = o->n_steps;
+  d.G = o->n_groups;
+  d.tsize = o->precision == DLRA_FP64 ? 8 : 4;
+  // step windows: a step spans at most dt/h_E + 2 groups; dt/h_E = G / n_steps
+  d.ng_step = std::min(d.G, d.G / d.n_steps + 3);
+  int mn = d.dim == 2 ? std::min(g->nx, g->ny) : std::min(g->nx, std::min(g->ny, g->nz));
+  d.max_rows = d.n / mn;
+  return true;
+}
+
+Plan make_plan(const Dims &d) {
+  Plan p;
+  const size_t T = d.tsize, n = d.n, ld = d.ld, P = d.P, R = d.R, m = d.m;
+  p.w_t = p.take(d.n_mat * n * T);
+  p.w_d = p.take(d.n_mat * n * 8);
+  p.s = p.take(n * T);
+  for (int i = 0; i < 4; ++i) p.tall[i] = p.take(ld * P * T);
+  p.psibar = p.take(size_t(d.n_steps) * n * T);
+  p.dose_c = p.take(n * 8);
+  p.dose_u = p.take(n * 8);
+  p.Apm = p.take(d.ndk * m * m * 8);
+  p.AV = p.take(d.ndk * m * P * 8);
+  p.stepS = p.take(size_t(d.n_steps) * d.n_mat * 8);
+  p.stepA = p.take(size_t(d.n_steps) * d.n_mat * (d.N + 1) * 8);
+  p.stepG = p.take(size_t(d.n_steps) * m * d.n_mat * 8);
+  p.minstop = p.take(size_t(d.n_steps) * 8);
+  p.S = p.take(R * R * 8);
+  p.V = p.take(m * P * 8);
+  p.Vn = p.take(m * P * 8);
+  p.Bm = p.take(d.ndk * P * P * 8);
+  p.Cm = p.take(d.ndk * P * P * 8);
+  p.Sh = p.take(P * P * 8);
+  p.Pp = p.take(P * R * 8);
+  p.Qp = p.take(P * R * 8);
+  p.Sp = p.take(R * R * 8);
+  p.G1 = p.take(P * P * 8);
+  p.G2 = p.take(P * P * 8);
+  p.Wg = p.take(P * P * 8);
+  p.T1 = p.take(P * P * 8);
+  p.T2 = p.take(P * P * 8);
+  p.Lm = p.take(m * P * 8);
+  p.L0 = p.take(m * P * 8);
+  p.La = p.take(m * P * 8);
+  p.Lb = p.take(m * P * 8);
+  p.Mi = p.take(d.n_mat * R * R * 8);
+  p.H = p.take(P * kMaxMat * 8);
+  p.Cg = p.take(P * kMaxMat * 8);
+  p.dc = p.take(P * 8);
+  p.tmp = p.take(P * 8);
+  p.work = p.take((4 * P * P + 3 * m * P + 4 * P + 64) * 8);
+  size_t ntile = (n + 31) / 32;
+  size_t nb = std::min<size_t>(kPartialBlocks, ntile);
+  p.partial_elems = (nb + 1) * std::max<size_t>(d.ndk * P * P, 64);
+  p.partial = p.take(p.partial_elems * 8);
+  p.ctl = p.take(sizeof(Ctl));
+  const size_t G = d.G;
+  p.rt_diag = p.take(d.n_mat * G * 9 * 8);
+  p.rt_up = p.take(d.n_mat * G * 9 * 8);
+  p.rt_lo = p.take(d.n_mat * G * 9 * 8);
+  p.rt_mass = p.take(3 * 8);
+  p.rt_c0 = p.take(3 * G * 8);
+  p.rt_g0 = p.take(size_t(d.n_steps) * 4);
+  p.rt_sw = p.take(size_t(d.n_steps) * d.ng_step * 3 * 8);
+  p.rt_stopw = p.take(d.n_mat * 3 * G * 8);
+  p.rt_rows = p.take(size_t(d.max_rows) * 4);
+  p.rt_f = p.take(size_t(d.max_rows) * 8);
+  p.rt_scratch = p.take(size_t(24) * G * d.max_rows * 8);
+  return p;
+}
+
+}  // namespace
+
+// ==================================================================== context
+struct dlra_ctx {
+  Dims d;
+  Plan plan;
+  dlra_grid grid;
+  dlra_options opt;
+  dlra_beam beam;
+  GridDev gdev;
+  hipStream_t st = nullptr;
+  char *base = nullptr;
+  // host-side state
+  int r = 0;
+  int step = 0;
+  bool traced = false;
+  double e_max = 0, dt = 0;
+  std::vector<int> n_sub;
+  std::vector<double> w_host;
+  TruncOpt topt;
+  // ray rows
+  RayParams rp{};
+  int n_rows = 0;
+  // rotating tall buffers: 0 = Uhat, 1 = K, 2 = Wa, 3 = Wb
+  void *tall[4];
+  double *V, *Vn;
+
+  template <typename T>
+  T *at(size_t off) {
+    return reinterpret_cast<T *>(base + off);
+  }
+  Ctl *ctl() { return at<Ctl>(plan.ctl); }
+};
+
+namespace {
+
+void upload(dlra_ctx *c, size_t off, const void *src, size_t bytes) {
+  HIPCHK(hipMemcpyAsync(c->base + off, src, bytes, hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+}
+
+template <typename T>
+void upload_cast(dlra_ctx *c, size_t off, const double *src, size_t count) {
+  std::vector<T> tmp(src, src + count);
+  HIPCHK(hipMemcpyAsync(c->base + off, tmp.data(), count * sizeof(T), hipMemcpyHostToDevice,
+                        c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+}
+
+// Ordered CGS2 with drop over the columns of cand (m x nc, col-major), then
+// unit vectors, until r orthonormal columns (initial angular basis).
+std::vector<double> initial_angular_basis(const std::vector<double> &g0, int m, int nc, int r,
+                                          double tol, double fill_tol) {
+  std::vector<double> Q;
+  double nrm = 0.0;
+  for (double v : g0) nrm += v * v;
+  nrm = std::sqrt(nrm);
+  int cnt = 0;
+  auto try_add = [&](std::vector<double> v, double thr) {
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<double> coef(cnt, 0.0);
+      for (int j = 0; j < cnt; ++j)
+        for (int t = 0; t < m; ++t) coef[j] += Q[size_t(j) * m + t] * v[t];
+      for (int t = 0; t < m; ++t)
+        for (int j = 0; j < cnt; ++j) v[t] -= Q[size_t(j) * m + t] * coef[j];
+    }
+    double nv = 0.0;
+    for (double x : v) nv += x * x;
+    nv = std::sqrt(nv);
+    if (nv > thr) {
+      for (double &x : v) x /= nv;
+      Q.insert(Q.end(), v.begin(), v.end());
+      ++cnt;
+    }
+  };
+  for (int c = 0; c < nc && cnt < r; ++c)
+    try_add(std::vector<double>(g0.begin() + size_t(c) * m, g0.begin() + size_t(c + 1) * m),
+            tol * nrm);
+  for (int c = 0; c < m && cnt < r; ++c) {
+    std::vector<double> e(m, 0.0);
+    e[c] = 1.0;
+    try_add(e, fill_tol);
+  }
+  if (cnt != r) throw std::runtime_error("initial angular basis: completion failed");
+  return Q;
+}
+
+template <typename T>
+int init_impl(dlra_ctx *c, const dlra_materials *mat) {
+  const Dims &d = c->d;
+  const Plan &p = c->plan;
+  const int n = d.n, m = d.m, N = d.N, nm = d.n_mat;
+  HIPCHK(hipMemsetAsync(c->base, 0, p.bytes, c->st));
+  // ---- angular algebra
+  std::vector<double> A[3];
+  streaming_matrices(N, A);
+  std::vector<double> Apm(size_t(d.ndk) * m * m);
+  for (int dd = 0; dd < d.dim; ++dd) {
+    std::vector<double> Ap, Am;
+    eigen_split(A[dd], m, Ap, Am);
+    // symmetric: row- and column-major coincide
+    std::copy(Ap.begin(), Ap.end(), Apm.begin() + size_t(2 * dd) * m * m);
+    std::copy(Am.begin(), Am.end(), Apm.begin() + size_t(2 * dd + 1) * m * m);
+  }
+  upload(c, p.Apm, Apm.data(), Apm.size() * 8);
+  std::vector<double> TM(m);
+  beam_moments(N, c->beam.dir, TM.data());
+  // ---- energy grid and per-step coefficients at E_{k+1/2}
+  c->e_max = c->beam.E0 + c->opt.e_max_sigmas * c->beam.sigma_E;
+  c->dt = (c->e_max - c->opt.e_cut) / d.n_steps;
+  std::vector<double> stepS(size_t(d.n_steps) * nm), stepA(size_t(d.n_steps) * nm * (N + 1)),
+      stepG(size_t(d.n_steps) * m * nm);
+  const int ne = mat->n_e, nl = mat->n_leg;
+  for (int k = 0; k < d.n_steps; ++k) {
+    const double E = c->e_max - (k + 0.5) * c->dt;
+    for (int i = 0; i < nm; ++i) {
+      stepS[size_t(k) * nm + i] = interp(mat->e, mat->S + size_t(i) * ne, ne, E);
+      std::vector<double> dg(N + 2), col(ne);
+      for (int l = 0; l < N + 2; ++l) {
+        for (int e = 0; e < ne; ++e) col[e] = mat->dG[(size_t(i) * ne + e) * nl + l];
+        dg[l] = interp(mat->e, col.data(), ne, E);
+      }
+      for (int l = 0; l <= N; ++l) stepA[(size_t(k) * nm + i) * (N + 1) + l] = -dg[l];
+      for (int l = 0; l <= N; ++l) {
+        double gt = dg[N + 1] - dg[l];
+        for (int kk = -l; kk <= l; ++kk) {
+          int pidx = l * l + l + kk;
+          stepG[(size_t(k) * nm + i) * m + pidx] = gt * TM[pidx];
+        }
+      }
+    }
+  }
+  upload(c, p.stepS, stepS.data(), stepS.size() * 8);
+  upload(c, p.stepA, stepA.data(), stepA.size() * 8);
+  upload(c, p.stepG, stepG.data(), stepG.size() * 8);
+  // ---- materials
+  upload(c, p.w_d, mat->w, size_t(nm) * n * 8);
+  if (sizeof(T) == 8) {
+    upload(c, p.w_t, mat->w, size_t(nm) * n * 8);
+  } else {
+    upload_cast<T>(c, p.w_t, mat->w, size_t(nm) * n);
+  }
+  // ---- RK4 substeps: minimum stopping power per step
+  launch_min_stop(n, c->at<double>(p.w_d), nm, c->at<double>(p.stepS), d.n_steps,
+                  c->at<double>(p.minstop), c->st);
+  std::vector<double> minstop(d.n_steps);
+  HIPCHK(hipMemcpyAsync(minstop.data(), c->base + p.minstop, d.n_steps * 8,
+                        hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  double nu = c->opt.nu_max > 0 ? c->opt.nu_max : (d.dim == 2 ? 0.45 : 0.35);
+  double hmin = d.dim == 2 ? std::min(c->grid.dx, c->grid.dy)
+                           : std::min(c->grid.dx, std::min(c->grid.dy, c->grid.dz));
+  c->n_sub.resize(d.n_steps);
+  for (int k = 0; k < d.n_steps; ++k) {
+    if (!(minstop[k] > 0)) return fail(DLRA_E_INVALID, "stopping power must be positive in every cell");
+    int ns = std::max(1, int(std::ceil(c->dt / (nu * minstop[k] * hmin) - 1e-9)));
+    if (c->opt.n_sub_max > 0 && ns > c->opt.n_sub_max)
+      return fail(DLRA_E_CFL, "energy step " + std::to_string(k) + " needs " +
+                                  std::to_string(ns) + " RK4 substeps > n_sub_max");
+    c->n_sub[k] = ns;
+  }
+  // ---- initial state: S = 0, U unit vectors at floor((j+1/2) n / r), V from g_0
+  const int r0 = c->opt.rank_mode == DLRA_RANK_FIXED ? c->opt.r : c->opt.r_min;
+  c->r = r0;
+  {
+    T one = T(1);
+    for (int j = 0; j < r0; ++j) {
+      size_t cell = size_t((j + 0.5) * double(n) / r0);
+      HIPCHK(hipMemcpyAsync(c->at<T>(p.tall[0]) + size_t(j) * d.ld + cell, &one, sizeof(T),
+                            hipMemcpyHostToDevice, c->st));
+      HIPCHK(hipStreamSynchronize(c->st));
+    }
+    std::vector<double> g0(stepG.begin(), stepG.begin() + size_t(m) * nm);
+    std::vector<double> V0 = initial_angular_basis(g0, m, nm, r0, c->opt.aug_tol, c->opt.fill_tol);
+    upload(c, p.V, V0.data(), V0.size() * 8);
+  }
+  // ---- ray tracer tables
+  {
+    const int G = d.G;
+    std::vector<double> diag(size_t(nm) * G * 9), up(size_t(nm) * G * 9), lo(size_t(nm) * G * 9);
+    std::vector<double> stopw(size_t(nm) * 3 * G);
+    EnergyOperator op;
+    for (int i = 0; i < nm; ++i) {
+      std::vector<double> sig(ne), Si(mat->S + size_t(i) * ne, mat->S + size_t(i + 1) * ne),
+          Ti(mat->T + size_t(i) * ne, mat->T + size_t(i + 1) * ne);
+      for (int e = 0; e < ne; ++e) sig[e] = mat->dG[(size_t(i) * ne + e) * nl + N + 1];
+      energy_operator(c->opt.e_cut, c->e_max, G, mat->e, ne, Si.data(), Ti.data(), sig.data(), op);
+      std::copy(op.diag.begin(), op.diag.end(), diag.begin() + size_t(i) * G * 9);
+      std::copy(op.up.begin(), op.up.end(), up.begin() + size_t(i) * G * 9);
+      std::copy(op.lo.begin(), op.lo.end(), lo.begin() + size_t(i) * G * 9);
+      weighted_integral(op, mat->e, Si.data(), ne, stopw.data() + size_t(i) * 3 * G);
+    }
+    upload(c, p.rt_diag, diag.data(), diag.size() * 8);
+    upload(c, p.rt_up, up.data(), up.size() * 8);
+    upload(c, p.rt_lo, lo.data(), lo.size() * 8);
+    upload(c, p.rt_stopw, stopw.data(), stopw.size() * 8);
+    double mass[3] = {op.h, op.h / 3.0, op.h / 5.0};
+    upload(c, p.rt_mass, mass, sizeof(mass));
+    std::vector<double> c0(3 * G);
+    project_gaussian(op, c->beam.E0, c->beam.sigma_E, c0.data());
+    upload(c, p.rt_c0, c0.data(), c0.size() * 8);
+    std::vector<int> g0s(d.n_steps);
+    std::vector<double> sw(size_t(d.n_steps) * d.ng_step * 3);
+    for (int k = 0; k < d.n_steps; ++k) {
+      double hi = c->e_max - k * c->dt, lo_ = c->e_max - (k + 1) * c->dt;
+      g0s[k] = step_integral(op, lo_, hi, d.ng_step, sw.data() + size_t(k) * d.ng_step * 3);
+      for (int t = 0; t < d.ng_step * 3; ++t) sw[size_t(k) * d.ng_step * 3 + t] /= c->dt;
+    }
+    upload(c, p.rt_g0, g0s.data(), g0s.size() * 4);
+    upload(c, p.rt_sw, sw.data(), sw.size() * 8);
+    // rows along the beam axis
+    const double *dir = c->beam.dir;
+    int axis = -1, nnz = 0;
+    for (int a = 0; a < 3; ++a)
+      if (dir[a] != 0.0) {
+        axis = a;
+        ++nnz;
+      }
+    if (nnz != 1)
+      return fail(DLRA_E_INVALID, "the ray tracer supports beams along a grid axis");
+    if (d.dim == 2 && axis == 2) return fail(DLRA_E_INVALID, "2D problems need in-plane beams");
+    const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
+    const double D[3] = {c->grid.dx, c->grid.dy, c->grid.dz};
+    const int len = axis == 0 ? nx : (axis == 1 ? ny : nz);
+    const int stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
+    std::vector<int> starts;
+    std::vector<double> fs;
+    const double sgm = c->beam.spot_sigma, cut = c->opt.beam_cut_sigmas * sgm;
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          int ijk[3] = {i, j, k};
+          if (ijk[axis] != 0) continue;
+          double xc[3] = {(i + 0.5) * D[0], (j + 0.5) * D[1], d.dim == 3 ? (k + 0.5) * D[2] : 0.0};
+          double rel[3], dot = 0.0, nrm2 = 0.0;
+          for (int a = 0; a < 3; ++a) rel[a] = xc[a] - c->beam.pos[a];
+          double dn = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+          for (int a = 0; a < 3; ++a) dot += rel[a] * dir[a] / dn;
+          for (int a = 0; a < 3; ++a) {
+            double v = rel[a] - dot * dir[a] / dn;
+            nrm2 += v * v;
+          }
+          double dp = std::sqrt(nrm2);
+          if (dp > cut) continue;
+          double f = d.dim == 2 ? std::exp(-0.5 * dp * dp / (sgm * sgm)) / (std::sqrt(2.0 * kPi) * sgm)
+                                : std::exp(-0.5 * dp * dp / (sgm * sgm)) / (2.0 * kPi * sgm * sgm);
+          starts.push_back((k * ny + j) * nx + i);
+          fs.push_back(f);
+        }
+    c->n_rows = int(starts.size());
+    if (c->n_rows > d.max_rows) return fail(DLRA_E_INVALID, "ray rows exceed the plan");
+    if (c->n_rows) {
+      upload(c, p.rt_rows, starts.data(), starts.size() * 4);
+      upload(c, p.rt_f, fs.data(), fs.size() * 8);
+    }
+    RayParams &rp = c->rp;
+    rp.G = G;
+    rp.n_mat = nm;
+    rp.n_steps = d.n_steps;
+    rp.ng_step = d.ng_step;
+    rp.axis = axis;
+    rp.sign = dir[axis] > 0 ? 1 : -1;
+    rp.n_rows = c->n_rows;
+    rp.row_len = len;
+    rp.row_stride = stride;
+    rp.n = n;
+    rp.half = 0.5 * D[axis];
+    rp.n_half = std::max(1, int(std::ceil(rp.half / c->opt.ray_h_max - 1e-9)));
+  }
+  HIPCHK(hipStreamSynchronize(c->st));
+  return DLRA_OK;
+}
+
+// ------------------------------------------------------------------ one energy step
+template <typename T>
+struct Stepper {
+  dlra_ctx *c;
+  using Acc = T;   // projections accumulate in the storage precision
+  const Dims &d() const { return c->d; }
+  T *tall(int i) { return reinterpret_cast<T *>(c->tall[i]); }
+  double *D(size_t off) { return c->at<double>(off); }
+
+  // Uhat[:, r:2r] <- orth_tau((I - U U^T) K), count -> ctl->kU.  K (tall 1) is consumed.
+  void augment_u(int r, T *K) {
+    const Plan &p = c->plan;
+    const int n = d().n, ld = d().ld, P = d().P;
+    T *U = tall(0);
+    T *R = U + size_t(r) * ld;
+    Ctl *ctl = c->ctl();
+    hipStream_t st = c->st;
+    launch_sumsq<T>(n, K, ld, r, &ctl->normsq, D(p.partial), p.partial_elems, st);
+    launch_gram<T, double>(n, U, ld, r, K, ld, r, nullptr, nullptr, D(p.G1), P, D(p.partial),
+                           p.partial_elems, st);
+    launch_update<T>(n, U, ld, r, D(p.G1), P, -1.0, K, ld, 1.0, R, ld, r, nullptr, nullptr, 0,
+                     st);
+    launch_gram<T, double>(n, U, ld, r, R, ld, r, nullptr, nullptr, D(p.G2), P, D(p.partial),
+                           p.partial_elems, st);
+    launch_update<T>(n, U, ld, r, D(p.G2), P, -1.0, R, ld, 1.0, R, ld, r, nullptr, nullptr, 0,
+                     st);
+    launch_gram<T, double>(n, R, ld, r, R, ld, r, nullptr, nullptr, D(p.Wg), r, D(p.partial),
+                           p.partial_elems, st);
+    const double tol = c->opt.aug_tol;
+    launch_gram_orth(r, D(p.Wg), D(p.T1), P, tol * tol, &ctl->normsq, &ctl->kU, nullptr,
+                     D(p.work), st);
+    launch_update<T>(n, R, ld, r, D(p.T1), P, 1.0, nullptr, 0, 0.0, K, ld, r, nullptr, nullptr,
+                     0, st);
+    launch_gram<T, double>(n, K, ld, r, K, ld, r, nullptr, nullptr, D(p.Wg), r, D(p.partial),
+                           p.partial_elems, st);
+    launch_gram_orth(r, D(p.Wg), D(p.T2), P, 0.0, nullptr, nullptr, &ctl->kU, D(p.work), st);
+    launch_update<T>(n, K, ld, r, D(p.T2), P, 1.0, nullptr, 0, 0.0, R, ld, r, nullptr, nullptr,
+                     0, st);
+  }
+
+  // Galerkin angular couplings B_dk = V^T A_dk V over q columns (ld P blocks)
+  void angular(int q, double *V) {
+    const Plan &p = c->plan;
+    const int m = d().m, P = d().P;
+    launch_small_gemm(0, 0, m, q, m, 1.0, D(p.Apm), m, size_t(m) * m, V, m, 0, 0.0, D(p.AV), m,
+                      size_t(m) * P, d().ndk, c->st);
+    launch_small_gemm(1, 0, q, q, m, 1.0, V, m, 0, D(p.AV), m, size_t(m) * P, 0.0, D(p.Bm), P,
+                      size_t(P) * P, d().ndk, c->st);
+  }
+
+  // truncate Sh, rotate Uhat (+ dose) and Vhat; returns the new rank
+  int truncate_rotate(int r, bool with_dose, const int *kU, const int *kV) {
+    const Plan &p = c->plan;
+    const int n = d().n, ld = d().ld, P = d().P, m = d().m, R = d().R;
+    Ctl *ctl = c->ctl();
+    hipStream_t st = c->st;
+    launch_truncate(D(p.Sh), P, kU, kV, r, c->topt, D(p.Pp), D(p.Qp), D(p.Sp), R, ctl, D(p.work),
+                    st);
+    int r1 = r;
+    if (c->opt.rank_mode == DLRA_RANK_ADAPTIVE) {
+      Ctl h;
+      HIPCHK(hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      r1 = h.r_new;
+    } else {
+      r1 = c->opt.r;
+    }
+    double *dcv = nullptr;
+    double dscale = 0.0;
+    if (with_dose) {
+      // dc = S' (Vhat Q')[0, :]^T
+      launch_small_gemm(1, 1, r1, 1, 2 * r, 1.0, D(p.Qp), P, 0, c->V, m, 0, 0.0, D(p.tmp), P, 0,
+                        1, st);
+      launch_small_gemm(0, 0, r1, 1, r1, 1.0, D(p.Sp), R, 0, D(p.tmp), P, 0, 0.0, D(p.dc), P, 0,
+                        1, st);
+      dcv = D(p.dc);
+      dscale = c->dt * std::sqrt(4.0 * kPi);
+    }
+    launch_update<T>(n, tall(0), ld, 2 * r, D(p.Pp), P, 1.0, nullptr, 0, 0.0, tall(2), ld, r1,
+                     with_dose ? D(p.dose_c) : nullptr, dcv, dscale, st);
+    std::swap(c->tall[0], c->tall[2]);
+    launch_small_gemm(0, 0, m, r1, 2 * r, 1.0, c->V, m, 0, D(p.Qp), P, 0, 0.0, c->Vn, m, 0, 1,
+                      st);
+    std::swap(c->V, c->Vn);
+    launch_copy_block(r1, r1, D(p.Sp), R, D(p.S), R, R, R, 1.0, st);
+    return r1;
+  }
+
+  void run() {
+    const Plan &p = c->plan;
+    const Dims &dd = d();
+    const int n = dd.n, ld = dd.ld, P = dd.P, m = dd.m, R = dd.R, N = dd.N, nm = dd.n_mat;
+    const int k = c->step;
+    const int ns = c->n_sub[k];
+    const double dt = c->dt, h = dt / ns;
+    hipStream_t st = c->st;
+    Ctl *ctl = c->ctl();
+    int r = c->r;
+    T *s = c->at<T>(p.s);
+    // coefficients
+    launch_inverse_stop<T>(c->gdev, c->at<T>(p.w_t), nm, D(p.stepS) + size_t(k) * nm, s, ctl, st);
+    // ---------------- streaming (augmented BUG, RK4)
+    angular(r, c->V);
+    launch_stencil_projection<T, Acc>(c->gdev, s, tall(0), ld, r, D(p.Cm), P, D(p.partial),
+                                      p.partial_elems, st);
+    // K-step: K0 = U S, Horner RK4
+    launch_update<T>(n, tall(0), ld, r, D(p.S), R, 1.0, nullptr, 0, 0.0, tall(1), ld, r, nullptr,
+                     nullptr, 0, st);
+    const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
+    for (int sub = 0; sub < ns; ++sub) {
+      T *K0 = tall(1);
+      T *in = K0;
+      T *outs[2] = {tall(2), tall(3)};
+      for (int stg = 0; stg < 4; ++stg) {
+        T *out = outs[stg & 1];
+        launch_kstep_stage<T>(c->gdev, s, in, K0, out, ld, r, D(p.Bm), P, cf[stg] * h, st);
+        in = out;
+      }
+      std::swap(c->tall[1], c->tall[3]);
+    }
+    // L-step: L0 = V S^T, Horner RK4 (m x r)
+    double *Lk = D(p.L0), *La = D(p.La), *Lb = D(p.Lb);
+    launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, Lk, m, 0, 1, st);
+    for (int sub = 0; sub < ns; ++sub) {
+      double *in = Lk;
+      double *outs[2] = {La, Lb};
+      for (int stg = 0; stg < 4; ++stg) {
+        double *out = outs[stg & 1];
+        launch_lstep_stage(m, r, dd.ndk, D(p.Apm), D(p.Cm), P, in, Lk, out, cf[stg] * h, st);
+        in = out;
+      }
+      std::swap(Lk, Lb);
+    }
+    // augmentation
+    augment_u(r, tall(1));
+    launch_vaug(m, r, c->V, m, Lk, c->opt.aug_tol, &ctl->kV, D(p.work), st);
+    // S-step on the augmented bases
+    launch_stencil_projection<T, Acc>(c->gdev, s, tall(0), ld, 2 * r, D(p.Cm), P, D(p.partial),
+                                      p.partial_elems, st);
+    angular(2 * r, c->V);
+    launch_copy_block(r, r, D(p.S), R, D(p.Sh), P, P, P, 1.0, st);
+    launch_sstep(2 * r, P, dd.ndk, D(p.Cm), D(p.Bm), D(p.Sh), D(p.work), h, ns, st);
+    r = truncate_rotate(r, false, &ctl->kU, &ctl->kV);
+    // ---------------- collided self-scattering (L-step, implicit Euler)
+    for (int i = 0; i < nm; ++i)
+      launch_gram<T, Acc>(n, tall(0), ld, r, tall(0), ld, r, c->at<T>(p.w_t) + size_t(i) * n, s,
+                          D(p.Mi) + size_t(i) * r * r, r, D(p.partial), p.partial_elems, st);
+    launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, D(p.L0), m, 0, 1, st);
+    launch_collided_solve(N, m, r, nm, D(p.Mi), D(p.stepA) + size_t(k) * nm * (N + 1), dt,
+                          D(p.L0), D(p.La), st);
+    launch_qr_complete(m, r, D(p.La), c->V, c->opt.aug_tol, c->opt.fill_tol, c->Vn, D(p.S), R,
+                       ctl, D(p.work), st);
+    std::swap(c->V, c->Vn);
+    // ---------------- uncollided in-scattering source (explicit Euler K, L, S)
+    const T *psi = c->at<T>(p.psibar) + size_t(k) * n;
+    const double *gk = D(p.stepG) + size_t(k) * m * nm;
+    launch_xt_source<T, Acc>(n, tall(0), ld, r, c->at<T>(p.w_t), nm, psi, D(p.H), P,
+                             D(p.partial), p.partial_elems, st);
+    launch_small_gemm(1, 0, r, nm, m, 1.0, c->V, m, 0, gk, m, 0, 0.0, D(p.Cg), P, 0, 1, st);
+    launch_source_k<T>(n, tall(0), ld, r, D(p.S), R, c->at<T>(p.w_t), nm, psi, D(p.Cg), P, dt,
+                       tall(1), st);
+    launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, D(p.Lm), m, 0, 1, st);
+    launch_small_gemm(0, 1, m, r, nm, dt, gk, m, 0, D(p.H), P, 0, 1.0, D(p.Lm), m, 0, 1, st);
+    augment_u(r, tall(1));
+    launch_vaug(m, r, c->V, m, D(p.Lm), c->opt.aug_tol, &ctl->kV, D(p.work), st);
+    launch_xt_source<T, Acc>(n, tall(0), ld, 2 * r, c->at<T>(p.w_t), nm, psi, D(p.H), P,
+                             D(p.partial), p.partial_elems, st);
+    launch_small_gemm(1, 0, 2 * r, nm, m, 1.0, c->V, m, 0, gk, m, 0, 0.0, D(p.Cg), P, 0, 1, st);
+    launch_copy_block(r, r, D(p.S), R, D(p.Sh), P, P, P, 1.0, st);
+    launch_small_gemm(0, 1, 2 * r, 2 * r, nm, dt, D(p.H), P, 0, D(p.Cg), P, 0, 1.0, D(p.Sh), P,
+                      0, 1, st);
+    r = truncate_rotate(r, true, &ctl->kU, &ctl->kV);
+    launch_check_finite(D(p.S), R * R, ctl, st);
+    c->r = r;
+    c->step = k + 1;
+    (void)N;
+  }
+};
+
+int sync_flags(dlra_ctx *c) {
+  Ctl h;
+  HIPCHK(hipMemcpyAsync(&h, c->ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (h.flags & kFlagNonFinite) return fail(DLRA_E_NUMERIC, "non-finite value in the low-rank state");
+  if (h.flags & kFlagStop) return fail(DLRA_E_NUMERIC, "non-positive stopping power");
+  if (h.flags & kFlagCompletion) return fail(DLRA_E_RANK, "basis completion failed");
+  return DLRA_OK;
+}
+
+__global__ void k_dose_out(int n, int n_mat, const double *__restrict__ Du,
+                           const double *__restrict__ Dc, const double *__restrict__ w, int flags,
+                           double *__restrict__ out) {
+  int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= n) return;
+  double v = 0.0;
+  if (flags & 1) v += Du[x];
+  if (flags & 2) v += Dc[x];
+  if (flags & 4) {
+    double rho = 0.0;
+    for (int i = 0; i < n_mat; ++i) rho += w[size_t(i) * n + x];
+    v = rho > 0.0 ? v / rho : 0.0;
+  }
+  out[x] = v;
+}
+
+template <typename T>
+int get_state_impl(dlra_ctx *c, double *U, double *S, double *V) {
+  const Dims &d = c->d;
+  const int r = c->r;
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (U) {
+    std::vector<T> col(d.n);
+    for (int j = 0; j < r; ++j) {
+      HIPCHK(hipMemcpy(col.data(), reinterpret_cast<T *>(c->tall[0]) + size_t(j) * d.ld,
+                       d.n * sizeof(T), hipMemcpyDeviceToHost));
+      for (int x = 0; x < d.n; ++x) U[size_t(x) * r + j] = double(col[x]);
+    }
+  }
+  if (S) {
+    std::vector<double> h(size_t(d.R) * d.R);
+    HIPCHK(hipMemcpy(h.data(), c->base + c->plan.S, h.size() * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) S[i * r + j] = h[i + size_t(j) * d.R];
+  }
+  if (V) {
+    std::vector<double> h(size_t(d.m) * r);
+    HIPCHK(hipMemcpy(h.data(), c->V, h.size() * 8, hipMemcpyDeviceToHost));
+    for (int p = 0; p < d.m; ++p)
+      for (int j = 0; j < r; ++j) V[size_t(p) * r + j] = h[p + size_t(j) * d.m];
+  }
+  return DLRA_OK;
+}
+
+template <typename T>
+int set_state_impl(dlra_ctx *c, const double *U, const double *S, const double *V, int r) {
+  const Dims &d = c->d;
+  HIPCHK(hipStreamSynchronize(c->st));
+  HIPCHK(hipMemset(c->tall[0], 0, size_t(d.ld) * d.P * sizeof(T)));
+  std::vector<T> col(d.n);
+  for (int j = 0; j < r; ++j) {
+    for (int x = 0; x < d.n; ++x) col[x] = T(U[size_t(x) * r + j]);
+    HIPCHK(hipMemcpy(reinterpret_cast<T *>(c->tall[0]) + size_t(j) * d.ld, col.data(),
+                     d.n * sizeof(T), hipMemcpyHostToDevice));
+  }
+  std::vector<double> hs(size_t(d.R) * d.R, 0.0);
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) hs[i + size_t(j) * d.R] = S[i * r + j];
+  HIPCHK(hipMemcpy(c->base + c->plan.S, hs.data(), hs.size() * 8, hipMemcpyHostToDevice));
+  std::vector<double> hv(size_t(d.m) * d.P, 0.0);
+  for (int p = 0; p < d.m; ++p)
+    for (int j = 0; j < r; ++j) hv[p + size_t(j) * d.m] = V[size_t(p) * r + j];
+  HIPCHK(hipMemcpy(c->V, hv.data(), hv.size() * 8, hipMemcpyHostToDevice));
+  c->r = r;
+  return DLRA_OK;
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+extern "C" {
+
+int dlra_workspace_size(const dlra_grid *grid, int n_mat, const dlra_options *opt,
+                        size_t *bytes) {
+  Dims d;
+  std::string err;
+  if (!bytes) return fail(DLRA_E_INVALID, "bytes is NULL");
+  if (!make_dims(grid, n_mat, opt, d, err)) return fail(DLRA_E_INVALID, err);
+  *bytes = make_plan(d).bytes;
+  return DLRA_OK;
+}
+
+int dlra_init(const dlra_grid *grid, const dlra_materials *mat, const dlra_beam *beam,
+              const dlra_options *opt, void *workspace, size_t workspace_bytes, void *stream,
+              dlra_ctx **out) {
+  if (!out) return fail(DLRA_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!mat || !beam || !workspace) return fail(DLRA_E_INVALID, "null materials, beam or workspace");
+  Dims d;
+  std::string err;
+  if (!make_dims(grid, mat->n_mat, opt, d, err)) return fail(DLRA_E_INVALID, err);
+  if (!mat->w || !mat->e || !mat->S || !mat->T || !mat->dG || mat->n_e < 2)
+    return fail(DLRA_E_INVALID, "material tables missing");
+  if (mat->n_leg < d.N + 2) return fail(DLRA_E_INVALID, "n_leg must be >= pn_degree + 2");
+  for (int e = 1; e < mat->n_e; ++e)
+    if (!(mat->e[e] > mat->e[e - 1])) return fail(DLRA_E_INVALID, "table energies must ascend");
+  for (size_t t = 0; t < size_t(mat->n_mat) * d.n; ++t)
+    if (!(mat->w[t] >= 0.0) || !std::isfinite(mat->w[t]))
+      return fail(DLRA_E_INVALID, "partial densities must be finite and >= 0");
+  double dn = std::sqrt(beam->dir[0] * beam->dir[0] + beam->dir[1] * beam->dir[1] +
+                        beam->dir[2] * beam->dir[2]);
+  if (!(std::fabs(dn - 1.0) < 1e-9)) return fail(DLRA_E_INVALID, "beam direction must be a unit vector");
+  if (!(beam->sigma_E > 0) || !(beam->spot_sigma > 0) || !(opt->e_cut > 0) ||
+      !(beam->E0 > opt->e_cut))
+    return fail(DLRA_E_INVALID, "need sigma_E > 0, spot_sigma > 0 and E0 > e_cut > 0");
+  if (!(opt->aug_tol > 0) || !(opt->fill_tol > 0) || !(opt->fill_tol < 0.1) || !(opt->floor_tol >= 0) ||
+      !(opt->ray_h_max > 0) || !(opt->beam_cut_sigmas > 0) || !(opt->e_max_sigmas > 0))
+    return fail(DLRA_E_INVALID, "tolerances out of range");
+  if (opt->rank_mode == DLRA_RANK_ADAPTIVE && !(opt->trunc_tol > 0))
+    return fail(DLRA_E_INVALID, "trunc_tol must be > 0 in adaptive mode");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(DLRA_E_INVALID, "workspace must be 256-byte aligned");
+  Plan plan = make_plan(d);
+  if (workspace_bytes < plan.bytes)
+    return fail(DLRA_E_NOMEM, "workspace too small: need " + std::to_string(plan.bytes) + " bytes");
+  dlra_ctx *c = new dlra_ctx();
+  c->d = d;
+  c->plan = plan;
+  c->grid = *grid;
+  c->opt = *opt;
+  c->beam = *beam;
+  c->st = reinterpret_cast<hipStream_t>(stream);
+  c->base = reinterpret_cast<char *>(workspace);
+  c->gdev.nx = grid->nx;
+  c->gdev.ny = grid->ny;
+  c->gdev.nz = grid->nz;
+  c->gdev.n = d.n;
+  c->gdev.dim = d.dim;
+  c->gdev.inv2h[0] = 1.0 / (2.0 * grid->dx);
+  c->gdev.inv2h[1] = 1.0 / (2.0 * grid->dy);
+  c->gdev.inv2h[2] = 1.0 / (2.0 * grid->dz);
+  c->topt.fixed = opt->rank_mode == DLRA_RANK_FIXED;
+  c->topt.r_fixed = opt->r;
+  c->topt.r_min = opt->r_min;
+  c->topt.r_max = opt->r_max;
+  c->topt.trunc_tol = opt->trunc_tol;
+  c->topt.floor_tol = opt->floor_tol;
+  c->topt.fill_tol = opt->fill_tol;
+  for (int i = 0; i < 4; ++i) c->tall[i] = c->base + plan.tall[i];
+  c->V = c->at<double>(plan.V);
+  c->Vn = c->at<double>(plan.Vn);
+  int rc;
+  try {
+    rc = d.tsize == 8 ? init_impl<double>(c, mat) : init_impl<float>(c, mat);
+  } catch (const std::exception &e) {
+    rc = fail(DLRA_E_HIP, e.what());
+  }
+  if (rc != DLRA_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return DLRA_OK;
+}
+
+int uncollided_raytrace(dlra_ctx *c) {
+  if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
+  try {
+    const Plan &p = c->plan;
+    const Dims &d = c->d;
+    HIPCHK(hipMemsetAsync(c->base + p.psibar, 0, size_t(d.n_steps) * d.n * d.tsize, c->st));
+    HIPCHK(hipMemsetAsync(c->base + p.dose_u, 0, size_t(d.n) * 8, c->st));
+    auto go = [&](auto *psib) {
+      using T = std::remove_pointer_t<decltype(psib)>;
+      launch_raytrace_rows<T>(c->rp, c->at<int>(p.rt_rows), c->at<double>(p.rt_f),
+                              c->at<double>(p.w_d), c->at<double>(p.rt_diag),
+                              c->at<double>(p.rt_up), c->at<double>(p.rt_lo),
+                              c->at<double>(p.rt_mass), c->at<double>(p.rt_c0),
+                              c->at<int>(p.rt_g0), c->at<double>(p.rt_sw),
+                              c->at<double>(p.rt_stopw), c->at<double>(p.rt_scratch), psib,
+                              c->at<double>(p.dose_u), c->st);
+    };
+    if (d.tsize == 8) go(c->at<double>(p.psibar));
+    else go(c->at<float>(p.psibar));
+    HIPCHK(hipGetLastError());
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  c->traced = true;
+  return DLRA_OK;
+}
+
+int dlra_step(dlra_ctx *c, int *rank_out) {
+  if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
+  if (!c->traced) return fail(DLRA_E_STATE, "uncollided_raytrace must precede dlra_step");
+  if (c->step >= c->d.n_steps) return fail(DLRA_E_STATE, "all energy steps done");
+  try {
+    if (c->d.tsize == 8) Stepper<double>{c}.run();
+    else Stepper<float>{c}.run();
+    HIPCHK(hipGetLastError());
+    if (rank_out) {
+      int rc = sync_flags(c);
+      if (rc != DLRA_OK) return rc;
+      *rank_out = c->r;
+    }
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  return DLRA_OK;
+}
+
+int dose_deposit(dlra_ctx *c, double *dose, int flags) {
+  if (!c || !dose) return fail(DLRA_E_INVALID, "null ctx or dose");
+  if (flags & ~7) return fail(DLRA_E_INVALID, "unknown flag bits");
+  try {
+    const Plan &p = c->plan;
+    k_dose_out<<<(c->d.n + 255) / 256, 256, 0, c->st>>>(c->d.n, c->d.n_mat,
+                                                        c->at<double>(p.dose_u),
+                                                        c->at<double>(p.dose_c),
+                                                        c->at<double>(p.w_d), flags, dose);
+    HIPCHK(hipGetLastError());
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  return DLRA_OK;
+}
+
+int dlra_get_state(dlra_ctx *c, double *U, double *S, double *V, int *rank, int *step) {
+  if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
+  if (rank) *rank = c->r;
+  if (step) *step = c->step;
+  try {
+    return c->d.tsize == 8 ? get_state_impl<double>(c, U, S, V) : get_state_impl<float>(c, U, S, V);
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+}
+
+int dlra_set_state(dlra_ctx *c, const double *U, const double *S, const double *V, int rank,
+                   int step) {
+  if (!c || !U || !S || !V) return fail(DLRA_E_INVALID, "null argument");
+  if (rank < 1 || rank > c->d.R) return fail(DLRA_E_INVALID, "rank outside [1, r_max]");
+  if (step < 0 || step > c->d.n_steps) return fail(DLRA_E_INVALID, "step outside [0, n_steps]");
+  try {
+    int rc = c->d.tsize == 8 ? set_state_impl<double>(c, U, S, V, rank)
+                             : set_state_impl<float>(c, U, S, V, rank);
+    if (rc == DLRA_OK) c->step = step;
+    return rc;
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+}
+
+int dlra_get_uncollided(dlra_ctx *c, double *psibar, double *Du) {
+  if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
+  if (!c->traced) return fail(DLRA_E_STATE, "uncollided_raytrace has not run");
+  try {
+    const Dims &d = c->d;
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (psibar) {
+      size_t cnt = size_t(d.n_steps) * d.n;
+      if (d.tsize == 8) {
+        HIPCHK(hipMemcpy(psibar, c->base + c->plan.psibar, cnt * 8, hipMemcpyDeviceToHost));
+      } else {
+        std::vector<float> h(cnt);
+        HIPCHK(hipMemcpy(h.data(), c->base + c->plan.psibar, cnt * 4, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < cnt; ++i) psibar[i] = h[i];
+      }
+    }
+    if (Du) HIPCHK(hipMemcpy(Du, c->base + c->plan.dose_u, size_t(d.n) * 8, hipMemcpyDeviceToHost));
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  return DLRA_OK;
+}
+
+int dlra_substeps(dlra_ctx *c, int k, int *n_sub) {
+  if (!c || !n_sub) return fail(DLRA_E_INVALID, "null argument");
+  if (k < 0 || k >= c->d.n_steps) return fail(DLRA_E_INVALID, "k outside [0, n_steps)");
+  *n_sub = c->n_sub[k];
+  return DLRA_OK;
+}
+
+int dlra_sync(dlra_ctx *c) {
+  if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
+  hipError_t e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return fail(DLRA_E_HIP, hipGetErrorString(e));
+  return DLRA_OK;
+}
+
+void dlra_destroy(dlra_ctx *c) { delete c; }
+
+const char *dlra_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,700 @@
+// Small dense FP64 kernels: angular Galerkin products, L- and S-step RK4
+// stages, SVD-based truncation, orthonormalisation of augmentations and the
+// collided self-scattering solves.  Matrices are column-major double.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace dlra {
+
+namespace {
+
+constexpr int kT = 16;
+constexpr int kWG = 512;   // threads of the single-workgroup kernels
+
+// ------------------------------------------------------------------ small GEMM
+__global__ void k_small_gemm(int ta, int tb, int M, int N, int K, double alpha,
+                             const double *__restrict__ A, int lda, size_t sA,
+                             const double *__restrict__ B, int ldb, size_t sB, double beta,
+                             double *C, int ldc, size_t sC) {
+  __shared__ double As[kT][kT + 1];
+  __shared__ double Bs[kT][kT + 1];
+  const int z = blockIdx.z;
+  A += z * sA;
+  B += z * sB;
+  C += z * sC;
+  const int tx = threadIdx.x % kT, ty = threadIdx.x / kT;
+  const int row = blockIdx.y * kT + tx;   // output row i
+  const int col = blockIdx.x * kT + ty;   // output col j
+  double acc = 0.0;
+  for (int k0 = 0; k0 < K; k0 += kT) {
+    // As[i][k] = op(A)(row0 + i, k0 + k)
+    {
+      int i = blockIdx.y * kT + tx, k = k0 + ty;
+      double v = 0.0;
+      if (i < M && k < K) v = ta ? A[k + size_t(i) * lda] : A[i + size_t(k) * lda];
+      As[tx][ty] = v;
+    }
+    {
+      int k = k0 + tx, j = blockIdx.x * kT + ty;
+      double v = 0.0;
+      if (k < K && j < N) v = tb ? B[j + size_t(k) * ldb] : B[k + size_t(j) * ldb];
+      Bs[tx][ty] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kT; ++k) acc += As[tx][k] * Bs[k][ty];
+    __syncthreads();
+  }
+  if (row < M && col < N) {
+    double *c = C + row + size_t(col) * ldc;
+    *c = alpha * acc + (beta == 0.0 ? 0.0 : beta * *c);
+  }
+}
+
+// ------------------------------------------------------------------ L-step stage
+constexpr int kLR = 16;   // rows per block
+
+__global__ __launch_bounds__(256) void k_lstep_stage(int m, int r, int ndk,
+                                                    const double *__restrict__ A,
+                                                    const double *__restrict__ C, int ldc,
+                                                    const double *__restrict__ in,
+                                                    const double *__restrict__ L0,
+                                                    double *__restrict__ out, double coef) {
+  __shared__ double Ts[kLR][65];
+  __shared__ double Acc[kLR][65];
+  const int row0 = blockIdx.x * kLR;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kLR * 65; e += 256) (&Acc[0][0])[e] = 0.0;
+  for (int dk = 0; dk < ndk; ++dk) {
+    const double *Ad = A + size_t(dk) * m * m;
+    const double *Cd = C + size_t(dk) * ldc * ldc;
+    __syncthreads();
+    // T(i, k) = sum_q A_dk(row0+i, q) in(q, k)
+    for (int e = tid; e < kLR * r; e += 256) {
+      int i = e % kLR, k = e / kLR;
+      int row = row0 + i;
+      double s = 0.0;
+      if (row < m)
+        for (int q = 0; q < m; ++q) s += Ad[row + size_t(q) * m] * in[q + size_t(k) * m];
+      Ts[i][k] = s;
+    }
+    __syncthreads();
+    // Acc(i, j) += sum_k T(i, k) C_dk(j, k)
+    for (int e = tid; e < kLR * r; e += 256) {
+      int i = e % kLR, j = e / kLR;
+      double s = 0.0;
+      for (int k = 0; k < r; ++k) s += Ts[i][k] * Cd[j + size_t(k) * ldc];
+      Acc[i][j] += s;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kLR * r; e += 256) {
+    int i = e % kLR, j = e / kLR;
+    int row = row0 + i;
+    if (row < m) out[row + size_t(j) * m] = L0[row + size_t(j) * m] - coef * Acc[i][j];
+  }
+}
+
+// ------------------------------------------------------------------ block helpers
+__device__ double blk_sum(double v, double *red) {
+  const int tid = threadIdx.x;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < int(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// C(p x q) = op(A) op(B) inside one workgroup (global operands), C distinct.
+__device__ void blk_gemm(int ta, int tb, int M, int N, int K, double alpha, const double *A,
+                         int lda, const double *B, int ldb, double beta, double *C, int ldc) {
+  for (int e = threadIdx.x; e < M * N; e += blockDim.x) {
+    int i = e % M, j = e / M;
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) {
+      double a = ta ? A[k + size_t(i) * lda] : A[i + size_t(k) * lda];
+      double b = tb ? B[j + size_t(k) * ldb] : B[k + size_t(j) * ldb];
+      s += a * b;
+    }
+    double *c = C + i + size_t(j) * ldc;
+    *c = alpha * s + (beta == 0.0 ? 0.0 : beta * *c);
+  }
+  __syncthreads();
+}
+
+// One-sided Jacobi: orthogonalise the q columns (length p) of A, accumulating
+// the rotations in V (q x q, initialised here).  Parallel round-robin
+// ordering, 8 lanes per column pair.
+__device__ void blk_jacobi(double *A, int lda, int p, int q, double *V, int ldv, int *flag) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < q * q; e += blockDim.x) V[(e % q) + size_t(e / q) * ldv] = (e % q == e / q) ? 1.0 : 0.0;
+  __syncthreads();
+  const int qe = q + (q & 1);
+  if (qe < 2) return;
+  const int lane8 = tid & 7;
+  const int grp = tid >> 3;
+  const int ngrp = blockDim.x >> 3;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int round = 0; round < qe - 1; ++round) {
+      for (int k = grp; k < qe / 2; k += ngrp) {
+        int i, j;
+        if (k == 0) {
+          i = round;
+          j = qe - 1;
+        } else {
+          i = (round + k) % (qe - 1);
+          j = (round - k + qe - 1) % (qe - 1);
+        }
+        if (i > j) {
+          int t = i;
+          i = j;
+          j = t;
+        }
+        bool valid = j < q;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (valid) {
+          for (int t = lane8; t < p; t += 8) {
+            double a = A[t + size_t(i) * lda], b = A[t + size_t(j) * lda];
+            al += a * a;
+            be += b * b;
+            ga += a * b;
+          }
+        }
+        for (int o = 4; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, 8);
+          be += __shfl_xor(be, o, 8);
+          ga += __shfl_xor(ga, o, 8);
+        }
+        if (valid && al > 0.0 && be > 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          double zeta = (be - al) / (2.0 * ga);
+          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+          for (int u = lane8; u < p; u += 8) {
+            double a = A[u + size_t(i) * lda], b = A[u + size_t(j) * lda];
+            A[u + size_t(i) * lda] = c * a - s * b;
+            A[u + size_t(j) * lda] = s * a + c * b;
+          }
+          for (int u = lane8; u < q; u += 8) {
+            double a = V[u + size_t(i) * ldv], b = V[u + size_t(j) * ldv];
+            V[u + size_t(i) * ldv] = c * a - s * b;
+            V[u + size_t(j) * ldv] = s * a + c * b;
+          }
+          if (lane8 == 0) *flag = 1;
+        }
+      }
+      __syncthreads();
+    }
+    int f = *flag;
+    __syncthreads();
+    if (!f) break;
+  }
+}
+
+// column norms of A (p x q) -> sig[q]; order[] = indices sorted by sig descending
+__device__ void blk_colnorms_sorted(const double *A, int lda, int p, int q, double *sig,
+                                    int *order) {
+  for (int j = threadIdx.x; j < q; j += blockDim.x) {
+    double s = 0.0;
+    for (int t = 0; t < p; ++t) s += A[t + size_t(j) * lda] * A[t + size_t(j) * lda];
+    sig[j] = sqrt(s);
+  }
+  __syncthreads();
+  // rank by counting (stable for ties by index)
+  for (int j = threadIdx.x; j < q; j += blockDim.x) {
+    int pos = 0;
+    for (int t = 0; t < q; ++t)
+      if (sig[t] > sig[j] || (sig[t] == sig[j] && t < j)) ++pos;
+    order[pos] = j;
+  }
+  __syncthreads();
+}
+
+// Append up to `need` fillers to the orthonormal columns Q[:, 0:cnt) (length p)
+// from the unit vectors e_0 .. e_{ncand-1} (ordered, two CGS passes, accepted
+// when the residual norm exceeds accept).  Returns the new count.
+__device__ int blk_fill(double *Q, int ldq, int p, int cnt, int need, int ncand, double accept,
+                        double *v, double *coef, double *red) {
+  int added = 0;
+  for (int cand = 0; cand < ncand && added < need; ++cand) {
+    for (int t = threadIdx.x; t < p; t += blockDim.x) v[t] = (t == cand) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+        double s = 0.0;
+        for (int t = 0; t < p; ++t) s += Q[t + size_t(j) * ldq] * v[t];
+        coef[j] = s;
+      }
+      __syncthreads();
+      for (int t = threadIdx.x; t < p; t += blockDim.x) {
+        double s = v[t];
+        for (int j = 0; j < cnt; ++j) s -= Q[t + size_t(j) * ldq] * coef[j];
+        v[t] = s;
+      }
+      __syncthreads();
+    }
+    double nv = 0.0;
+    for (int t = threadIdx.x; t < p; t += blockDim.x) nv += v[t] * v[t];
+    nv = sqrt(blk_sum(nv, red));
+    if (nv > accept) {
+      for (int t = threadIdx.x; t < p; t += blockDim.x) Q[t + size_t(cnt) * ldq] = v[t] / nv;
+      ++cnt;
+      ++added;
+    }
+    __syncthreads();
+  }
+  return cnt;
+}
+
+// ------------------------------------------------------------------ S-step
+__global__ __launch_bounds__(1024) void k_sstep(int P, int ld, int ndk,
+                                               const double *__restrict__ Ch,
+                                               const double *__restrict__ Bh, double *S,
+                                               double *work, double h, int n_sub) {
+  const int PP = P * P;
+  double *S0 = work, *Wm = work + PP, *Tm = work + 2 * PP, *Fm = work + 3 * PP;
+  const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
+  for (int sub = 0; sub < n_sub; ++sub) {
+    for (int e = threadIdx.x; e < PP; e += blockDim.x) {
+      double v = S[(e % P) + size_t(e / P) * ld];
+      S0[e] = v;
+      Wm[e] = v;
+    }
+    __syncthreads();
+    for (int stage = 0; stage < 4; ++stage) {
+      for (int e = threadIdx.x; e < PP; e += blockDim.x) Fm[e] = 0.0;
+      __syncthreads();
+      for (int dk = 0; dk < ndk; ++dk) {
+        const double *C = Ch + size_t(dk) * ld * ld;
+        const double *B = Bh + size_t(dk) * ld * ld;
+        // T = W B_dk
+        for (int e = threadIdx.x; e < PP; e += blockDim.x) {
+          int i = e % P, j = e / P;
+          double s = 0.0;
+          for (int k = 0; k < P; ++k) s += Wm[i + k * P] * B[k + size_t(j) * ld];
+          Tm[e] = s;
+        }
+        __syncthreads();
+        // F -= C_dk T
+        for (int e = threadIdx.x; e < PP; e += blockDim.x) {
+          int i = e % P, j = e / P;
+          double s = 0.0;
+          for (int k = 0; k < P; ++k) s += C[i + size_t(k) * ld] * Tm[k + j * P];
+          Fm[e] -= s;
+        }
+        __syncthreads();
+      }
+      for (int e = threadIdx.x; e < PP; e += blockDim.x) Wm[e] = S0[e] + cf[stage] * h * Fm[e];
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < PP; e += blockDim.x) S[(e % P) + size_t(e / P) * ld] = Wm[e];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ Gram orthonormalisation
+__global__ __launch_bounds__(kWG) void k_gram_orth(int q, const double *__restrict__ W,
+                                                  double *T, int ldt, double tol2,
+                                                  const double *normsq, int *count,
+                                                  const int *restrict_count, double *work) {
+  __shared__ double red[16];
+  __shared__ int flag;
+  __shared__ int order[128];
+  __shared__ double sig[128];
+  const int qq = restrict_count ? *restrict_count : q;
+  double *A = work;               // qq x qq copy of W
+  double *V = work + q * q;       // eigenvectors
+  for (int e = threadIdx.x; e < qq * qq; e += blockDim.x) {
+    int i = e % qq, j = e / qq;
+    A[i + j * qq] = W[i + j * q];
+  }
+  for (int e = threadIdx.x; e < q * q; e += blockDim.x) T[(e % q) + size_t(e / q) * ldt] = 0.0;
+  __syncthreads();
+  blk_jacobi(A, qq, qq, qq, V, qq, &flag);
+  __syncthreads();
+  // for the PSD W, the column norms of W V are its eigenvalues
+  blk_colnorms_sorted(A, qq, qq, qq, sig, order);
+  const double thresh = restrict_count ? 0.0 : tol2 * (*normsq);
+  int kept = 0;
+  for (int t = 0; t < qq; ++t)
+    if (sig[order[t]] > thresh && sig[order[t]] > 0.0) ++kept;
+  for (int e = threadIdx.x; e < qq * kept; e += blockDim.x) {
+    int i = e % qq, c = e / qq;
+    int j = order[c];
+    T[i + size_t(c) * ldt] = V[i + j * qq] / sqrt(sig[j]);
+  }
+  if (threadIdx.x == 0 && count != nullptr && restrict_count == nullptr) *count = kept;
+  (void)red;
+}
+
+// ------------------------------------------------------------------ V augmentation
+__global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
+                                             const double *__restrict__ L, double tol, int *count,
+                                             double *work) {
+  __shared__ double red[16];
+  __shared__ int flag;
+  __shared__ int order[128];
+  __shared__ double sig[128];
+  double *R = work;                    // m x r
+  double *G = R + size_t(m) * r;       // r x r
+  double *W = G + r * r;               // r x r
+  double *Q = W + r * r;               // r x r
+  double *X = Q + r * r;               // m x r
+  // ||L||_F^2
+  double nl = 0.0;
+  for (int e = threadIdx.x; e < m * r; e += blockDim.x) nl += L[e] * L[e];
+  nl = blk_sum(nl, red);
+  for (int e = threadIdx.x; e < m * r; e += blockDim.x) R[e] = L[e];
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    blk_gemm(1, 0, r, r, m, 1.0, Vh, ldv, R, m, 0.0, G, r);              // G = V^T R
+    for (int e = threadIdx.x; e < m * r; e += blockDim.x) {              // R -= V G
+      int i = e % m, j = e / m;
+      double s = 0.0;
+      for (int k = 0; k < r; ++k) s += Vh[i + size_t(k) * ldv] * G[k + j * r];
+      R[e] -= s;
+    }
+    __syncthreads();
+  }
+  blk_gemm(1, 0, r, r, m, 1.0, R, m, R, m, 0.0, W, r);                   // W = R^T R
+  blk_jacobi(W, r, r, r, Q, r, &flag);
+  __syncthreads();
+  blk_colnorms_sorted(W, r, r, r, sig, order);
+  const double thresh = tol * tol * nl;
+  int kept = 0;
+  for (int t = 0; t < r; ++t)
+    if (sig[order[t]] > thresh && sig[order[t]] > 0.0) ++kept;
+  // X1 = R Q_k diag(lambda^-1/2)
+  for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
+    int i = e % m, c = e / m;
+    int j = order[c];
+    double s = 0.0;
+    for (int k = 0; k < r; ++k) s += R[i + size_t(k) * m] * Q[k + j * r];
+    X[i + size_t(c) * m] = s / sqrt(sig[j]);
+  }
+  __syncthreads();
+  if (kept > 0) {
+    // second pass: project once more against V, then X = X1 Q2 diag(lambda2^-1/2)
+    blk_gemm(1, 0, r, kept, m, 1.0, Vh, ldv, X, m, 0.0, G, r);
+    for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
+      int i = e % m, j = e / m;
+      double s = 0.0;
+      for (int k = 0; k < r; ++k) s += Vh[i + size_t(k) * ldv] * G[k + j * r];
+      X[e] -= s;
+    }
+    __syncthreads();
+    blk_gemm(1, 0, kept, kept, m, 1.0, X, m, X, m, 0.0, W, kept);
+    blk_jacobi(W, kept, kept, kept, Q, kept, &flag);
+    __syncthreads();
+    blk_colnorms_sorted(W, kept, kept, kept, sig, order);
+    for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
+      int i = e % m, c = e / m;
+      int j = order[c];
+      double s = 0.0;
+      for (int k = 0; k < kept; ++k) s += X[i + size_t(k) * m] * Q[k + j * kept];
+      Vh[i + size_t(r + c) * ldv] = s / sqrt(sig[j]);
+    }
+  }
+  for (int e = threadIdx.x; e < m * (r - kept); e += blockDim.x) {
+    int i = e % m, c = e / m;
+    Vh[i + size_t(r + kept + c) * ldv] = 0.0;
+  }
+  if (threadIdx.x == 0) *count = kept;
+}
+
+// ------------------------------------------------------------------ truncation
+__global__ __launch_bounds__(kWG) void k_truncate(const double *__restrict__ Sh, int P,
+                                                 const int *kU, const int *kV, int r_base,
+                                                 TruncOpt opt, double *Pp, double *Qp,
+                                                 double *Sp, int lds, Ctl *ctl, double *work) {
+  __shared__ double red[16];
+  __shared__ int flag;
+  __shared__ int order[128];
+  __shared__ double sig[128];
+  const int pU = r_base + (kU ? *kU : 0);
+  const int pV = r_base + (kV ? *kV : 0);
+  const bool cols = pU >= pV;                 // Jacobi on columns of Sh or of Sh^T
+  const int p = cols ? pU : pV, q = cols ? pV : pU;
+  double *A = work;                           // p x q
+  double *V = A + P * P;                      // q x q
+  double *v = V + P * P;                      // P
+  double *coef = v + P;                       // P
+  for (int e = threadIdx.x; e < p * q; e += blockDim.x) {
+    int i = e % p, j = e / p;
+    A[i + j * p] = cols ? Sh[i + j * P] : Sh[j + i * P];
+  }
+  __syncthreads();
+  blk_jacobi(A, p, p, q, V, q, &flag);
+  __syncthreads();
+  blk_colnorms_sorted(A, p, p, q, sig, order);
+  // rank
+  int r1;
+  double s1 = q > 0 ? sig[order[0]] : 0.0;
+  if (opt.fixed) {
+    r1 = opt.r_fixed < q ? opt.r_fixed : q;
+  } else {
+    double total = 0.0;
+    for (int t = 0; t < q; ++t) total += sig[order[t]];
+    double tail = 0.0;
+    r1 = q;
+    // smallest r1 with sum_{t >= r1} sigma_t <= tol * total
+    for (int t = q; t >= 0; --t) {
+      if (t < q) tail += sig[order[t]];
+      if (tail <= opt.trunc_tol * total) r1 = t;
+      else break;
+    }
+    if (r1 < opt.r_min) r1 = opt.r_min;
+    if (r1 > opt.r_max) r1 = opt.r_max;
+    if (r1 > q) r1 = q;
+  }
+  int kept = 0;
+  if (s1 > 0.0)
+    for (int t = 0; t < r1; ++t)
+      if (sig[order[t]] > opt.floor_tol * s1) ++kept;
+  // singular vectors of the kept directions: left (pU) and right (pV)
+  for (int e = threadIdx.x; e < P * r1; e += blockDim.x) {
+    Pp[e] = 0.0;
+    Qp[e] = 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kept * p; e += blockDim.x) {
+    int i = e % p, c = e / p;
+    int j = order[c];
+    double a = A[i + j * p] / sig[j];
+    if (cols) Pp[i + c * P] = a;
+    else Qp[i + c * P] = a;
+  }
+  for (int e = threadIdx.x; e < kept * q; e += blockDim.x) {
+    int i = e % q, c = e / q;
+    int j = order[c];
+    double b = V[i + j * q];
+    if (cols) Qp[i + c * P] = b;
+    else Pp[i + c * P] = b;
+  }
+  __syncthreads();
+  int cu = blk_fill(Pp, P, pU, kept, r1 - kept, pU, opt.fill_tol, v, coef, red);
+  int cv = blk_fill(Qp, P, pV, kept, r1 - kept, pV, opt.fill_tol, v, coef, red);
+  for (int e = threadIdx.x; e < r1 * r1; e += blockDim.x) {
+    int i = e % r1, j = e / r1;
+    Sp[i + j * lds] = (i == j && i < kept) ? sig[order[i]] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    ctl->r_new = r1;
+    if (cu != r1 || cv != r1) atomicOr(&ctl->flags, kFlagCompletion);
+    if (!(s1 == s1) || s1 > 1e300) atomicOr(&ctl->flags, kFlagNonFinite);
+  }
+}
+
+// ------------------------------------------------------------------ collided solves
+__global__ __launch_bounds__(256) void k_collided_solve(int N, int m, int r, int n_mat,
+                                                       const double *__restrict__ M,
+                                                       const double *__restrict__ a, double dt,
+                                                       const double *__restrict__ L0,
+                                                       double *__restrict__ L1) {
+  __shared__ double A[64 * 64];
+  const int l = blockIdx.x;
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+    int i = e % r, j = e / r;
+    double s = (i == j) ? 1.0 : 0.0;
+    for (int mi = 0; mi < n_mat; ++mi) s -= dt * a[mi * (N + 1) + l] * M[size_t(mi) * r * r + e];
+    A[i + j * 64] = s;
+  }
+  __syncthreads();
+  // Cholesky A = R R^T (lower R in place)
+  for (int k = 0; k < r; ++k) {
+    if (threadIdx.x == 0) A[k + k * 64] = sqrt(A[k + k * 64]);
+    __syncthreads();
+    for (int i = k + 1 + threadIdx.x; i < r; i += blockDim.x) A[i + k * 64] /= A[k + k * 64];
+    __syncthreads();
+    for (int e = threadIdx.x; e < (r - k - 1) * (r - k - 1); e += blockDim.x) {
+      int i = k + 1 + e % (r - k - 1), j = k + 1 + e / (r - k - 1);
+      if (j <= i) A[i + j * 64] -= A[i + k * 64] * A[j + k * 64];
+    }
+    __syncthreads();
+  }
+  // rows p of degree l: solve R R^T x = L0(p, :)^T
+  const int p0 = l * l, np = 2 * l + 1;
+  for (int t = threadIdx.x; t < np; t += blockDim.x) {
+    const int p = p0 + t;
+    double x[64];
+    for (int j = 0; j < r; ++j) x[j] = L0[p + size_t(j) * m];
+    for (int i = 0; i < r; ++i) {
+      double s = x[i];
+      for (int k = 0; k < i; ++k) s -= A[i + k * 64] * x[k];
+      x[i] = s / A[i + i * 64];
+    }
+    for (int i = r - 1; i >= 0; --i) {
+      double s = x[i];
+      for (int k = i + 1; k < r; ++k) s -= A[k + i * 64] * x[k];
+      x[i] = s / A[i + i * 64];
+    }
+    for (int j = 0; j < r; ++j) L1[p + size_t(j) * m] = x[j];
+  }
+}
+
+// ------------------------------------------------------------------ QR with completion
+__global__ __launch_bounds__(kWG) void k_qr_complete(int m, int r, const double *__restrict__ L1,
+                                                    const double *__restrict__ V, double tol,
+                                                    double fill_tol, double *Vt, double *St,
+                                                    int lds, Ctl *ctl, double *work) {
+  __shared__ double red[16];
+  double *v = work;
+  double *coef = work + m;
+  double nl = 0.0;
+  for (int e = threadIdx.x; e < m * r; e += blockDim.x) nl += L1[e] * L1[e];
+  const double thr = tol * sqrt(blk_sum(nl, red));
+  int cnt = 0;
+  for (int src = 0; src < 2; ++src) {
+    const double *cand = src == 0 ? L1 : V;
+    const double accept = src == 0 ? thr : fill_tol;
+    for (int c = 0; c < r && cnt < r; ++c) {
+      for (int t = threadIdx.x; t < m; t += blockDim.x) v[t] = cand[t + size_t(c) * m];
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+          double s = 0.0;
+          for (int t = 0; t < m; ++t) s += Vt[t + size_t(j) * m] * v[t];
+          coef[j] = s;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < m; t += blockDim.x) {
+          double s = v[t];
+          for (int j = 0; j < cnt; ++j) s -= Vt[t + size_t(j) * m] * coef[j];
+          v[t] = s;
+        }
+        __syncthreads();
+      }
+      double nv = 0.0;
+      for (int t = threadIdx.x; t < m; t += blockDim.x) nv += v[t] * v[t];
+      nv = sqrt(blk_sum(nv, red));
+      if (nv > accept) {
+        for (int t = threadIdx.x; t < m; t += blockDim.x) Vt[t + size_t(cnt) * m] = v[t] / nv;
+        ++cnt;
+      }
+      __syncthreads();
+    }
+  }
+  if (cnt != r && threadIdx.x == 0) atomicOr(&ctl->flags, kFlagCompletion);
+  // S~ = L1^T V~
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+    int i = e % r, j = e / r;
+    double s = 0.0;
+    for (int t = 0; t < m; ++t) s += L1[t + size_t(i) * m] * Vt[t + size_t(j) * m];
+    St[i + j * lds] = s;
+  }
+}
+
+__global__ void k_check_finite(const double *__restrict__ x, int count, Ctl *ctl) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < count) {
+    double v = x[e];
+    if (!(v == v) || fabs(v) > 1e300) atomicOr(&ctl->flags, kFlagNonFinite);
+  }
+}
+
+__global__ void k_min_stop(int n, const double *__restrict__ w, int n_mat,
+                           const double *__restrict__ Sk, double *out) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  double mn = 1e300;
+  for (int x = threadIdx.x; x < n; x += 256) {
+    double s = 0.0;
+    for (int i = 0; i < n_mat; ++i) s += w[size_t(i) * n + x] * Sk[k * n_mat + i];
+    mn = s < mn ? s : mn;
+  }
+  red[threadIdx.x] = mn;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = red[0];
+}
+
+}  // namespace
+
+void launch_small_gemm(int ta, int tb, int M, int N, int K, double alpha, const double *A,
+                       int lda, size_t sA, const double *B, int ldb, size_t sB, double beta,
+                       double *C, int ldc, size_t sC, int batch, hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  dim3 grid((N + kT - 1) / kT, (M + kT - 1) / kT, batch);
+  k_small_gemm<<<grid, kT * kT, 0, st>>>(ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta,
+                                         C, ldc, sC);
+}
+
+void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C, int ldc,
+                        const double *in, const double *L0, double *out, double coef,
+                        hipStream_t st) {
+  k_lstep_stage<<<(m + kLR - 1) / kLR, 256, 0, st>>>(m, r, ndk, A, C, ldc, in, L0, out, coef);
+}
+
+void launch_sstep(int p, int ld, int ndk, const double *Ch, const double *Bh, double *S,
+                  double *work, double h, int n_sub, hipStream_t st) {
+  k_sstep<<<1, 1024, 0, st>>>(p, ld, ndk, Ch, Bh, S, work, h, n_sub);
+}
+
+__global__ void k_copy_block(int rows, int cols, const double *__restrict__ src, int lds,
+                             double *__restrict__ dst, int ldd, int dst_rows, int dst_cols,
+                             double alpha) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= dst_rows * dst_cols) return;
+  int i = e % dst_rows, j = e / dst_rows;
+  double v = 0.0;
+  if (i < rows && j < cols && src != nullptr) v = alpha * src[i + size_t(j) * lds];
+  dst[i + size_t(j) * ldd] = v;
+}
+
+void launch_copy_block(int rows, int cols, const double *src, int lds, double *dst, int ldd,
+                       int dst_rows, int dst_cols, double alpha, hipStream_t st) {
+  int tot = dst_rows * dst_cols;
+  if (tot <= 0) return;
+  k_copy_block<<<(tot + 255) / 256, 256, 0, st>>>(rows, cols, src, lds, dst, ldd, dst_rows,
+                                                  dst_cols, alpha);
+}
+
+void launch_gram_orth(int q, const double *W, double *T, int ldt, double tol2,
+                      const double *normsq, int *count, const int *restrict_count, double *work,
+                      hipStream_t st) {
+  k_gram_orth<<<1, kWG, 0, st>>>(q, W, T, ldt, tol2, normsq, count, restrict_count, work);
+}
+
+void launch_vaug(int m, int r, double *Vh, int ldv, const double *L, double tol, int *count,
+                 double *work, hipStream_t st) {
+  k_vaug<<<1, kWG, 0, st>>>(m, r, Vh, ldv, L, tol, count, work);
+}
+
+void launch_truncate(const double *Sh, int P, const int *kU, const int *kV, int r_base,
+                     TruncOpt opt, double *Pp, double *Qp, double *Sp, int lds, Ctl *ctl,
+                     double *work, hipStream_t st) {
+  k_truncate<<<1, kWG, 0, st>>>(Sh, P, kU, kV, r_base, opt, Pp, Qp, Sp, lds, ctl, work);
+}
+
+void launch_collided_solve(int N, int m, int r, int n_mat, const double *M, const double *a,
+                           double dt, const double *L0, double *L1, hipStream_t st) {
+  k_collided_solve<<<N + 1, 256, 0, st>>>(N, m, r, n_mat, M, a, dt, L0, L1);
+}
+
+void launch_qr_complete(int m, int r, const double *L1, const double *V, double tol,
+                        double fill_tol, double *Vt, double *St, int lds, Ctl *ctl,
+                        double *work, hipStream_t st) {
+  k_qr_complete<<<1, kWG, 0, st>>>(m, r, L1, V, tol, fill_tol, Vt, St, lds, ctl, work);
+}
+
+void launch_check_finite(const double *x, int count, Ctl *ctl, hipStream_t st) {
+  if (count <= 0) return;
+  k_check_finite<<<(count + 255) / 256, 256, 0, st>>>(x, count, ctl);
+}
+
+void launch_min_stop(int n, const double *w, int n_mat, const double *Sk, int n_steps,
+                     double *out, hipStream_t st) {
+  k_min_stop<<<n_steps, 256, 0, st>>>(n, w, n_mat, Sk, out);
+}
+
+}  // namespace dlra

@@ -1,0 +1,71 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/dlra.h, and rejects invalid problems before touching the
+device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2508_04484_amd import binding as B
+from workloads import configs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "dlra.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*([a-z_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = B.load()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(B.EXPORTS) == names
+
+
+def test_struct_layouts_match_header():
+    # field order and sizes as in include/dlra.h (LP64)
+    assert C.sizeof(B.Grid) == 3 * 4 + 4 + 3 * 8
+    assert C.sizeof(B.Beam) == 10 * 8
+    assert C.sizeof(B.Options) == 9 * 4 + 4 + 9 * 8
+    assert C.sizeof(B.Materials) == 3 * 4 + 4 + 5 * 8
+
+
+def test_workspace_size_scales_with_problem():
+    small = B.workspace_size(configs.small_2d())
+    big = B.workspace_size(configs.small_2d(nx=64, ny=64))
+    assert 0 < small < big
+
+
+@pytest.mark.parametrize("bad", [
+    dict(r=0), dict(r=60, r_max=60), dict(n_steps=0), dict(precision="half"),
+    dict(rank_mode="adaptive", r_min=5, r_max=3),
+])
+def test_invalid_options_rejected(bad):
+    p = configs.small_2d()
+    opts = p.options.with_(**bad)
+    if opts.precision not in ("fp64", "mixed"):
+        o = B.make_options(p.options)
+        o.precision = 7
+    else:
+        o = B.make_options(opts)
+    out = C.c_size_t(0)
+    rc = B.load().dlra_workspace_size(C.byref(B.make_grid(p.grid)), p.materials.n_mat,
+                                      C.byref(o), C.byref(out))
+    assert rc == -1
+    assert B.load().dlra_last_error()
+
+
+def test_init_rejects_null_workspace_without_touching_the_gpu():
+    p = configs.small_2d()
+    lib = B.load()
+    ctx = C.c_void_p(0)
+    rc = lib.dlra_init(C.byref(B.make_grid(p.grid)), None, None,
+                       C.byref(B.make_options(p.options)), None, 0, None, C.byref(ctx))
+    assert rc == -1 and not ctx.value
