@@ -1,0 +1,222 @@
+"""Throughput of the DLRA proton-transport energy step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c3]
+
+Default workload (c3): 128^3 voxels of 1 mm, Gaussian-random-field density
+0.2..1.9 g/cm^3 mixed from water/bone/air, one 150 MeV pencil beam
+(sigma 5 mm), P_15 (256 moments), fixed rank 30, 250 energy steps, FP32
+stencil/projections with FP64 QR/SVD/truncation.  Inputs are generated
+(seeded) and resident in HBM before timing.  A "step" is one energy step
+(dlra_step: streaming BUG with RK4 substeps, collided scattering, uncollided
+source, truncation, dose).  The uncollided ray tracer runs once before the
+timed region and is reported separately.
+
+Prints one JSON line (value = energy-steps/s over the K timed steps), with a
+roofline entry for the dominant kernel (the K-step stencil stage, timed live
+with HIP events on the library's stream) and the CPU reference timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DLRA energy-steps/s at 128³ r=30; beams/s batched vs plain; adjoint/fwd"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
+FP32_MFMA_TFLOPS = 157.3
+
+
+def kstage_algorithmic(problem):
+    """(flops, bytes) of one K-step RK4 stage over all cells: per cell the
+    contraction of 2*dim difference vectors with r x r couplings (2 ndk r^2),
+    the differences (4 ndk r) and the stage combine (2 r); bytes = read the
+    stage input, K0 and s, write the stage output."""
+    g, o = problem.grid, problem.options
+    ndk = 2 * g.dim
+    r = o.r if o.rank_mode == "fixed" else o.r_max
+    b = 8 if o.precision == "fp64" else 4
+    flops = g.n * (2 * ndk * r * r + 4 * ndk * r + 2 * r)
+    nbytes = g.n * (3 * r + 1) * b
+    return flops, nbytes
+
+
+def cpu_baseline(problem, budget_planes=8):
+    """Time one reference (CPU, FP64) step on a z-slab of the phantom from a
+    seeded random rank-r state at the step whose substep count is closest to
+    the run's mean, and scale to the whole phantom."""
+    import dataclasses
+
+    import numpy as np
+
+    from oracle import coeffs, dlra, solver
+    from workloads.problem import Grid
+
+    try:
+        import threadpoolctl
+        threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    g = problem.grid
+    o = problem.options
+    nzs = min(budget_planes, g.nz)
+    z0 = (g.nz - nzs) // 2
+    sub = Grid(g.nx, g.ny, nzs, g.dx, g.dy, g.dz)
+    plane = g.nx * g.ny
+    w = problem.materials.w[:, z0 * plane:(z0 + nzs) * plane].copy()
+    mats = dataclasses.replace(problem.materials, w=w)
+    beam = dataclasses.replace(problem.beams[0], pos=(0.0, problem.beams[0].pos[1],
+                                                      0.5 * nzs * g.dz))
+    p = dataclasses.replace(problem, grid=sub, materials=mats, beams=[beam],
+                            options=o.with_(precision="fp64"))
+    nsub = [coeffs.step_coeffs(problem, problem.beams[0], k).n_sub for k in range(o.n_steps)]
+    mean_nsub = sum(nsub) / len(nsub)
+    k = min(range(o.n_steps), key=lambda j: abs(nsub[j] - mean_nsub))
+    rng = np.random.default_rng(7)
+    r = o.r
+    U, _ = np.linalg.qr(rng.standard_normal((sub.n, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((p.m, r)))
+    S = np.diag(np.logspace(0, -6, r))
+    st = dlra.State(U, S, V, np.zeros(sub.n), k)
+    c = coeffs.step_coeffs(p, beam, k)
+    x = (np.arange(sub.n) % g.nx + 0.5) * g.dx
+    psi = np.exp(-x)                                      # synthetic uncollided source
+    Apm = solver.streaming_split(p)
+    t0 = time.perf_counter()
+    dlra.step(st, c, Apm, p, psi)
+    dt = time.perf_counter() - t0
+    scale = (g.n / sub.n) * (mean_nsub / c.n_sub)
+    return {
+        "value": 1.0 / (dt * scale), "unit": "energy-steps/s", "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"one FP64 reference step (k={k}, n_sub={c.n_sub}) on a "
+                   f"{g.nx}x{g.ny}x{nzs} slab of the phantom from a seeded random rank-{r} "
+                   f"state with a synthetic source, {dt:.2f} s, scaled by cells "
+                   f"x{g.n / sub.n:.0f} and substeps x{mean_nsub / c.n_sub:.3f} "
+                   f"(run mean n_sub {mean_nsub:.2f})"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=250)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(the path runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2508_04484_amd as dl
+    from workloads import configs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    problem = configs.CONFIGS[args.config]()
+    o = problem.options
+    K = min(args.steps, o.n_steps)
+
+    # warm-up: a separate solver runs W steps (code objects, allocator, caches)
+    if args.warmup > 0:
+        s = dl.BeamSolver(problem, 0)
+        s.raytrace()
+        for _ in range(min(args.warmup, o.n_steps)):
+            s.step()
+        s.sync()
+        s.close()
+        del s
+        torch.cuda.synchronize()
+
+    s = dl.BeamSolver(problem, 0)
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.raytrace()
+    s.sync()
+    t_ray = time.perf_counter() - t0
+    prof_ray = s.profile_read()["raytrace"]
+    s.profile(True)          # reset counters for the timed region
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(K):
+        s.step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = s.profile_read()
+    s.profile(False)
+    rank = s.step(sync=True) if False else None
+    nsub = [s.substeps(k) for k in range(K)]
+    s.close()
+
+    ms_step = 1000.0 * wall / K
+    flops, nbytes = kstage_algorithmic(problem)
+    ks_ms, ks_n = prof["kstage"]
+    avg = ks_ms / max(ks_n, 1) / 1000.0
+    achieved_flops = flops / avg / 1e12
+    achieved_gbs = nbytes / avg / 1e9
+    # the stage kernel computes its contraction with FP64 vector FMAs
+    frac_alu = achieved_flops / FP64_VECTOR_TFLOPS
+    frac_hbm = achieved_gbs / HBM_PEAK_GBS
+    if frac_alu >= frac_hbm:
+        roof = {"bound": "alu", "achieved": round(achieved_flops, 3), "peak": FP64_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(frac_alu, 4), "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(frac_hbm, 4), "traffic": None}
+    roof.update({"kernel": "k_kstep_stage", "avg_launch_ms": round(avg * 1e3, 4),
+                 "launches": ks_n, "algorithmic_flops_per_launch": flops,
+                 "algorithmic_bytes_per_launch": nbytes,
+                 "hbm_frac": round(frac_hbm, 4), "alu_frac": round(frac_alu, 4)})
+    g = problem.grid
+    out = {
+        "metric": METRIC,
+        "value": round(K / wall, 4),
+        "unit": "energy-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if o.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{problem.name}: {g.nx}x{g.ny}x{g.nz} voxels of {g.dx * 10:g} mm, "
+                         f"{problem.beams[0].E0:g} MeV pencil beam, P_{o.pn_degree} "
+                         f"({problem.m} moments), rank {o.r} ({o.rank_mode}), "
+                         f"{o.n_steps} energy steps, {o.precision}"),
+            "cells": g.n, "moments": problem.m, "rank": o.r, "energy_steps_total": o.n_steps,
+            "timed_steps": f"0..{K - 1}", "mean_rk4_substeps": round(sum(nsub) / len(nsub), 3),
+        },
+        "event_ms_per_step": round(ev0.elapsed_time(ev1) / K, 3),
+        "raytrace_ms": round(1000.0 * t_ray, 2),
+        "raytrace_kernel_ms": round(prof_ray[0], 2),
+        "phase_ms_per_step": {k: round(v[0] / K, 3) for k, v in prof.items()
+                              if k not in ("raytrace",) and v[1] > 0},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline and args.config == "c3":
+        out["cpu_baseline"] = cpu_baseline(problem)
+    elif not args.no_cpu_baseline:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

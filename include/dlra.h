@@ -182,6 +182,29 @@ int dlra_substeps(dlra_ctx *ctx, int k, int *n_sub);
 /* Waits for the context's stream. */
 int dlra_sync(dlra_ctx *ctx);
 
+/* Timing of the library's own work with HIP events recorded on the context's
+ * stream (measurement support; adds one event pair per timed launch).
+ *   dlra_profile(ctx, on): on = 1 starts recording, 0 stops; counters are
+ *                          reset when recording starts.
+ *   dlra_profile_read(ctx, phase, total_ms, count): synchronises and returns
+ *                          the summed duration and number of recorded launches
+ *                          of one phase (DLRA_PH_*). */
+enum {
+  DLRA_PH_KSTAGE = 0,      /* one RK4 stage of the K-step stencil kernel */
+  DLRA_PH_PROJECTION = 1,  /* stencil projections U^T d(sU) */
+  DLRA_PH_LSTEP = 2,       /* L-step RK4 (all substeps of one step) */
+  DLRA_PH_AUGMENT = 3,     /* basis augmentation (U and V, both BUG parts) */
+  DLRA_PH_SSTEP = 4,       /* S-step RK4 */
+  DLRA_PH_TRUNCATE = 5,    /* SVD truncation and basis rotation */
+  DLRA_PH_COLLIDED = 6,    /* collided self-scattering L-step and QR */
+  DLRA_PH_SOURCE = 7,      /* uncollided source products */
+  DLRA_PH_STEP = 8,        /* a whole dlra_step */
+  DLRA_PH_RAYTRACE = 9,    /* uncollided_raytrace */
+  DLRA_PH_COUNT = 10
+};
+int dlra_profile(dlra_ctx *ctx, int on);
+int dlra_profile_read(dlra_ctx *ctx, int phase, double *total_ms, long long *count);
+
 /* Releases the context (not the caller's workspace). */
 void dlra_destroy(dlra_ctx *ctx);
 

@@ -23,7 +23,10 @@ DOSE_UNCOLLIDED, DOSE_COLLIDED, DOSE_PER_MASS = 1, 2, 4
 
 EXPORTS = ["dlra_workspace_size", "dlra_init", "uncollided_raytrace", "dlra_step",
            "dose_deposit", "dlra_get_state", "dlra_set_state", "dlra_get_uncollided",
-           "dlra_substeps", "dlra_sync", "dlra_destroy", "dlra_last_error"]
+           "dlra_substeps", "dlra_sync", "dlra_profile", "dlra_profile_read", "dlra_destroy",
+           "dlra_last_error"]
+PHASES = ["kstage", "projection", "lstep", "augment", "sstep", "truncate", "collided", "source",
+          "step", "raytrace"]
 
 
 class DlraError(RuntimeError):
@@ -85,6 +88,8 @@ def load(path: str = LIB_PATH):
     lib.dlra_get_uncollided.argtypes = [P, D, D]
     lib.dlra_substeps.argtypes = [P, I, C.POINTER(I)]
     lib.dlra_sync.argtypes = [P]
+    lib.dlra_profile.argtypes = [P, I]
+    lib.dlra_profile_read.argtypes = [P, I, D, C.POINTER(C.c_longlong)]
     lib.dlra_destroy.argtypes = [P]
     lib.dlra_destroy.restype = None
     lib.dlra_last_error.restype = C.c_char_p
@@ -198,6 +203,18 @@ class BeamSolver:
         out = self.torch.empty(self.n, dtype=self.torch.float64, device="cuda")
         check(self.lib.dose_deposit(self.ctx, C.c_void_p(out.data_ptr()), flags))
         self.sync()
+        return out
+
+    def profile(self, on=True):
+        check(self.lib.dlra_profile(self.ctx, 1 if on else 0))
+
+    def profile_read(self):
+        """{phase: (total_ms, launches)} of the event timings recorded so far."""
+        out = {}
+        for i, name in enumerate(PHASES):
+            ms, cnt = C.c_double(0.0), C.c_longlong(0)
+            check(self.lib.dlra_profile_read(self.ctx, i, C.byref(ms), C.byref(cnt)))
+            out[name] = (ms.value, cnt.value)
         return out
 
     def substeps(self, k):

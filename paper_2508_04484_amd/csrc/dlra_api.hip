@@ -53,7 +53,7 @@ struct Plan {
   }
   // offsets
   size_t w_t, w_d, s, tall[4], psibar, dose_c, dose_u, Apm, AV, stepS, stepA, stepG, minstop;
-  size_t S, V, Vn, Bm, Cm, Sh, Pp, Qp, Sp, G1, G2, Wg, T1, T2, Lm, L0, La, Lb, Mi, H, Cg, dc,
+  size_t S, V, Vn, Bm, Bpk, Cm, Sh, Pp, Qp, Sp, G1, G2, Wg, T1, T2, Lm, L0, La, Lb, Mi, H, Cg, dc,
       tmp, work, partial, ctl;
   size_t rt_diag, rt_up, rt_lo, rt_mass, rt_c0, rt_g0, rt_sw, rt_stopw, rt_rows, rt_f,
       rt_scratch;
@@ -151,6 +151,7 @@ Plan make_plan(const Dims &d) {
   p.V = p.take(m * P * 8);
   p.Vn = p.take(m * P * 8);
   p.Bm = p.take(d.ndk * P * P * 8);
+  p.Bpk = p.take(d.ndk * 64 * 64 * 8);
   p.Cm = p.take(d.ndk * P * P * 8);
   p.Sh = p.take(P * P * 8);
   p.Pp = p.take(P * R * 8);
@@ -217,15 +218,79 @@ struct dlra_ctx {
   // rotating tall buffers: 0 = Uhat, 1 = K, 2 = Wa, 3 = Wb
   void *tall[4];
   double *V, *Vn;
+  // event-based timing
+  struct Rec {
+    hipEvent_t a, b;
+    int ph;
+  };
+  bool prof = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> pending;
+  double prof_ms[DLRA_PH_COUNT] = {};
+  long long prof_n[DLRA_PH_COUNT] = {};
 
   template <typename T>
   T *at(size_t off) {
     return reinterpret_cast<T *>(base + off);
   }
   Ctl *ctl() { return at<Ctl>(plan.ctl); }
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
+    return e;
+  }
+  void drain() {
+    if (pending.empty()) return;
+    if (hipStreamSynchronize(st) != hipSuccess) throw std::runtime_error("stream sync failed");
+    for (auto &r : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        prof_ms[r.ph] += ms;
+        prof_n[r.ph] += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  ~dlra_ctx() {
+    if (!pending.empty() || !pool.empty()) {
+      hipStreamSynchronize(st);
+      for (auto &r : pending) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+      }
+      for (auto e : pool) hipEventDestroy(e);
+    }
+  }
 };
 
 namespace {
+
+// records an event pair around a phase when timing is on
+struct PhaseTimer {
+  dlra_ctx *c;
+  int ph;
+  hipEvent_t a = nullptr;
+  PhaseTimer(dlra_ctx *c_, int ph_) : c(c_), ph(ph_) {
+    if (c->prof) {
+      a = c->event();
+      hipEventRecord(a, c->st);
+    }
+  }
+  ~PhaseTimer() {
+    if (a) {
+      hipEvent_t b = c->event();
+      hipEventRecord(b, c->st);
+      c->pending.push_back({a, b, ph});
+    }
+  }
+};
 
 void upload(dlra_ctx *c, size_t off, const void *src, size_t bytes) {
   HIPCHK(hipMemcpyAsync(c->base + off, src, bytes, hipMemcpyHostToDevice, c->st));
@@ -563,13 +628,18 @@ struct Stepper {
     Ctl *ctl = c->ctl();
     int r = c->r;
     T *s = c->at<T>(p.s);
+    PhaseTimer t_step(c, DLRA_PH_STEP);
     // coefficients
     launch_inverse_stop<T>(c->gdev, c->at<T>(p.w_t), nm, D(p.stepS) + size_t(k) * nm, s, ctl, st);
     // ---------------- streaming (augmented BUG, RK4)
     angular(r, c->V);
-    launch_stencil_projection<T, Acc>(c->gdev, s, tall(0), ld, r, D(p.Cm), P, D(p.partial),
-                                      p.partial_elems, st);
+    {
+      PhaseTimer t(c, DLRA_PH_PROJECTION);
+      launch_stencil_projection<T, Acc>(c->gdev, s, tall(0), ld, r, D(p.Cm), P, D(p.partial),
+                                        p.partial_elems, st);
+    }
     // K-step: K0 = U S, Horner RK4
+    launch_pack_couplings<T>(dd.ndk, r, D(p.Bm), P, c->at<T>(p.Bpk), st);
     launch_update<T>(n, tall(0), ld, r, D(p.S), R, 1.0, nullptr, 0, 0.0, tall(1), ld, r, nullptr,
                      nullptr, 0, st);
     const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
@@ -579,67 +649,98 @@ struct Stepper {
       T *outs[2] = {tall(2), tall(3)};
       for (int stg = 0; stg < 4; ++stg) {
         T *out = outs[stg & 1];
-        launch_kstep_stage<T>(c->gdev, s, in, K0, out, ld, r, D(p.Bm), P, cf[stg] * h, st);
+        PhaseTimer t(c, DLRA_PH_KSTAGE);
+        launch_kstep_stage<T>(c->gdev, s, in, K0, out, ld, r, c->at<T>(p.Bpk), cf[stg] * h, st);
         in = out;
       }
       std::swap(c->tall[1], c->tall[3]);
     }
     // L-step: L0 = V S^T, Horner RK4 (m x r)
     double *Lk = D(p.L0), *La = D(p.La), *Lb = D(p.Lb);
-    launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, Lk, m, 0, 1, st);
-    for (int sub = 0; sub < ns; ++sub) {
-      double *in = Lk;
-      double *outs[2] = {La, Lb};
-      for (int stg = 0; stg < 4; ++stg) {
-        double *out = outs[stg & 1];
-        launch_lstep_stage(m, r, dd.ndk, D(p.Apm), D(p.Cm), P, in, Lk, out, cf[stg] * h, st);
-        in = out;
+    {
+      PhaseTimer t(c, DLRA_PH_LSTEP);
+      launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, Lk, m, 0, 1, st);
+      for (int sub = 0; sub < ns; ++sub) {
+        double *in = Lk;
+        double *outs[2] = {La, Lb};
+        for (int stg = 0; stg < 4; ++stg) {
+          double *out = outs[stg & 1];
+          launch_lstep_stage(m, r, dd.ndk, D(p.Apm), D(p.Cm), P, in, Lk, out, cf[stg] * h,
+                             D(p.AV), size_t(m) * P, st);
+          in = out;
+        }
+        std::swap(Lk, Lb);
       }
-      std::swap(Lk, Lb);
     }
     // augmentation
-    augment_u(r, tall(1));
-    launch_vaug(m, r, c->V, m, Lk, c->opt.aug_tol, &ctl->kV, D(p.work), st);
+    {
+      PhaseTimer t(c, DLRA_PH_AUGMENT);
+      augment_u(r, tall(1));
+      launch_vaug(m, r, c->V, m, Lk, c->opt.aug_tol, &ctl->kV, D(p.work), st);
+    }
     // S-step on the augmented bases
-    launch_stencil_projection<T, Acc>(c->gdev, s, tall(0), ld, 2 * r, D(p.Cm), P, D(p.partial),
-                                      p.partial_elems, st);
-    angular(2 * r, c->V);
-    launch_copy_block(r, r, D(p.S), R, D(p.Sh), P, P, P, 1.0, st);
-    launch_sstep(2 * r, P, dd.ndk, D(p.Cm), D(p.Bm), D(p.Sh), D(p.work), h, ns, st);
-    r = truncate_rotate(r, false, &ctl->kU, &ctl->kV);
+    {
+      PhaseTimer t(c, DLRA_PH_PROJECTION);
+      launch_stencil_projection<T, Acc>(c->gdev, s, tall(0), ld, 2 * r, D(p.Cm), P, D(p.partial),
+                                        p.partial_elems, st);
+    }
+    {
+      PhaseTimer t(c, DLRA_PH_SSTEP);
+      angular(2 * r, c->V);
+      launch_copy_block(r, r, D(p.S), R, D(p.Sh), P, P, P, 1.0, st);
+      launch_sstep(2 * r, P, dd.ndk, D(p.Cm), D(p.Bm), D(p.Sh), D(p.work), h, ns, st);
+    }
+    {
+      PhaseTimer t(c, DLRA_PH_TRUNCATE);
+      r = truncate_rotate(r, false, &ctl->kU, &ctl->kV);
+    }
     // ---------------- collided self-scattering (L-step, implicit Euler)
-    for (int i = 0; i < nm; ++i)
-      launch_gram<T, Acc>(n, tall(0), ld, r, tall(0), ld, r, c->at<T>(p.w_t) + size_t(i) * n, s,
-                          D(p.Mi) + size_t(i) * r * r, r, D(p.partial), p.partial_elems, st);
-    launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, D(p.L0), m, 0, 1, st);
-    launch_collided_solve(N, m, r, nm, D(p.Mi), D(p.stepA) + size_t(k) * nm * (N + 1), dt,
-                          D(p.L0), D(p.La), st);
-    launch_qr_complete(m, r, D(p.La), c->V, c->opt.aug_tol, c->opt.fill_tol, c->Vn, D(p.S), R,
-                       ctl, D(p.work), st);
-    std::swap(c->V, c->Vn);
+    {
+      PhaseTimer t(c, DLRA_PH_COLLIDED);
+      for (int i = 0; i < nm; ++i)
+        launch_gram<T, Acc>(n, tall(0), ld, r, tall(0), ld, r, c->at<T>(p.w_t) + size_t(i) * n,
+                            s, D(p.Mi) + size_t(i) * r * r, r, D(p.partial), p.partial_elems, st);
+      launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, D(p.L0), m, 0, 1, st);
+      launch_collided_solve(N, m, r, nm, D(p.Mi), D(p.stepA) + size_t(k) * nm * (N + 1), dt,
+                            D(p.L0), D(p.La), st);
+      launch_qr_complete(m, r, D(p.La), c->V, c->opt.aug_tol, c->opt.fill_tol, c->Vn, D(p.S), R,
+                         ctl, D(p.work), st);
+      std::swap(c->V, c->Vn);
+    }
     // ---------------- uncollided in-scattering source (explicit Euler K, L, S)
     const T *psi = c->at<T>(p.psibar) + size_t(k) * n;
     const double *gk = D(p.stepG) + size_t(k) * m * nm;
-    launch_xt_source<T, Acc>(n, tall(0), ld, r, c->at<T>(p.w_t), nm, psi, D(p.H), P,
-                             D(p.partial), p.partial_elems, st);
-    launch_small_gemm(1, 0, r, nm, m, 1.0, c->V, m, 0, gk, m, 0, 0.0, D(p.Cg), P, 0, 1, st);
-    launch_source_k<T>(n, tall(0), ld, r, D(p.S), R, c->at<T>(p.w_t), nm, psi, D(p.Cg), P, dt,
-                       tall(1), st);
-    launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, D(p.Lm), m, 0, 1, st);
-    launch_small_gemm(0, 1, m, r, nm, dt, gk, m, 0, D(p.H), P, 0, 1.0, D(p.Lm), m, 0, 1, st);
-    augment_u(r, tall(1));
-    launch_vaug(m, r, c->V, m, D(p.Lm), c->opt.aug_tol, &ctl->kV, D(p.work), st);
-    launch_xt_source<T, Acc>(n, tall(0), ld, 2 * r, c->at<T>(p.w_t), nm, psi, D(p.H), P,
-                             D(p.partial), p.partial_elems, st);
-    launch_small_gemm(1, 0, 2 * r, nm, m, 1.0, c->V, m, 0, gk, m, 0, 0.0, D(p.Cg), P, 0, 1, st);
-    launch_copy_block(r, r, D(p.S), R, D(p.Sh), P, P, P, 1.0, st);
-    launch_small_gemm(0, 1, 2 * r, 2 * r, nm, dt, D(p.H), P, 0, D(p.Cg), P, 0, 1.0, D(p.Sh), P,
-                      0, 1, st);
-    r = truncate_rotate(r, true, &ctl->kU, &ctl->kV);
+    {
+      PhaseTimer t(c, DLRA_PH_SOURCE);
+      launch_xt_source<T, Acc>(n, tall(0), ld, r, c->at<T>(p.w_t), nm, psi, D(p.H), P,
+                               D(p.partial), p.partial_elems, st);
+      launch_small_gemm(1, 0, r, nm, m, 1.0, c->V, m, 0, gk, m, 0, 0.0, D(p.Cg), P, 0, 1, st);
+      launch_source_k<T>(n, tall(0), ld, r, D(p.S), R, c->at<T>(p.w_t), nm, psi, D(p.Cg), P, dt,
+                         tall(1), st);
+      launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, D(p.Lm), m, 0, 1, st);
+      launch_small_gemm(0, 1, m, r, nm, dt, gk, m, 0, D(p.H), P, 0, 1.0, D(p.Lm), m, 0, 1, st);
+    }
+    {
+      PhaseTimer t(c, DLRA_PH_AUGMENT);
+      augment_u(r, tall(1));
+      launch_vaug(m, r, c->V, m, D(p.Lm), c->opt.aug_tol, &ctl->kV, D(p.work), st);
+    }
+    {
+      PhaseTimer t(c, DLRA_PH_SOURCE);
+      launch_xt_source<T, Acc>(n, tall(0), ld, 2 * r, c->at<T>(p.w_t), nm, psi, D(p.H), P,
+                               D(p.partial), p.partial_elems, st);
+      launch_small_gemm(1, 0, 2 * r, nm, m, 1.0, c->V, m, 0, gk, m, 0, 0.0, D(p.Cg), P, 0, 1, st);
+      launch_copy_block(r, r, D(p.S), R, D(p.Sh), P, P, P, 1.0, st);
+      launch_small_gemm(0, 1, 2 * r, 2 * r, nm, dt, D(p.H), P, 0, D(p.Cg), P, 0, 1.0, D(p.Sh), P,
+                        0, 1, st);
+    }
+    {
+      PhaseTimer t(c, DLRA_PH_TRUNCATE);
+      r = truncate_rotate(r, true, &ctl->kU, &ctl->kV);
+    }
     launch_check_finite(D(p.S), R * R, ctl, st);
     c->r = r;
     c->step = k + 1;
-    (void)N;
   }
 };
 
@@ -825,6 +926,7 @@ int uncollided_raytrace(dlra_ctx *c) {
                               c->at<double>(p.rt_stopw), c->at<double>(p.rt_scratch), psib,
                               c->at<double>(p.dose_u), c->st);
     };
+    PhaseTimer t(c, DLRA_PH_RAYTRACE);
     if (d.tsize == 8) go(c->at<double>(p.psibar));
     else go(c->at<float>(p.psibar));
     HIPCHK(hipGetLastError());
@@ -930,6 +1032,36 @@ int dlra_sync(dlra_ctx *c) {
   if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
   hipError_t e = hipStreamSynchronize(c->st);
   if (e != hipSuccess) return fail(DLRA_E_HIP, hipGetErrorString(e));
+  return DLRA_OK;
+}
+
+int dlra_profile(dlra_ctx *c, int on) {
+  if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
+  try {
+    c->drain();
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  if (on) {
+    for (int i = 0; i < DLRA_PH_COUNT; ++i) {
+      c->prof_ms[i] = 0.0;
+      c->prof_n[i] = 0;
+    }
+  }
+  c->prof = on != 0;
+  return DLRA_OK;
+}
+
+int dlra_profile_read(dlra_ctx *c, int phase, double *total_ms, long long *count) {
+  if (!c || !total_ms || !count) return fail(DLRA_E_INVALID, "null argument");
+  if (phase < 0 || phase >= DLRA_PH_COUNT) return fail(DLRA_E_INVALID, "unknown phase");
+  try {
+    c->drain();
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  *total_ms = c->prof_ms[phase];
+  *count = c->prof_n[phase];
   return DLRA_OK;
 }
 

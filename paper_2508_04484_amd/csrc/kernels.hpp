@@ -49,11 +49,14 @@ void launch_inverse_stop(const GridDev &g, const T *w, int n_mat, const double *
                          Ctl *ctl, hipStream_t st);
 
 // out = K0 + coef * F(W), F(W) = -sum_d [ d^b_d(sW) Bp_d + d^f_d(sW) Bm_d ] (K-step
-// right-hand side); B[(2d+0)] = Bp_d, B[(2d+1)] = Bm_d, each r x r col-major
-// with leading dimension ldb, double.
+// right-hand side), on the matrix cores.  Bp: couplings packed by
+// launch_pack_couplings, Bp[(dk RB + k) RB + j] = B_dk(k, j), RB = 16 ceil(r/16),
+// dk = 2d + {0: +, 1: -}.
 template <typename T>
 void launch_kstep_stage(const GridDev &g, const T *s, const T *W, const T *K0, T *out, int ld,
-                        int r, const double *B, int ldb, double coef, hipStream_t st);
+                        int r, const T *Bp, double coef, hipStream_t st);
+template <typename T>
+void launch_pack_couplings(int ndk, int r, const double *B, int ldb, T *Bp, hipStream_t st);
 
 // partial sums of C[dk](a, c) = sum_x X(x,a) d_dk(sY)(x,c), dk = 2d + {0: b, 1: f};
 // then reduced into C (2*dim blocks, each p x p col-major, ldc).
@@ -102,10 +105,11 @@ void launch_small_gemm(int ta, int tb, int M, int N, int K, double alpha, const 
                        int lda, size_t sA, const double *B, int ldb, size_t sB, double beta,
                        double *C, int ldc, size_t sC, int batch, hipStream_t st);
 
-// out = L0 + coef * F_L(in), F_L(L) = -sum_dk A_dk L C_dk^T (m x r, ld m)
+// out = L0 + coef * F_L(in), F_L(L) = -sum_dk A_dk L C_dk^T (m x r, ld m);
+// T: scratch for the ndk products A_dk in (m x r each, ts apart)
 void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C, int ldc,
                         const double *in, const double *L0, double *out, double coef,
-                        hipStream_t st);
+                        double *T, size_t ts, hipStream_t st);
 
 // Horner RK4 of the S-step on the p x p matrix S (leading dim ld, as Ch, Bh
 // whose dk-th blocks are ld*ld apart), n_sub substeps.

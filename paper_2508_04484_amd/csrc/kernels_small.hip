@@ -54,50 +54,6 @@ __global__ void k_small_gemm(int ta, int tb, int M, int N, int K, double alpha,
   }
 }
 
-// ------------------------------------------------------------------ L-step stage
-constexpr int kLR = 16;   // rows per block
-
-__global__ __launch_bounds__(256) void k_lstep_stage(int m, int r, int ndk,
-                                                    const double *__restrict__ A,
-                                                    const double *__restrict__ C, int ldc,
-                                                    const double *__restrict__ in,
-                                                    const double *__restrict__ L0,
-                                                    double *__restrict__ out, double coef) {
-  __shared__ double Ts[kLR][65];
-  __shared__ double Acc[kLR][65];
-  const int row0 = blockIdx.x * kLR;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kLR * 65; e += 256) (&Acc[0][0])[e] = 0.0;
-  for (int dk = 0; dk < ndk; ++dk) {
-    const double *Ad = A + size_t(dk) * m * m;
-    const double *Cd = C + size_t(dk) * ldc * ldc;
-    __syncthreads();
-    // T(i, k) = sum_q A_dk(row0+i, q) in(q, k)
-    for (int e = tid; e < kLR * r; e += 256) {
-      int i = e % kLR, k = e / kLR;
-      int row = row0 + i;
-      double s = 0.0;
-      if (row < m)
-        for (int q = 0; q < m; ++q) s += Ad[row + size_t(q) * m] * in[q + size_t(k) * m];
-      Ts[i][k] = s;
-    }
-    __syncthreads();
-    // Acc(i, j) += sum_k T(i, k) C_dk(j, k)
-    for (int e = tid; e < kLR * r; e += 256) {
-      int i = e % kLR, j = e / kLR;
-      double s = 0.0;
-      for (int k = 0; k < r; ++k) s += Ts[i][k] * Cd[j + size_t(k) * ldc];
-      Acc[i][j] += s;
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < kLR * r; e += 256) {
-    int i = e % kLR, j = e / kLR;
-    int row = row0 + i;
-    if (row < m) out[row + size_t(j) * m] = L0[row + size_t(j) * m] - coef * Acc[i][j];
-  }
-}
-
 // ------------------------------------------------------------------ block helpers
 __device__ double blk_sum(double v, double *red) {
   const int tid = threadIdx.x;
@@ -254,49 +210,102 @@ __device__ int blk_fill(double *Q, int ldq, int p, int cnt, int need, int ncand,
 }
 
 // ------------------------------------------------------------------ S-step
-__global__ __launch_bounds__(1024) void k_sstep(int P, int ld, int ndk,
-                                               const double *__restrict__ Ch,
-                                               const double *__restrict__ Bh, double *S,
-                                               double *work, double h, int n_sub) {
+// Horner RK4 of dS/dt = -sum_dk C_dk S B_dk on one workgroup: the stage input W
+// and the product T = W B_dk live in LDS (P <= 100, 160 KB), each thread keeps
+// its outputs of S0 and F in registers; C_dk and B_dk are read coalesced.
+constexpr int kSMax = 100;
+constexpr int kSThreads = 1024;
+constexpr int kSPer = (kSMax * kSMax + kSThreads - 1) / kSThreads;
+
+__global__ __launch_bounds__(kSThreads) void k_sstep(int P, int ld, int ndk,
+                                                    const double *__restrict__ Ch,
+                                                    const double *__restrict__ Bh, double *S,
+                                                    double h, int n_sub) {
+  __shared__ double Ws[kSMax * kSMax];
+  __shared__ double Ts[kSMax * kSMax];
   const int PP = P * P;
-  double *S0 = work, *Wm = work + PP, *Tm = work + 2 * PP, *Fm = work + 3 * PP;
+  const int tid = threadIdx.x;
+  double S0[kSPer], F[kSPer];
+#pragma unroll
+  for (int u = 0; u < kSPer; ++u) {
+    int e = tid + u * kSThreads;
+    S0[u] = e < PP ? S[(e % P) + size_t(e / P) * ld] : 0.0;
+  }
   const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
   for (int sub = 0; sub < n_sub; ++sub) {
-    for (int e = threadIdx.x; e < PP; e += blockDim.x) {
-      double v = S[(e % P) + size_t(e / P) * ld];
-      S0[e] = v;
-      Wm[e] = v;
+#pragma unroll
+    for (int u = 0; u < kSPer; ++u) {
+      int e = tid + u * kSThreads;
+      if (e < PP) Ws[e] = S0[u];
     }
     __syncthreads();
     for (int stage = 0; stage < 4; ++stage) {
-      for (int e = threadIdx.x; e < PP; e += blockDim.x) Fm[e] = 0.0;
-      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kSPer; ++u) F[u] = 0.0;
       for (int dk = 0; dk < ndk; ++dk) {
         const double *C = Ch + size_t(dk) * ld * ld;
         const double *B = Bh + size_t(dk) * ld * ld;
-        // T = W B_dk
-        for (int e = threadIdx.x; e < PP; e += blockDim.x) {
-          int i = e % P, j = e / P;
-          double s = 0.0;
-          for (int k = 0; k < P; ++k) s += Wm[i + k * P] * B[k + size_t(j) * ld];
-          Tm[e] = s;
+#pragma unroll
+        for (int u = 0; u < kSPer; ++u) {
+          int e = tid + u * kSThreads;
+          if (e < PP) {
+            int i = e % P, j = e / P;
+            const double *Bj = B + size_t(j) * ld;
+            double acc = 0.0;
+            for (int k = 0; k < P; ++k) acc += Ws[i + k * P] * Bj[k];
+            Ts[e] = acc;
+          }
         }
         __syncthreads();
-        // F -= C_dk T
-        for (int e = threadIdx.x; e < PP; e += blockDim.x) {
-          int i = e % P, j = e / P;
-          double s = 0.0;
-          for (int k = 0; k < P; ++k) s += C[i + size_t(k) * ld] * Tm[k + j * P];
-          Fm[e] -= s;
+#pragma unroll
+        for (int u = 0; u < kSPer; ++u) {
+          int e = tid + u * kSThreads;
+          if (e < PP) {
+            int i = e % P, j = e / P;
+            double acc = 0.0;
+            for (int k = 0; k < P; ++k) acc += C[i + size_t(k) * ld] * Ts[k + j * P];
+            F[u] -= acc;
+          }
         }
         __syncthreads();
       }
-      for (int e = threadIdx.x; e < PP; e += blockDim.x) Wm[e] = S0[e] + cf[stage] * h * Fm[e];
+#pragma unroll
+      for (int u = 0; u < kSPer; ++u) {
+        int e = tid + u * kSThreads;
+        if (e < PP) Ws[e] = S0[u] + cf[stage] * h * F[u];
+      }
       __syncthreads();
     }
-    for (int e = threadIdx.x; e < PP; e += blockDim.x) S[(e % P) + size_t(e / P) * ld] = Wm[e];
+#pragma unroll
+    for (int u = 0; u < kSPer; ++u) {
+      int e = tid + u * kSThreads;
+      if (e < PP) S0[u] = Ws[e];
+    }
     __syncthreads();
   }
+#pragma unroll
+  for (int u = 0; u < kSPer; ++u) {
+    int e = tid + u * kSThreads;
+    if (e < PP) S[(e % P) + size_t(e / P) * ld] = S0[u];
+  }
+}
+
+// L-step stage combine: out = L0 - coef sum_dk T_dk C_dk^T, T_dk = A_dk in
+// (m x r blocks, leading dim m, strided by ts).
+__global__ void k_lstep_combine(int m, int r, int ndk, const double *__restrict__ T, size_t ts,
+                                const double *__restrict__ C, int ldc,
+                                const double *__restrict__ L0, double *__restrict__ out,
+                                double coef) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * r) return;
+  int i = e % m, j = e / m;
+  double acc = 0.0;
+  for (int dk = 0; dk < ndk; ++dk) {
+    const double *Td = T + dk * ts;
+    const double *Cd = C + size_t(dk) * ldc * ldc;
+    for (int k = 0; k < r; ++k) acc += Td[i + size_t(k) * m] * Cd[j + size_t(k) * ldc];
+  }
+  out[i + size_t(j) * m] = L0[i + size_t(j) * m] - coef * acc;
 }
 
 // ------------------------------------------------------------------ Gram orthonormalisation
@@ -631,13 +640,15 @@ void launch_small_gemm(int ta, int tb, int M, int N, int K, double alpha, const 
 
 void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C, int ldc,
                         const double *in, const double *L0, double *out, double coef,
-                        hipStream_t st) {
-  k_lstep_stage<<<(m + kLR - 1) / kLR, 256, 0, st>>>(m, r, ndk, A, C, ldc, in, L0, out, coef);
+                        double *T, size_t ts, hipStream_t st) {
+  launch_small_gemm(0, 0, m, r, m, 1.0, A, m, size_t(m) * m, in, m, 0, 0.0, T, m, ts, ndk, st);
+  k_lstep_combine<<<(m * r + 255) / 256, 256, 0, st>>>(m, r, ndk, T, ts, C, ldc, L0, out, coef);
 }
 
 void launch_sstep(int p, int ld, int ndk, const double *Ch, const double *Bh, double *S,
                   double *work, double h, int n_sub, hipStream_t st) {
-  k_sstep<<<1, 1024, 0, st>>>(p, ld, ndk, Ch, Bh, S, work, h, n_sub);
+  (void)work;
+  k_sstep<<<1, kSThreads, 0, st>>>(p, ld, ndk, Ch, Bh, S, h, n_sub);
 }
 
 __global__ void k_copy_block(int rows, int cols, const double *__restrict__ src, int lds,

@@ -2,6 +2,8 @@
 // Gram reductions and tall-skinny updates (gfx950, wave64).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace dlra {
@@ -54,131 +56,6 @@ __global__ void k_inverse_stop(GridDev g, const T *__restrict__ w, int n_mat,
   s[x] = T(1.0 / st);
 }
 
-// ------------------------------------------------------------------ K-step stage
-constexpr int kTC = 32;   // cells per tile of the reductions
-
-template <typename T, int kTS>
-__global__ __launch_bounds__(kBlock) void k_kstep_stage(GridDev g, const T *__restrict__ s,
-                                                       const T *__restrict__ W,
-                                                       const T *__restrict__ K0,
-                                                       T *__restrict__ out, int ld, int r,
-                                                       const double *__restrict__ B, int ldb,
-                                                       double coef) {
-  extern __shared__ unsigned char smem_raw[];
-  T *D = reinterpret_cast<T *>(smem_raw);        // [kTS][ndk][r]
-  const int ndk = 2 * g.dim;
-  const int x0 = blockIdx.x * kTS;
-  const int tid = threadIdx.x;
-  // phase 1: difference vectors of the tile
-  const int total = kTS * ndk * r;
-  for (int idx = tid; idx < total; idx += kBlock) {
-    int c = idx % kTS;
-    int rest = idx / kTS;
-    int k = rest % r;
-    int dk = rest / r;
-    int x = x0 + c;
-    T v = T(0);
-    if (x < g.n) {
-      int cc[3];
-      cell_coords(g, x, cc);
-      v = stencil_diff(g, s, W + size_t(k) * ld, x, cc, dk >> 1, dk & 1);
-    }
-    D[(c * ndk + dk) * r + k] = v;
-  }
-  __syncthreads();
-  // phase 2: out(x, j) = K0(x, j) - coef * sum_{dk,k} D(x, dk, k) B_dk(k, j)
-  int L = 1;
-  while (L < r) L <<= 1;
-  const int groups = kBlock / L;
-  const int j = tid % L;
-  const int grp = tid / L;
-  if (j >= r || grp >= groups) return;
-  constexpr int kMaxCells = kTS;
-  double acc[kMaxCells];
-  const int ncell = (kTS + groups - 1 - grp) / groups;
-#pragma unroll
-  for (int u = 0; u < kMaxCells; ++u) acc[u] = 0.0;
-  for (int dk = 0; dk < ndk; ++dk) {
-    const double *Bd = B + size_t(dk) * ldb * ldb;
-    for (int k = 0; k < r; ++k) {
-      const double b = Bd[k + size_t(j) * ldb];
-#pragma unroll
-      for (int u = 0; u < kMaxCells; ++u) {
-        if (u < ncell) {
-          int c = grp + u * groups;
-          acc[u] += double(D[(c * ndk + dk) * r + k]) * b;
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kMaxCells; ++u) {
-    if (u < ncell) {
-      int x = x0 + grp + u * groups;
-      if (x < g.n) {
-        size_t o = size_t(j) * ld + x;
-        out[o] = T(double(K0[o]) - coef * acc[u]);
-      }
-    }
-  }
-}
-
-// ------------------------------------------------------------------ reductions
-template <typename Acc, int kMaxOut>
-struct OutAcc {
-  Acc v[kMaxOut];
-};
-
-// Stencil projections: for one dk at a time.
-template <typename T, typename Acc>
-__global__ __launch_bounds__(kBlock) void k_stencil_projection(GridDev g, const T *__restrict__ s,
-                                                              const T *__restrict__ X, int ld,
-                                                              int p, double *__restrict__ partial) {
-  extern __shared__ unsigned char smem_raw[];
-  T *Xs = reinterpret_cast<T *>(smem_raw);   // [kTC][p]
-  T *Ds = Xs + kTC * p;                      // [kTC][p]
-  const int ndk = 2 * g.dim;
-  const int tid = threadIdx.x;
-  const int pp = p * p;
-  const int nout = (pp + kBlock - 1) / kBlock;
-  const int ntile = (g.n + kTC - 1) / kTC;
-  for (int dk = 0; dk < ndk; ++dk) {
-    Acc acc[40];
-    for (int u = 0; u < 40; ++u) acc[u] = Acc(0);
-    for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
-      const int x0 = t * kTC;
-      __syncthreads();
-      for (int idx = tid; idx < kTC * p; idx += kBlock) {
-        int c = idx % kTC, a = idx / kTC;
-        int x = x0 + c;
-        T xv = T(0), dv = T(0);
-        if (x < g.n) {
-          int cc[3];
-          cell_coords(g, x, cc);
-          xv = X[size_t(a) * ld + x];
-          dv = stencil_diff(g, s, X + size_t(a) * ld, x, cc, dk >> 1, dk & 1);
-        }
-        Xs[c * p + a] = xv;
-        Ds[c * p + a] = dv;
-      }
-      __syncthreads();
-      for (int u = 0; u < nout; ++u) {
-        int o = tid + u * kBlock;
-        if (o < pp) {
-          int a = o % p, b = o / p;
-          Acc sum = Acc(0);
-          for (int c = 0; c < kTC; ++c) sum += Acc(Xs[c * p + a]) * Acc(Ds[c * p + b]);
-          acc[u] += sum;
-        }
-      }
-    }
-    for (int u = 0; u < nout; ++u) {
-      int o = tid + u * kBlock;
-      if (o < pp) partial[(size_t(blockIdx.x) * ndk + dk) * pp + o] = double(acc[u]);
-    }
-  }
-}
-
 template <typename T>
 struct YMat {
   const T *Y;
@@ -203,50 +80,174 @@ struct WMatS {
   __device__ T operator()(int x) const { return w[x] * s[x]; }
 };
 
-// G(a, c) = sum_x X(x, a) wt(x) Y(x, c) partial sums
-template <typename T, typename Acc, typename YF, typename WF>
-__global__ __launch_bounds__(kBlock) void k_gram(int n, const T *__restrict__ X, int ldx, int p,
-                                                YF yf, int q, WF wf,
-                                                double *__restrict__ partial) {
-  extern __shared__ unsigned char smem_raw[];
-  T *Xs = reinterpret_cast<T *>(smem_raw);   // [kTC][p]
-  T *Ys = Xs + kTC * p;                      // [kTC][q]
-  const int tid = threadIdx.x;
-  const int pq = p * q;
-  const int nout = (pq + kBlock - 1) / kBlock;
-  const int ntile = (n + kTC - 1) / kTC;
-  Acc acc[40];
-  for (int u = 0; u < 40; ++u) acc[u] = Acc(0);
-  for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
-    const int x0 = t * kTC;
-    __syncthreads();
-    for (int idx = tid; idx < kTC * p; idx += kBlock) {
-      int c = idx % kTC, a = idx / kTC;
-      int x = x0 + c;
-      Xs[c * p + a] = x < n ? T(X[size_t(a) * ldx + x] * wf(x)) : T(0);
-    }
-    for (int idx = tid; idx < kTC * q; idx += kBlock) {
-      int c = idx % kTC, b = idx / kTC;
-      int x = x0 + c;
-      Ys[c * q + b] = x < n ? yf(x, b) : T(0);
-    }
-    __syncthreads();
-    for (int u = 0; u < nout; ++u) {
-      int o = tid + u * kBlock;
-      if (o < pq) {
-        int a = o % p, b = o / p;
-        Acc sum = Acc(0);
-        for (int c = 0; c < kTC; ++c) sum += Acc(Xs[c * p + a]) * Acc(Ys[c * q + b]);
-        acc[u] += sum;
+// ------------------------------------------------------------------ K-step stage
+constexpr int kTC = 32;   // cells per tile of the reductions
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+// Accumulator layouts of the 16x16x4 MFMAs (lane l, register v, column
+// l % 16): row 4 (l / 16) + v for f32, row l / 16 + 4 v for f64.
+template <>
+struct Mfma<float> {
+  using acc_t = f4v;
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<double> {
+  using acc_t = d4v;
+  static __device__ __forceinline__ int row(int q, int v) { return q + 4 * v; }
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// One RK4 stage of the K-step as a dense contraction on the matrix cores:
+//   out(x, j) = K0(x, j) - coef * sum_{dk, k} D_dk(x, k) B_dk(k, j),
+// D_dk = second-order one-sided differences of s o W.  Each wave owns 16
+// consecutive cells and all r <= 16 NJ outputs; the 16x16x4 MFMA takes
+// A(i, kk) = D(cell x0 + i, 4t + kk) from lane i + 16 kk (computed in
+// registers from W and s) and B(kk, j) = Bp(4t + kk, 16 jt + j) from lane
+// j + 16 kk; the accumulator rows follow Mfma<T>::row.
+template <typename T, int NJ>
+__global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restrict__ s,
+                                                    const T *__restrict__ W,
+                                                    const T *__restrict__ K0,
+                                                    T *__restrict__ out, int ld, int r,
+                                                    const T *__restrict__ Bp, double coef) {
+  constexpr int RB = 16 * NJ;
+  using acc_t = typename Mfma<T>::acc_t;
+  const int lane = threadIdx.x & 63;
+  const int x0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (x0 >= g.n) return;
+  const int c = lane & 15, q = lane >> 4;
+  const int x = x0 + c;
+  const bool valid = x < g.n;
+  int cc[3] = {0, 0, 0};
+  if (valid) cell_coords(g, x, cc);
+  acc_t acc[NJ];
+#pragma unroll
+  for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+  const int ksteps = (r + 3) >> 2;
+  const int size[3] = {g.nx, g.ny, g.nz};
+  for (int d = 0; d < g.dim; ++d) {
+    const int st = d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny);
+    const bool m1 = valid && cc[d] >= 1, m2 = valid && cc[d] >= 2;
+    const bool p1 = valid && cc[d] + 1 < size[d], p2 = valid && cc[d] + 2 < size[d];
+    const T s0 = valid ? s[x] : T(0);
+    const T sm1 = m1 ? s[x - st] : T(0), sm2 = m2 ? s[x - 2 * st] : T(0);
+    const T sp1 = p1 ? s[x + st] : T(0), sp2 = p2 ? s[x + 2 * st] : T(0);
+    const T ih = T(g.inv2h[d]);
+    const T *Bb = Bp + size_t(2 * d) * RB * RB;
+    const T *Bf = Bb + size_t(RB) * RB;
+    for (int kq = 0; kq < ksteps; ++kq) {
+      const int k = 4 * kq + q;
+      T db = T(0), df = T(0);
+      if (valid && k < r) {
+        const T *col = W + size_t(k) * ld;
+        const T w0 = s0 * col[x];
+        const T wm1 = m1 ? sm1 * col[x - st] : T(0);
+        const T wm2 = m2 ? sm2 * col[x - 2 * st] : T(0);
+        const T wp1 = p1 ? sp1 * col[x + st] : T(0);
+        const T wp2 = p2 ? sp2 * col[x + 2 * st] : T(0);
+        db = (T(3) * w0 - T(4) * wm1 + wm2) * ih;
+        df = (T(4) * wp1 - T(3) * w0 - wp2) * ih;
+      }
+      const int brow = (4 * kq + q) * RB + c;
+#pragma unroll
+      for (int jt = 0; jt < NJ; ++jt) {
+        acc[jt] = Mfma<T>::op(db, Bb[brow + 16 * jt], acc[jt]);
+        acc[jt] = Mfma<T>::op(df, Bf[brow + 16 * jt], acc[jt]);
       }
     }
   }
-  for (int u = 0; u < nout; ++u) {
-    int o = tid + u * kBlock;
-    if (o < pq) partial[size_t(blockIdx.x) * pq + o] = double(acc[u]);
+#pragma unroll
+  for (int jt = 0; jt < NJ; ++jt) {
+    const int j = 16 * jt + c;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int xi = x0 + Mfma<T>::row(q, v);
+      if (xi < g.n && j < r) {
+        const size_t o = size_t(j) * ld + xi;
+        out[o] = T(double(K0[o]) - coef * double(acc[jt][v]));
+      }
+    }
   }
 }
 
+// Tall-skinny contractions on the matrix cores: per block a chunk of cells,
+// per wave one 16-column tile of the right factor, all 16-row tiles of the
+// left factor; K runs over cells in groups of 4 (lane l holds cell l / 16).
+//   stencil mode (blockIdx.y = dk):  P_dk(a, b) = sum_x X(x, a) d_dk(s o X)(x, b)
+//   gram mode:                       P(a, b) = sum_x X(x, a) wt(x) Y(x, b)
+// Partial sums of block (bx, by) go to partial[(bx * gridDim.y + by) * pq].
+template <typename T, typename Tc, int NA, bool STENCIL, typename YF, typename WF>
+__global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__restrict__ s,
+                                                      const T *__restrict__ X, int ldx, int p,
+                                                      YF yf, int q, WF wf, int chunk,
+                                                      double *__restrict__ partial) {
+  using acc_t = typename Mfma<Tc>::acc_t;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = lane & 15, qq = lane >> 4;
+  const int dk = blockIdx.y;
+  const int b = w * 16 + c;
+  acc_t acc[NA];
+#pragma unroll
+  for (int at = 0; at < NA; ++at) acc[at] = acc_t{0, 0, 0, 0};
+  const int x_begin = blockIdx.x * chunk;
+  const int x_end = min(g.n, x_begin + chunk);
+  for (int xk = x_begin; xk < x_end; xk += 4) {
+    const int x = xk + qq;
+    const bool valid = x < x_end;
+    Tc bv = Tc(0);
+    if (valid && b < q) {
+      if constexpr (STENCIL) {
+        int cc[3];
+        cell_coords(g, x, cc);
+        bv = Tc(stencil_diff(g, s, X + size_t(b) * ldx, x, cc, dk >> 1, dk & 1));
+      } else {
+        bv = Tc(yf(x, b));
+      }
+    }
+    Tc wx = Tc(1);
+    if constexpr (!STENCIL) wx = valid ? Tc(wf(x)) : Tc(0);
+#pragma unroll
+    for (int at = 0; at < NA; ++at) {
+      const int a = at * 16 + c;
+      Tc av = (valid && a < p) ? Tc(X[size_t(a) * ldx + x]) * wx : Tc(0);
+      acc[at] = Mfma<Tc>::op(av, bv, acc[at]);
+    }
+  }
+  const size_t pq = size_t(p) * q;
+  double *out = partial + (size_t(blockIdx.x) * gridDim.y + blockIdx.y) * pq;
+#pragma unroll
+  for (int at = 0; at < NA; ++at) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = at * 16 + Mfma<Tc>::row(qq, v);
+      if (a < p && b < q) out[a + size_t(b) * p] = double(acc[at][v]);
+    }
+  }
+}
+
+// Bp[(dk RB + k) RB + j] = B_dk(k, j) (zero padded to RB), from the
+// column-major double couplings (leading dimension ldb, blocks ldb^2 apart).
+template <typename T>
+__global__ void k_pack_couplings(int ndk, int r, int RB, const double *__restrict__ B, int ldb,
+                                 T *__restrict__ Bp) {
+  int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= ndk * RB * RB) return;
+  int j = e % RB, k = (e / RB) % RB, dk = e / (RB * RB);
+  double v = (k < r && j < r) ? B[size_t(dk) * ldb * ldb + k + size_t(j) * ldb] : 0.0;
+  Bp[e] = T(v);
+}
+
+// ------------------------------------------------------------------ reductions
 __global__ void k_reduce_partials(const double *__restrict__ partial, int nblocks, int elems,
                                   double *__restrict__ out) {
   int e = blockIdx.x * kBlock + threadIdx.x;
@@ -369,12 +370,52 @@ void launch_inverse_stop(const GridDev &g, const T *w, int n_mat, const double *
 }
 
 template <typename T>
+void launch_pack_couplings(int ndk, int r, const double *B, int ldb, T *Bp, hipStream_t st) {
+  const int RB = ((r + 15) / 16) * 16;
+  const int tot = ndk * RB * RB;
+  k_pack_couplings<T><<<(tot + kBlock - 1) / kBlock, kBlock, 0, st>>>(ndk, r, RB, B, ldb, Bp);
+}
+
+template <typename T>
 void launch_kstep_stage(const GridDev &g, const T *s, const T *W, const T *K0, T *out, int ld,
-                        int r, const double *B, int ldb, double coef, hipStream_t st) {
-  constexpr int TS = sizeof(T) == 8 ? 16 : 32;
-  size_t shm = size_t(TS) * 2 * g.dim * r * sizeof(T);
-  k_kstep_stage<T, TS><<<(g.n + TS - 1) / TS, kBlock, shm, st>>>(g, s, W, K0, out, ld, r, B,
-                                                                  ldb, coef);
+                        int r, const T *Bp, double coef, hipStream_t st) {
+  const int blocks = (g.n + 63) / 64;
+  const int nj = (r + 15) / 16;
+  switch (nj) {
+    case 1: k_kstage_mfma<T, 1><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef); break;
+    case 2: k_kstage_mfma<T, 2><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef); break;
+    case 3: k_kstage_mfma<T, 3><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef); break;
+    default: k_kstage_mfma<T, 4><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef); break;
+  }
+}
+
+template <typename T, typename Tc, bool STENCIL, typename YF, typename WF>
+static void contract(const GridDev &g, const T *s, const T *X, int ldx, int p, YF yf, int q,
+                     WF wf, int ny, double *partial, size_t partial_elems, hipStream_t st,
+                     int &nb_out) {
+  const size_t pq = size_t(p) * q;
+  int nb = std::max(1, std::min(kMaxPartialBlocks, (g.n + 255) / 256));
+  // partial sums of nb * ny blocks plus the reduced ny blocks behind them
+  while (nb > 1 && size_t(nb + 1) * ny * pq > partial_elems) nb /= 2;
+  int chunk = (g.n + nb - 1) / nb;
+  chunk = (chunk + 3) / 4 * 4;
+  nb = (g.n + chunk - 1) / chunk;
+  const int na = (p + 15) / 16, nbw = (q + 15) / 16;
+  dim3 grid(nb, ny), block(64 * nbw);
+#define DLRA_CONTRACT(NA)                                                                  \
+  k_contract_mfma<T, Tc, NA, STENCIL, YF, WF><<<grid, block, 0, st>>>(g, s, X, ldx, p, yf, q, \
+                                                                       wf, chunk, partial)
+  switch (na) {
+    case 1: DLRA_CONTRACT(1); break;
+    case 2: DLRA_CONTRACT(2); break;
+    case 3: DLRA_CONTRACT(3); break;
+    case 4: DLRA_CONTRACT(4); break;
+    case 5: DLRA_CONTRACT(5); break;
+    case 6: DLRA_CONTRACT(6); break;
+    default: DLRA_CONTRACT(7); break;
+  }
+#undef DLRA_CONTRACT
+  nb_out = nb;
 }
 
 template <typename T, typename Acc>
@@ -382,12 +423,10 @@ void launch_stencil_projection(const GridDev &g, const T *s, const T *X, int ld,
                                double *C, int ldc, double *partial, size_t partial_elems,
                                hipStream_t st) {
   const int ndk = 2 * g.dim;
-  int nb = partial_blocks(g.n, kTC);
-  size_t per = size_t(ndk) * p * p;
-  if (size_t(nb + 1) * per > partial_elems) nb = int(partial_elems / per) - 1;
-  size_t shm = size_t(2) * kTC * p * sizeof(T);
-  k_stencil_projection<T, Acc><<<nb, kBlock, shm, st>>>(g, s, X, ld, p, partial);
-  // reduce into the first per elements of the partial area's tail
+  int nb = 0;
+  contract<T, Acc, true>(g, s, X, ld, p, YMat<T>{X, ld}, p, WOne<T>{}, ndk, partial,
+                         partial_elems, st, nb);
+  const size_t per = size_t(ndk) * p * p;
   double *red = partial + size_t(nb) * per;
   k_reduce_partials<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, nb, int(per), red);
   k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, p, ndk, C, ldc,
@@ -398,18 +437,16 @@ template <typename T, typename Acc>
 void launch_gram(int n, const T *X, int ldx, int p, const T *Y, int ldy, int q, const T *wmat,
                  const T *s, double *G, int ldg, double *partial, size_t partial_elems,
                  hipStream_t st) {
-  int nb = partial_blocks(n, kTC);
-  size_t per = size_t(p) * q;
-  if (size_t(nb + 1) * per > partial_elems) nb = int(partial_elems / per) - 1;
-  size_t shm = size_t(kTC) * (p + q) * sizeof(T);
-  YMat<T> yf{Y, ldy};
-  if (wmat != nullptr) {
-    k_gram<T, Acc, YMat<T>, WMatS<T>><<<nb, kBlock, shm, st>>>(n, X, ldx, p, yf, q,
-                                                              WMatS<T>{wmat, s}, partial);
-  } else {
-    k_gram<T, Acc, YMat<T>, WOne<T>><<<nb, kBlock, shm, st>>>(n, X, ldx, p, yf, q, WOne<T>{},
-                                                             partial);
-  }
+  GridDev g{};
+  g.n = n;
+  int nb = 0;
+  if (wmat != nullptr)
+    contract<T, Acc, false>(g, s, X, ldx, p, YMat<T>{Y, ldy}, q, WMatS<T>{wmat, s}, 1, partial,
+                            partial_elems, st, nb);
+  else
+    contract<T, Acc, false>(g, s, X, ldx, p, YMat<T>{Y, ldy}, q, WOne<T>{}, 1, partial,
+                            partial_elems, st, nb);
+  const size_t per = size_t(p) * q;
   double *red = partial + size_t(nb) * per;
   k_reduce_partials<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, nb, int(per), red);
   k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, q, 1, G, ldg, 0);
@@ -419,12 +456,12 @@ template <typename T, typename Acc>
 void launch_xt_source(int n, const T *X, int ld, int p, const T *w, int n_mat, const T *psi,
                       double *H, int ldh, double *partial, size_t partial_elems,
                       hipStream_t st) {
-  int nb = partial_blocks(n, kTC);
-  size_t per = size_t(p) * n_mat;
-  if (size_t(nb + 1) * per > partial_elems) nb = int(partial_elems / per) - 1;
-  size_t shm = size_t(kTC) * (p + n_mat) * sizeof(T);
-  k_gram<T, Acc, YSrc<T>, WOne<T>><<<nb, kBlock, shm, st>>>(n, X, ld, p, YSrc<T>{w, psi, n},
-                                                           n_mat, WOne<T>{}, partial);
+  GridDev g{};
+  g.n = n;
+  int nb = 0;
+  contract<T, Acc, false>(g, nullptr, X, ld, p, YSrc<T>{w, psi, n}, n_mat, WOne<T>{}, 1, partial,
+                          partial_elems, st, nb);
+  const size_t per = size_t(p) * n_mat;
   double *red = partial + size_t(nb) * per;
   k_reduce_partials<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, nb, int(per), red);
   k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, n_mat, 1, H, ldh, 0);
@@ -475,7 +512,8 @@ void launch_reduce_partials(const double *partial, int nblocks, int elems, doubl
   template void launch_inverse_stop<T>(const GridDev &, const T *, int, const double *, T *,  \
                                        Ctl *, hipStream_t);                                   \
   template void launch_kstep_stage<T>(const GridDev &, const T *, const T *, const T *, T *,  \
-                                      int, int, const double *, int, double, hipStream_t);    \
+                                      int, int, const T *, double, hipStream_t);              \
+  template void launch_pack_couplings<T>(int, int, const double *, int, T *, hipStream_t);    \
   template void launch_stencil_projection<T, Acc>(const GridDev &, const T *, const T *, int, \
                                                   int, double *, int, double *, size_t,       \
                                                   hipStream_t);                               \
