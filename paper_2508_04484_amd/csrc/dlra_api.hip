@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dlra.h"
+#include "dlra.h"
 #include "kernels.hpp"
 #include "setup.hpp"
 
@@ -203,6 +203,8 @@ struct dlra_ctx {
   dlra_beam beam;
   GridDev gdev;
   hipStream_t st = nullptr;
+  hipStream_t st2 = nullptr;            // side stream of the L-step (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   char *base = nullptr;
   // host-side state
   int r = 0;
@@ -259,6 +261,12 @@ struct dlra_ctx {
     pending.clear();
   }
   ~dlra_ctx() {
+    if (st2) {
+      hipStreamSynchronize(st2);
+      hipStreamDestroy(st2);
+    }
+    if (ev_fork) hipEventDestroy(ev_fork);
+    if (ev_join) hipEventDestroy(ev_join);
     if (!pending.empty() || !pool.empty()) {
       hipStreamSynchronize(st);
       for (auto &r : pending) {
@@ -276,17 +284,19 @@ namespace {
 struct PhaseTimer {
   dlra_ctx *c;
   int ph;
+  hipStream_t s;
   hipEvent_t a = nullptr;
-  PhaseTimer(dlra_ctx *c_, int ph_) : c(c_), ph(ph_) {
+  PhaseTimer(dlra_ctx *c_, int ph_, hipStream_t s_ = nullptr)
+      : c(c_), ph(ph_), s(s_ ? s_ : c_->st) {
     if (c->prof) {
       a = c->event();
-      hipEventRecord(a, c->st);
+      hipEventRecord(a, s);
     }
   }
   ~PhaseTimer() {
     if (a) {
       hipEvent_t b = c->event();
-      hipEventRecord(b, c->st);
+      hipEventRecord(b, s);
       c->pending.push_back({a, b, ph});
     }
   }
@@ -638,11 +648,33 @@ struct Stepper {
       launch_stencil_projection<T, Acc>(c->gdev, s, tall(0), ld, r, D(p.Cm), P, D(p.partial),
                                         p.partial_elems, st);
     }
+    const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};   // Horner coefficients of RK4
+    // L-step: L0 = V S^T, Horner RK4 (m x r), on the side stream: it only
+    // needs V, S and the couplings C, and runs beside the K-step
+    double *Lk = D(p.L0), *La = D(p.La), *Lb = D(p.Lb);
+    HIPCHK(hipEventRecord(c->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(c->st2, c->ev_fork, 0));
+    {
+      hipStream_t s2 = c->st2;
+      PhaseTimer t(c, DLRA_PH_LSTEP, s2);
+      launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, Lk, m, 0, 1, s2);
+      for (int sub = 0; sub < ns; ++sub) {
+        double *in = Lk;
+        double *outs[2] = {La, Lb};
+        for (int stg = 0; stg < 4; ++stg) {
+          double *out = outs[stg & 1];
+          launch_lstep_stage(m, r, dd.ndk, D(p.Apm), D(p.Cm), P, in, Lk, out, cf[stg] * h,
+                             D(p.AV), size_t(m) * P, s2);
+          in = out;
+        }
+        std::swap(Lk, Lb);
+      }
+    }
+    HIPCHK(hipEventRecord(c->ev_join, c->st2));
     // K-step: K0 = U S, Horner RK4
     launch_pack_couplings<T>(dd.ndk, r, D(p.Bm), P, c->at<T>(p.Bpk), st);
     launch_update<T>(n, tall(0), ld, r, D(p.S), R, 1.0, nullptr, 0, 0.0, tall(1), ld, r, nullptr,
                      nullptr, 0, st);
-    const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
     for (int sub = 0; sub < ns; ++sub) {
       T *K0 = tall(1);
       T *in = K0;
@@ -655,23 +687,7 @@ struct Stepper {
       }
       std::swap(c->tall[1], c->tall[3]);
     }
-    // L-step: L0 = V S^T, Horner RK4 (m x r)
-    double *Lk = D(p.L0), *La = D(p.La), *Lb = D(p.Lb);
-    {
-      PhaseTimer t(c, DLRA_PH_LSTEP);
-      launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, Lk, m, 0, 1, st);
-      for (int sub = 0; sub < ns; ++sub) {
-        double *in = Lk;
-        double *outs[2] = {La, Lb};
-        for (int stg = 0; stg < 4; ++stg) {
-          double *out = outs[stg & 1];
-          launch_lstep_stage(m, r, dd.ndk, D(p.Apm), D(p.Cm), P, in, Lk, out, cf[stg] * h,
-                             D(p.AV), size_t(m) * P, st);
-          in = out;
-        }
-        std::swap(Lk, Lb);
-      }
-    }
+    HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
     // augmentation
     {
       PhaseTimer t(c, DLRA_PH_AUGMENT);
@@ -876,6 +892,12 @@ int dlra_init(const dlra_grid *grid, const dlra_materials *mat, const dlra_beam 
   c->opt = *opt;
   c->beam = *beam;
   c->st = reinterpret_cast<hipStream_t>(stream);
+  if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return fail(DLRA_E_HIP, "creating the side stream or its events failed");
+  }
   c->base = reinterpret_cast<char *>(workspace);
   c->gdev.nx = grid->nx;
   c->gdev.ny = grid->ny;

@@ -210,83 +210,51 @@ __device__ int blk_fill(double *Q, int ldq, int p, int cnt, int need, int ncand,
 }
 
 // ------------------------------------------------------------------ S-step
-// Horner RK4 of dS/dt = -sum_dk C_dk S B_dk on one workgroup: the stage input W
-// and the product T = W B_dk live in LDS (P <= 100, 160 KB), each thread keeps
-// its outputs of S0 and F in registers; C_dk and B_dk are read coalesced.
-constexpr int kSMax = 100;
-constexpr int kSThreads = 1024;
-constexpr int kSPer = (kSMax * kSMax + kSThreads - 1) / kSThreads;
+// One RK4 stage (Horner form) of dS/dt = -sum_dk C_dk S B_dk:
+//   out(:, J) = S0(:, J) - coef sum_dk C_dk (W B_dk(:, J))
+// Each workgroup owns the columns J = [j0, j0 + kSJ): it stages the whole
+// stage input W in LDS and needs no other workgroup's result.  out may alias
+// S0 (each workgroup reads S0(:, J) before writing it).
+constexpr int kSJ = 4;
+constexpr int kSMaxOut = 100 * kSJ;   // outputs per S-step workgroup (P <= 100)
 
-__global__ __launch_bounds__(kSThreads) void k_sstep(int P, int ld, int ndk,
+__global__ __launch_bounds__(256) void k_sstep_stage(int P, int ld, int ndk,
                                                     const double *__restrict__ Ch,
-                                                    const double *__restrict__ Bh, double *S,
-                                                    double h, int n_sub) {
-  __shared__ double Ws[kSMax * kSMax];
-  __shared__ double Ts[kSMax * kSMax];
-  const int PP = P * P;
-  const int tid = threadIdx.x;
-  double S0[kSPer], F[kSPer];
-#pragma unroll
-  for (int u = 0; u < kSPer; ++u) {
-    int e = tid + u * kSThreads;
-    S0[u] = e < PP ? S[(e % P) + size_t(e / P) * ld] : 0.0;
-  }
-  const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
-  for (int sub = 0; sub < n_sub; ++sub) {
-#pragma unroll
-    for (int u = 0; u < kSPer; ++u) {
-      int e = tid + u * kSThreads;
-      if (e < PP) Ws[e] = S0[u];
+                                                    const double *__restrict__ Bh,
+                                                    const double *S0, const double *__restrict__ W,
+                                                    double *out, double coef) {
+  extern __shared__ double smem_d[];
+  double *Ws = smem_d;                 // P x P
+  double *Ts = smem_d + P * P;         // P x kSJ
+  const int j0 = blockIdx.x * kSJ;
+  const int nj = min(kSJ, P - j0);
+  for (int e = threadIdx.x; e < P * P; e += blockDim.x) Ws[e] = W[(e % P) + size_t(e / P) * ld];
+  double F[(kSMaxOut + 255) / 256];
+  for (int u = 0; u < (kSMaxOut + 255) / 256; ++u) F[u] = 0.0;
+  __syncthreads();
+  for (int dk = 0; dk < ndk; ++dk) {
+    const double *C = Ch + size_t(dk) * ld * ld;
+    const double *B = Bh + size_t(dk) * ld * ld;
+    for (int e = threadIdx.x; e < P * nj; e += blockDim.x) {
+      int i = e % P, jj = e / P;
+      const double *Bj = B + size_t(j0 + jj) * ld;
+      double acc = 0.0;
+      for (int k = 0; k < P; ++k) acc += Ws[i + k * P] * Bj[k];
+      Ts[i + jj * P] = acc;
     }
     __syncthreads();
-    for (int stage = 0; stage < 4; ++stage) {
-#pragma unroll
-      for (int u = 0; u < kSPer; ++u) F[u] = 0.0;
-      for (int dk = 0; dk < ndk; ++dk) {
-        const double *C = Ch + size_t(dk) * ld * ld;
-        const double *B = Bh + size_t(dk) * ld * ld;
-#pragma unroll
-        for (int u = 0; u < kSPer; ++u) {
-          int e = tid + u * kSThreads;
-          if (e < PP) {
-            int i = e % P, j = e / P;
-            const double *Bj = B + size_t(j) * ld;
-            double acc = 0.0;
-            for (int k = 0; k < P; ++k) acc += Ws[i + k * P] * Bj[k];
-            Ts[e] = acc;
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kSPer; ++u) {
-          int e = tid + u * kSThreads;
-          if (e < PP) {
-            int i = e % P, j = e / P;
-            double acc = 0.0;
-            for (int k = 0; k < P; ++k) acc += C[i + size_t(k) * ld] * Ts[k + j * P];
-            F[u] -= acc;
-          }
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int u = 0; u < kSPer; ++u) {
-        int e = tid + u * kSThreads;
-        if (e < PP) Ws[e] = S0[u] + cf[stage] * h * F[u];
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < kSPer; ++u) {
-      int e = tid + u * kSThreads;
-      if (e < PP) S0[u] = Ws[e];
+    for (int u = 0, e = threadIdx.x; e < P * nj; ++u, e += blockDim.x) {
+      int i = e % P, jj = e / P;
+      double acc = 0.0;
+      for (int k = 0; k < P; ++k) acc += C[i + size_t(k) * ld] * Ts[k + jj * P];
+      F[u] -= acc;
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int u = 0; u < kSPer; ++u) {
-    int e = tid + u * kSThreads;
-    if (e < PP) S[(e % P) + size_t(e / P) * ld] = S0[u];
+  for (int u = 0, e = threadIdx.x; e < P * nj; ++u, e += blockDim.x) {
+    int i = e % P, jj = e / P;
+    size_t o = i + size_t(j0 + jj) * ld;
+    out[o] = S0[o] + coef * F[u];
   }
 }
 
@@ -647,8 +615,22 @@ void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C,
 
 void launch_sstep(int p, int ld, int ndk, const double *Ch, const double *Bh, double *S,
                   double *work, double h, int n_sub, hipStream_t st) {
-  (void)work;
-  k_sstep<<<1, kSThreads, 0, st>>>(p, ld, ndk, Ch, Bh, S, h, n_sub);
+  double *Wa = work, *Wb = work + size_t(ld) * ld;
+  const size_t shm = (size_t(p) * p + size_t(p) * kSJ) * sizeof(double);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sstep_stage),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+  const int blocks = (p + kSJ - 1) / kSJ;
+  const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
+  for (int sub = 0; sub < n_sub; ++sub) {
+    const double *in = S;
+    double *outs[4] = {Wa, Wb, Wa, S};
+    for (int stage = 0; stage < 4; ++stage) {
+      k_sstep_stage<<<blocks, 256, shm, st>>>(p, ld, ndk, Ch, Bh, S, in, outs[stage],
+                                              cf[stage] * h);
+      in = outs[stage];
+    }
+  }
 }
 
 __global__ void k_copy_block(int rows, int cols, const double *__restrict__ src, int lds,

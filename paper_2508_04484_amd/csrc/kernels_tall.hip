@@ -114,17 +114,53 @@ struct Mfma<double> {
 // A(i, kk) = D(cell x0 + i, 4t + kk) from lane i + 16 kk (computed in
 // registers from W and s) and B(kk, j) = Bp(4t + kk, 16 jt + j) from lane
 // j + 16 kk; the accumulator rows follow Mfma<T>::row.
+// Block -> cells map of the stage kernel.  Each block owns 64 cells: 4 waves
+// of 16 consecutive cells.  When nx is a multiple of 16 the 64 cells are a
+// 16 (x) x 4 (y) patch, and blocks are ordered so that (i) the hardware's
+// round-robin of blocks over the 8 XCDs hands every XCD one contiguous range
+// of the logical order and (ii) the logical order sweeps 32 x 32 columns of
+// cells through all z before moving on: the +-2-plane stencil halo of the
+// blocks in flight stays in the XCD's L2.  Otherwise blocks take 64
+// consecutive cells.  Returns the first cell of the calling wave, or -1.
+__device__ __forceinline__ int stage_wave_cell(const GridDev &g, int tiled) {
+  const int wave = threadIdx.x >> 6;
+  const int nblk = gridDim.x;
+  const int b = blockIdx.x;
+  // (i) XCD-contiguous logical block id (a permutation of 0..nblk-1)
+  const int xcd = b & 7, per = nblk >> 3, rem = nblk & 7;
+  const int L = xcd * per + min(xcd, rem) + (b >> 3);
+  if (!tiled) {
+    const int x0 = (L * 4 + wave) * 16;
+    return x0 < g.n ? x0 : -1;
+  }
+  // (ii) tile columns of 2 x 8 patches (32 x 32 cells), z innermost over the column
+  const int px = g.nx >> 4, py = (g.ny + 3) >> 2;
+  const int tpx = min(2, px), tpy = min(8, py);
+  const int ntx = (px + tpx - 1) / tpx;
+  const int per_col = tpx * tpy * g.nz;
+  const int col = L / per_col, rc = L % per_col;
+  const int z = rc / (tpx * tpy), pin = rc % (tpx * tpy);
+  const int tx = col % ntx, ty = col / ntx;
+  const int ix = tx * tpx + pin % tpx, iy = ty * tpy + pin / tpx;
+  if (ix >= px || iy >= py) return -1;
+  const int y = iy * 4 + wave;
+  if (y >= g.ny) return -1;
+  return (z * g.ny + y) * g.nx + ix * 16;
+}
+
 template <typename T, int NJ>
 __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restrict__ s,
                                                     const T *__restrict__ W,
                                                     const T *__restrict__ K0,
                                                     T *__restrict__ out, int ld, int r,
-                                                    const T *__restrict__ Bp, double coef) {
+                                                    const T *__restrict__ Bp, double coef,
+                                                    int tiled) {
   constexpr int RB = 16 * NJ;
+  constexpr int KS = 4 * NJ;       // MFMA k-steps per direction
   using acc_t = typename Mfma<T>::acc_t;
+  const int x0 = stage_wave_cell(g, tiled);
+  if (x0 < 0) return;
   const int lane = threadIdx.x & 63;
-  const int x0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-  if (x0 >= g.n) return;
   const int c = lane & 15, q = lane >> 4;
   const int x = x0 + c;
   const bool valid = x < g.n;
@@ -133,7 +169,6 @@ __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restr
   acc_t acc[NJ];
 #pragma unroll
   for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
-  const int ksteps = (r + 3) >> 2;
   const int size[3] = {g.nx, g.ny, g.nz};
   for (int d = 0; d < g.dim; ++d) {
     const int st = d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny);
@@ -145,9 +180,13 @@ __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restr
     const T ih = T(g.inv2h[d]);
     const T *Bb = Bp + size_t(2 * d) * RB * RB;
     const T *Bf = Bb + size_t(RB) * RB;
-    for (int kq = 0; kq < ksteps; ++kq) {
+    T db[KS], df[KS];
+    // all loads of this direction first (k = 4 kq + q), then the MFMAs
+#pragma unroll
+    for (int kq = 0; kq < KS; ++kq) {
       const int k = 4 * kq + q;
-      T db = T(0), df = T(0);
+      db[kq] = T(0);
+      df[kq] = T(0);
       if (valid && k < r) {
         const T *col = W + size_t(k) * ld;
         const T w0 = s0 * col[x];
@@ -155,14 +194,17 @@ __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restr
         const T wm2 = m2 ? sm2 * col[x - 2 * st] : T(0);
         const T wp1 = p1 ? sp1 * col[x + st] : T(0);
         const T wp2 = p2 ? sp2 * col[x + 2 * st] : T(0);
-        db = (T(3) * w0 - T(4) * wm1 + wm2) * ih;
-        df = (T(4) * wp1 - T(3) * w0 - wp2) * ih;
+        db[kq] = (T(3) * w0 - T(4) * wm1 + wm2) * ih;
+        df[kq] = (T(4) * wp1 - T(3) * w0 - wp2) * ih;
       }
+    }
+#pragma unroll
+    for (int kq = 0; kq < KS; ++kq) {
       const int brow = (4 * kq + q) * RB + c;
 #pragma unroll
       for (int jt = 0; jt < NJ; ++jt) {
-        acc[jt] = Mfma<T>::op(db, Bb[brow + 16 * jt], acc[jt]);
-        acc[jt] = Mfma<T>::op(df, Bf[brow + 16 * jt], acc[jt]);
+        acc[jt] = Mfma<T>::op(db[kq], Bb[brow + 16 * jt], acc[jt]);
+        acc[jt] = Mfma<T>::op(df[kq], Bf[brow + 16 * jt], acc[jt]);
       }
     }
   }
@@ -180,51 +222,79 @@ __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restr
   }
 }
 
-// Tall-skinny contractions on the matrix cores: per block a chunk of cells,
-// per wave one 16-column tile of the right factor, all 16-row tiles of the
-// left factor; K runs over cells in groups of 4 (lane l holds cell l / 16).
+// Tall-skinny contractions on the matrix cores.  Per block a chunk of cells,
+// processed in tiles of 64 cells: the tile of the left factor X (64 x p) and
+// of the right factor (64 x q: differences of s o X in stencil mode, Y times
+// the weights otherwise) are staged in LDS with coalesced loads (consecutive
+// threads read consecutive cells of one column), then each wave (one 16-column
+// tile b of the right factor) runs the 16x16x4 MFMAs over the 16 groups of 4
+// cells for all 16-row tiles a of the left factor.
 //   stencil mode (blockIdx.y = dk):  P_dk(a, b) = sum_x X(x, a) d_dk(s o X)(x, b)
 //   gram mode:                       P(a, b) = sum_x X(x, a) wt(x) Y(x, b)
 // Partial sums of block (bx, by) go to partial[(bx * gridDim.y + by) * pq].
+constexpr int kCT = 64;   // cells per staged tile
+
 template <typename T, typename Tc, int NA, bool STENCIL, typename YF, typename WF>
 __global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__restrict__ s,
                                                       const T *__restrict__ X, int ldx, int p,
                                                       YF yf, int q, WF wf, int chunk,
                                                       double *__restrict__ partial) {
   using acc_t = typename Mfma<Tc>::acc_t;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  extern __shared__ unsigned char smem_raw[];
+  const int pa = 16 * NA + 1;                        // row lengths (odd: no bank conflicts)
+  const int nbw = (q + 15) >> 4;
+  const int pb = 16 * nbw + 1;
+  Tc *Xs = reinterpret_cast<Tc *>(smem_raw);         // [kCT][pa]
+  Tc *Ys = Xs + kCT * pa;                            // [kCT][pb]
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int w = tid >> 6, lane = tid & 63;
   const int c = lane & 15, qq = lane >> 4;
   const int dk = blockIdx.y;
-  const int b = w * 16 + c;
   acc_t acc[NA];
 #pragma unroll
   for (int at = 0; at < NA; ++at) acc[at] = acc_t{0, 0, 0, 0};
   const int x_begin = blockIdx.x * chunk;
   const int x_end = min(g.n, x_begin + chunk);
-  for (int xk = x_begin; xk < x_end; xk += 4) {
-    const int x = xk + qq;
-    const bool valid = x < x_end;
-    Tc bv = Tc(0);
-    if (valid && b < q) {
-      if constexpr (STENCIL) {
-        int cc[3];
-        cell_coords(g, x, cc);
-        bv = Tc(stencil_diff(g, s, X + size_t(b) * ldx, x, cc, dk >> 1, dk & 1));
-      } else {
-        bv = Tc(yf(x, b));
+  for (int x0 = x_begin; x0 < x_end; x0 += kCT) {
+    __syncthreads();
+    for (int e = tid; e < kCT * 16 * NA; e += nthr) {
+      const int cc_ = e % kCT, a = e / kCT;
+      const int x = x0 + cc_;
+      Tc v = Tc(0);
+      if (x < x_end && a < p) {
+        v = Tc(X[size_t(a) * ldx + x]);
+        if constexpr (!STENCIL) v *= Tc(wf(x));
       }
+      Xs[cc_ * pa + a] = v;
     }
-    Tc wx = Tc(1);
-    if constexpr (!STENCIL) wx = valid ? Tc(wf(x)) : Tc(0);
+    for (int e = tid; e < kCT * 16 * nbw; e += nthr) {
+      const int cc_ = e % kCT, b = e / kCT;
+      const int x = x0 + cc_;
+      Tc v = Tc(0);
+      if (x < x_end && b < q) {
+        if constexpr (STENCIL) {
+          int cd[3];
+          cell_coords(g, x, cd);
+          v = Tc(stencil_diff(g, s, X + size_t(b) * ldx, x, cd, dk >> 1, dk & 1));
+        } else {
+          v = Tc(yf(x, b));
+        }
+      }
+      Ys[cc_ * pb + b] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k4 = 0; k4 < kCT / 4; ++k4) {
+      const int cell = 4 * k4 + qq;
+      const Tc bv = Ys[cell * pb + w * 16 + c];
 #pragma unroll
-    for (int at = 0; at < NA; ++at) {
-      const int a = at * 16 + c;
-      Tc av = (valid && a < p) ? Tc(X[size_t(a) * ldx + x]) * wx : Tc(0);
-      acc[at] = Mfma<Tc>::op(av, bv, acc[at]);
+      for (int at = 0; at < NA; ++at)
+        acc[at] = Mfma<Tc>::op(Xs[cell * pa + at * 16 + c], bv, acc[at]);
     }
   }
   const size_t pq = size_t(p) * q;
   double *out = partial + (size_t(blockIdx.x) * gridDim.y + blockIdx.y) * pq;
+  const int b = w * 16 + c;
 #pragma unroll
   for (int at = 0; at < NA; ++at) {
 #pragma unroll
@@ -379,13 +449,22 @@ void launch_pack_couplings(int ndk, int r, const double *B, int ldb, T *Bp, hipS
 template <typename T>
 void launch_kstep_stage(const GridDev &g, const T *s, const T *W, const T *K0, T *out, int ld,
                         int r, const T *Bp, double coef, hipStream_t st) {
-  const int blocks = (g.n + 63) / 64;
+  const int tiled = (g.nx % 16 == 0) ? 1 : 0;
+  int blocks;
+  if (tiled) {
+    const int px = g.nx / 16, py = (g.ny + 3) / 4;
+    const int tpx = std::min(2, px), tpy = std::min(8, py);
+    const int ncol = ((px + tpx - 1) / tpx) * ((py + tpy - 1) / tpy);
+    blocks = ncol * tpx * tpy * g.nz;
+  } else {
+    blocks = (g.n + 63) / 64;
+  }
   const int nj = (r + 15) / 16;
   switch (nj) {
-    case 1: k_kstage_mfma<T, 1><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef); break;
-    case 2: k_kstage_mfma<T, 2><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef); break;
-    case 3: k_kstage_mfma<T, 3><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef); break;
-    default: k_kstage_mfma<T, 4><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef); break;
+    case 1: k_kstage_mfma<T, 1><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef, tiled); break;
+    case 2: k_kstage_mfma<T, 2><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef, tiled); break;
+    case 3: k_kstage_mfma<T, 3><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef, tiled); break;
+    default: k_kstage_mfma<T, 4><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef, tiled); break;
   }
 }
 
@@ -402,9 +481,15 @@ static void contract(const GridDev &g, const T *s, const T *X, int ldx, int p, Y
   nb = (g.n + chunk - 1) / chunk;
   const int na = (p + 15) / 16, nbw = (q + 15) / 16;
   dim3 grid(nb, ny), block(64 * nbw);
+  const size_t shm = size_t(kCT) * (16 * na + 1 + 16 * nbw + 1) * sizeof(Tc);
 #define DLRA_CONTRACT(NA)                                                                  \
-  k_contract_mfma<T, Tc, NA, STENCIL, YF, WF><<<grid, block, 0, st>>>(g, s, X, ldx, p, yf, q, \
-                                                                       wf, chunk, partial)
+  do {                                                                                     \
+    auto kern = k_contract_mfma<T, Tc, NA, STENCIL, YF, WF>;                               \
+    if (shm > 65536)                                                                       \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                       \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));    \
+    kern<<<grid, block, shm, st>>>(g, s, X, ldx, p, yf, q, wf, chunk, partial);            \
+  } while (0)
   switch (na) {
     case 1: DLRA_CONTRACT(1); break;
     case 2: DLRA_CONTRACT(2); break;
