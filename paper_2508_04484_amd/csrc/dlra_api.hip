@@ -39,7 +39,7 @@ struct HipError : std::runtime_error {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxRank = 50;      // 2 r_max <= 100 columns in the small kernels
-constexpr int kPartialBlocks = 240;
+constexpr int kPartialBlocks = 1024;   // partial-sum blocks of a contraction
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -262,18 +262,18 @@ struct dlra_ctx {
   }
   ~dlra_ctx() {
     if (st2) {
-      hipStreamSynchronize(st2);
-      hipStreamDestroy(st2);
+      (void)hipStreamSynchronize(st2);
+      (void)hipStreamDestroy(st2);
     }
-    if (ev_fork) hipEventDestroy(ev_fork);
-    if (ev_join) hipEventDestroy(ev_join);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     if (!pending.empty() || !pool.empty()) {
-      hipStreamSynchronize(st);
+      (void)hipStreamSynchronize(st);
       for (auto &r : pending) {
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
       }
-      for (auto e : pool) hipEventDestroy(e);
+      for (auto e : pool) (void)hipEventDestroy(e);
     }
   }
 };
@@ -290,13 +290,13 @@ struct PhaseTimer {
       : c(c_), ph(ph_), s(s_ ? s_ : c_->st) {
     if (c->prof) {
       a = c->event();
-      hipEventRecord(a, s);
+      (void)hipEventRecord(a, s);
     }
   }
   ~PhaseTimer() {
     if (a) {
       hipEvent_t b = c->event();
-      hipEventRecord(b, s);
+      (void)hipEventRecord(b, s);
       c->pending.push_back({a, b, ph});
     }
   }

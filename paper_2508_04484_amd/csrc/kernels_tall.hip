@@ -11,7 +11,9 @@ namespace dlra {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMaxPartialBlocks = 240;
+constexpr int kMaxPartialBlocks = 1024;   // partial-sum blocks of one contraction
+constexpr int kContractWaves = 8192;      // waves a contraction launch aims for
+constexpr int kSumsqBlocks = 2048;
 
 __device__ __forceinline__ void cell_coords(const GridDev &g, int x, int c[3]) {
   c[0] = x % g.nx;
@@ -22,23 +24,25 @@ __device__ __forceinline__ void cell_coords(const GridDev &g, int x, int c[3]) {
 
 // second-order one-sided difference of v(x) = s(x) W(x, col) along d
 // (zero ghost cells); kind 0: backward (3v_i - 4v_{i-1} + v_{i-2}),
-// kind 1: forward (-3v_i + 4v_{i+1} - v_{i+2}), times 1/(2 Delta_d).
+// kind 1: forward (-3v_i + 4v_{i+1} - v_{i+2}), times 1/(2 Delta_d).  The
+// neighbour loads use clamped indices and are unconditional (a load inside
+// a divergent branch would be followed by a full wait); terms outside the
+// grid are zeroed by a select.
 template <typename T>
 __device__ __forceinline__ T stencil_diff(const GridDev &g, const T *__restrict__ s,
                                           const T *__restrict__ col, int x, const int c[3],
                                           int d, int kind) {
   const int size[3] = {g.nx, g.ny, g.nz};
   const int stride = d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny);
+  const bool ok1 = kind == 0 ? c[d] >= 1 : c[d] + 1 < size[d];
+  const bool ok2 = kind == 0 ? c[d] >= 2 : c[d] + 2 < size[d];
+  const int sg = kind == 0 ? -stride : stride;
+  const int i1 = ok1 ? x + sg : x, i2 = ok2 ? x + 2 * sg : x;
   const T v0 = s[x] * col[x];
-  T v1 = T(0), v2 = T(0);
-  if (kind == 0) {
-    if (c[d] >= 1) v1 = s[x - stride] * col[x - stride];
-    if (c[d] >= 2) v2 = s[x - 2 * stride] * col[x - 2 * stride];
-    return (T(3) * v0 - T(4) * v1 + v2) * T(g.inv2h[d]);
-  }
-  if (c[d] + 1 < size[d]) v1 = s[x + stride] * col[x + stride];
-  if (c[d] + 2 < size[d]) v2 = s[x + 2 * stride] * col[x + 2 * stride];
-  return (T(-3) * v0 + T(4) * v1 - v2) * T(g.inv2h[d]);
+  const T a1 = s[i1] * col[i1], a2 = s[i2] * col[i2];
+  const T v1 = ok1 ? a1 : T(0), v2 = ok2 ? a2 : T(0);
+  const T diff = T(3) * v0 - T(4) * v1 + v2;
+  return (kind == 0 ? diff : -diff) * T(g.inv2h[d]);
 }
 
 // ------------------------------------------------------------------ 1/S
@@ -110,10 +114,11 @@ struct Mfma<double> {
 // One RK4 stage of the K-step as a dense contraction on the matrix cores:
 //   out(x, j) = K0(x, j) - coef * sum_{dk, k} D_dk(x, k) B_dk(k, j),
 // D_dk = second-order one-sided differences of s o W.  Each wave owns 16
-// consecutive cells and all r <= 16 NJ outputs; the 16x16x4 MFMA takes
-// A(i, kk) = D(cell x0 + i, 4t + kk) from lane i + 16 kk (computed in
-// registers from W and s) and B(kk, j) = Bp(4t + kk, 16 jt + j) from lane
-// j + 16 kk; the accumulator rows follow Mfma<T>::row.
+// consecutive cells and all r <= 16 NJ outputs.  The 16x16x4 MFMA computes
+// the transposed tile out^T = B^T D^T: A(j, kk) = Bp(4t + kk, 16 jt + j) from
+// lane j + 16 kk and B(kk, i) = D(cell x0 + i, 4t + kk) from lane i + 16 kk
+// (computed in registers from W and s); accumulator rows (outputs j) follow
+// Mfma<T>::row, columns are the cells.
 // Block -> cells map of the stage kernel.  Each block owns 64 cells: 4 waves
 // of 16 consecutive cells.  When nx is a multiple of 16 the 64 cells are a
 // 16 (x) x 4 (y) patch, and blocks are ordered so that (i) the hardware's
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restr
                                                     const T *__restrict__ Bp, double coef,
                                                     int tiled) {
   constexpr int RB = 16 * NJ;
-  constexpr int KS = 4 * NJ;       // MFMA k-steps per direction
+  constexpr int KU = 4;            // MFMA k-steps whose loads are issued together
   using acc_t = typename Mfma<T>::acc_t;
   const int x0 = stage_wave_cell(g, tiled);
   if (x0 < 0) return;
@@ -164,60 +169,74 @@ __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restr
   const int c = lane & 15, q = lane >> 4;
   const int x = x0 + c;
   const bool valid = x < g.n;
+  // Every load below uses an in-range (clamped) index and is unconditional;
+  // masked terms are zeroed afterwards by their stencil weight or a select.
+  // Loads inside divergent branches would each be followed by a full wait.
+  const int xc = valid ? x : g.n - 1;
   int cc[3] = {0, 0, 0};
-  if (valid) cell_coords(g, x, cc);
+  cell_coords(g, xc, cc);
   acc_t acc[NJ];
 #pragma unroll
   for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
   const int size[3] = {g.nx, g.ny, g.nz};
+  const int ksteps = (r + 3) >> 2;
   for (int d = 0; d < g.dim; ++d) {
     const int st = d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny);
     const bool m1 = valid && cc[d] >= 1, m2 = valid && cc[d] >= 2;
     const bool p1 = valid && cc[d] + 1 < size[d], p2 = valid && cc[d] + 2 < size[d];
-    const T s0 = valid ? s[x] : T(0);
-    const T sm1 = m1 ? s[x - st] : T(0), sm2 = m2 ? s[x - 2 * st] : T(0);
-    const T sp1 = p1 ? s[x + st] : T(0), sp2 = p2 ? s[x + 2 * st] : T(0);
+    const int im1 = m1 ? xc - st : xc, im2 = m2 ? xc - 2 * st : xc;
+    const int ip1 = p1 ? xc + st : xc, ip2 = p2 ? xc + 2 * st : xc;
+    // s at the stencil points, zero outside the grid (zero ghost cells)
+    T s0 = s[xc], sm1 = s[im1], sm2 = s[im2], sp1 = s[ip1], sp2 = s[ip2];
+    s0 = valid ? s0 : T(0);
+    sm1 = m1 ? sm1 : T(0);
+    sm2 = m2 ? sm2 : T(0);
+    sp1 = p1 ? sp1 : T(0);
+    sp2 = p2 ? sp2 : T(0);
     const T ih = T(g.inv2h[d]);
     const T *Bb = Bp + size_t(2 * d) * RB * RB;
     const T *Bf = Bb + size_t(RB) * RB;
-    T db[KS], df[KS];
-    // all loads of this direction first (k = 4 kq + q), then the MFMAs
+    for (int k0 = 0; k0 < ksteps; k0 += KU) {
+      T db[KU], df[KU];
 #pragma unroll
-    for (int kq = 0; kq < KS; ++kq) {
-      const int k = 4 * kq + q;
-      db[kq] = T(0);
-      df[kq] = T(0);
-      if (valid && k < r) {
-        const T *col = W + size_t(k) * ld;
-        const T w0 = s0 * col[x];
-        const T wm1 = m1 ? sm1 * col[x - st] : T(0);
-        const T wm2 = m2 ? sm2 * col[x - 2 * st] : T(0);
-        const T wp1 = p1 ? sp1 * col[x + st] : T(0);
-        const T wp2 = p2 ? sp2 * col[x + 2 * st] : T(0);
-        db[kq] = (T(3) * w0 - T(4) * wm1 + wm2) * ih;
-        df[kq] = (T(4) * wp1 - T(3) * w0 - wp2) * ih;
+      for (int u = 0; u < KU; ++u) {
+        const int k = 4 * (k0 + u) + q;
+        const T *col = W + size_t(min(k, r - 1)) * ld;
+        const T a0 = col[xc], am1 = col[im1], am2 = col[im2], ap1 = col[ip1], ap2 = col[ip2];
+        const T w0 = s0 * a0;
+        const T bk = (T(3) * w0 - T(4) * (sm1 * am1) + sm2 * am2) * ih;
+        const T fk = (T(4) * (sp1 * ap1) - T(3) * w0 - sp2 * ap2) * ih;
+        db[u] = k < r ? bk : T(0);
+        df[u] = k < r ? fk : T(0);
       }
-    }
 #pragma unroll
-    for (int kq = 0; kq < KS; ++kq) {
-      const int brow = (4 * kq + q) * RB + c;
+      for (int u = 0; u < KU; ++u) {
+        if (k0 + u < ksteps) {
+          const int brow = (4 * (k0 + u) + q) * RB + c;
 #pragma unroll
-      for (int jt = 0; jt < NJ; ++jt) {
-        acc[jt] = Mfma<T>::op(db[kq], Bb[brow + 16 * jt], acc[jt]);
-        acc[jt] = Mfma<T>::op(df[kq], Bf[brow + 16 * jt], acc[jt]);
+          for (int jt = 0; jt < NJ; ++jt) {
+            acc[jt] = Mfma<T>::op(Bb[brow + 16 * jt], db[u], acc[jt]);
+            acc[jt] = Mfma<T>::op(Bf[brow + 16 * jt], df[u], acc[jt]);
+          }
+        }
       }
     }
   }
+  // the accumulator holds the transposed tile (rows = outputs j, columns =
+  // cells), so 16 consecutive lanes store 16 consecutive cells of one column
+  T k0v[NJ][4];
+#pragma unroll
+  for (int jt = 0; jt < NJ; ++jt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      k0v[jt][v] = K0[size_t(min(16 * jt + Mfma<T>::row(q, v), r - 1)) * ld + xc];
 #pragma unroll
   for (int jt = 0; jt < NJ; ++jt) {
-    const int j = 16 * jt + c;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int xi = x0 + Mfma<T>::row(q, v);
-      if (xi < g.n && j < r) {
-        const size_t o = size_t(j) * ld + xi;
-        out[o] = T(double(K0[o]) - coef * double(acc[jt][v]));
-      }
+      const int j = 16 * jt + Mfma<T>::row(q, v);
+      if (valid && j < r)
+        out[size_t(j) * ld + x] = T(double(k0v[jt][v]) - coef * double(acc[jt][v]));
     }
   }
 }
@@ -257,30 +276,30 @@ __global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__res
   const int x_end = min(g.n, x_begin + chunk);
   for (int x0 = x_begin; x0 < x_end; x0 += kCT) {
     __syncthreads();
+    // staging: clamped, unconditional loads (see stencil_diff), zeroed by a select
+#pragma unroll 4
     for (int e = tid; e < kCT * 16 * NA; e += nthr) {
       const int cc_ = e % kCT, a = e / kCT;
       const int x = x0 + cc_;
-      Tc v = Tc(0);
-      if (x < x_end && a < p) {
-        v = Tc(X[size_t(a) * ldx + x]);
-        if constexpr (!STENCIL) v *= Tc(wf(x));
-      }
-      Xs[cc_ * pa + a] = v;
+      const int xc = min(x, x_end - 1);
+      Tc v = Tc(X[size_t(min(a, p - 1)) * ldx + xc]);
+      if constexpr (!STENCIL) v *= Tc(wf(xc));
+      Xs[cc_ * pa + a] = (x < x_end && a < p) ? v : Tc(0);
     }
+#pragma unroll 4
     for (int e = tid; e < kCT * 16 * nbw; e += nthr) {
       const int cc_ = e % kCT, b = e / kCT;
       const int x = x0 + cc_;
-      Tc v = Tc(0);
-      if (x < x_end && b < q) {
-        if constexpr (STENCIL) {
-          int cd[3];
-          cell_coords(g, x, cd);
-          v = Tc(stencil_diff(g, s, X + size_t(b) * ldx, x, cd, dk >> 1, dk & 1));
-        } else {
-          v = Tc(yf(x, b));
-        }
+      const int xc = min(x, x_end - 1), bc = min(b, q - 1);
+      Tc v;
+      if constexpr (STENCIL) {
+        int cd[3];
+        cell_coords(g, xc, cd);
+        v = Tc(stencil_diff(g, s, X + size_t(bc) * ldx, xc, cd, dk >> 1, dk & 1));
+      } else {
+        v = Tc(yf(xc, bc));
       }
-      Ys[cc_ * pb + b] = v;
+      Ys[cc_ * pb + b] = (x < x_end && b < q) ? v : Tc(0);
     }
     __syncthreads();
 #pragma unroll 4
@@ -318,13 +337,31 @@ __global__ void k_pack_couplings(int ndk, int r, int RB, const double *__restric
 }
 
 // ------------------------------------------------------------------ reductions
-__global__ void k_reduce_partials(const double *__restrict__ partial, int nblocks, int elems,
-                                  double *__restrict__ out) {
-  int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= elems) return;
+// out[e] = sum_b partial[b * elems + e] in a fixed order: 8 groups of threads
+// take every 8th block for 32 consecutive elements, then group sums combine.
+constexpr int kRedE = 32, kRedG = 8;
+__global__ __launch_bounds__(kRedE * kRedG) void k_reduce_partials(
+    const double *__restrict__ partial, int nblocks, int elems, double *__restrict__ out) {
+  __shared__ double red[kRedG][kRedE];
+  const int el = threadIdx.x % kRedE, grp = threadIdx.x / kRedE;
+  const int e = blockIdx.x * kRedE + el;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[size_t(b) * elems + e];
-  out[e] = s;
+  if (e < elems)
+    for (int b = grp; b < nblocks; b += kRedG) s += partial[size_t(b) * elems + e];
+  red[grp][el] = s;
+  __syncthreads();
+  if (grp == 0 && e < elems) {
+    double t = 0.0;
+    for (int g = 0; g < kRedG; ++g) t += red[g][el];
+    out[e] = t;
+  }
+}
+
+void reduce_partials(const double *partial, int nblocks, int elems, double *out,
+                     hipStream_t st) {
+  if (elems <= 0) return;
+  k_reduce_partials<<<(elems + kRedE - 1) / kRedE, kRedE * kRedG, 0, st>>>(partial, nblocks,
+                                                                         elems, out);
 }
 
 // scatter a reduced p x q block into a col-major matrix with leading dim ldc
@@ -343,6 +380,7 @@ __global__ void k_sumsq(int n, const T *__restrict__ X, int ld, int q, double *p
   __shared__ double red[kBlock];
   double acc = 0.0;
   for (int c = 0; c < q; ++c)
+#pragma unroll 4
     for (int x = blockIdx.x * kBlock + threadIdx.x; x < n; x += gridDim.x * kBlock) {
       double v = double(X[size_t(c) * ld + x]);
       acc += v * v;
@@ -357,62 +395,105 @@ __global__ void k_sumsq(int n, const T *__restrict__ X, int ld, int q, double *p
 }
 
 // ------------------------------------------------------------------ updates
-constexpr int kUC = 64;   // cells per update tile
+// Tall-skinny update on the matrix cores:
+//   Z(x, j) = alpha Y(x, j) + beta sum_a X(x, a) G(a, j) + sum_i src_i(x) sC(j, i),
+// src_i(x) = sdt w_i(x) psi(x) (only when sw != nullptr), and optionally
+// dose(x) += dscale sum_j Z(x, j) dc(j).  The coefficient matrix (beta G with
+// the rows sC^T appended, as T, rows padded to a multiple of 4) is staged in
+// LDS once per block; the waves then take 16-cell tiles and compute the
+// transposed tile Z^T = Gs^T X^T: A(j, kk) = Gs(4t + kk, 16 jt + j) from LDS,
+// B(kk, i) = X(x0 + i, 4t + kk) from lane i + 16 kk, so the stores of 16
+// consecutive lanes are 16 consecutive cells of one column.  Y may alias Z
+// (each element is read and written by the same lane); X must not.
+constexpr int kUpdBlocks = 2048;
+constexpr int kUpdChunk = 8;      // MFMA k-steps whose loads are issued together
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(int n, const T *__restrict__ X, int ldx, int p,
-                                                  const double *__restrict__ G, int ldg,
-                                                  double beta, const T *Y, int ldy,
-                                                  double alpha, T *Z,
-                                                  int ldz, int q, double *__restrict__ dose,
-                                                  const double *__restrict__ dc, double dscale,
-                                                  const T *__restrict__ sw, int n_mat,
-                                                  const T *__restrict__ spsi,
-                                                  const double *__restrict__ sC, int ldsc,
-                                                  double sdt) {
+template <typename T, int NQ>
+__global__ __launch_bounds__(256) void k_update_mfma(
+    int n, const T *__restrict__ X, int ldx, int p, const double *__restrict__ G, int ldg,
+    double beta, const T *Y, int ldy, double alpha, T *Z, int ldz, int q,
+    double *__restrict__ dose, const double *__restrict__ dc, double dscale,
+    const T *__restrict__ sw, int n_mat, const T *__restrict__ spsi,
+    const double *__restrict__ sC, int ldsc, double sdt) {
+  using acc_t = typename Mfma<T>::acc_t;
+  constexpr int QS = 16 * NQ;
   extern __shared__ unsigned char smem_raw[];
-  T *Xs = reinterpret_cast<T *>(smem_raw);   // [kUC][p + 1]
-  __shared__ double dred[kBlock];
-  const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * kUC;
-  const int ps = p + 1;
-  for (int idx = tid; idx < kUC * p; idx += kBlock) {
-    int c = idx % kUC, a = idx / kUC;
-    int x = x0 + c;
-    Xs[c * ps + a] = x < n ? X[size_t(a) * ldx + x] : T(0);
+  const int ne = p + (sw != nullptr ? n_mat : 0);
+  const int nk = (ne + 3) & ~3;
+  T *Gs = reinterpret_cast<T *>(smem_raw);                 // [nk][QS]
+  double *dcs = reinterpret_cast<double *>(Gs + nk * QS);  // [QS]
+  for (int e = threadIdx.x; e < nk * QS; e += blockDim.x) {
+    const int a = e / QS, j = e % QS;
+    double v = 0.0;
+    if (j < q) {
+      if (a < p) v = beta * G[size_t(j) * ldg + a];
+      else if (a < ne) v = sC[j + size_t(a - p) * ldsc];
+    }
+    Gs[e] = T(v);
   }
+  if (dose != nullptr)
+    for (int j = threadIdx.x; j < QS; j += blockDim.x) dcs[j] = j < q ? dc[j] : 0.0;
   __syncthreads();
-  const int c = tid % kUC;
-  const int cg = tid / kUC;
-  const int x = x0 + c;
-  double dsum = 0.0;
-  if (x < n) {
-    double src[kMaxMat];
-    if (sw != nullptr) {
-      double ps_ = double(spsi[x]);
-      for (int i = 0; i < n_mat; ++i) src[i] = sdt * double(sw[size_t(i) * n + x]) * ps_;
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 15, qd = lane >> 4;
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  const int ntiles = (n + 15) >> 4;
+  for (int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < ntiles;
+       tile += waves) {
+    const int x = 16 * tile + c;
+    const bool valid = x < n;
+    const int xc = valid ? x : n - 1;   // clamped: loads stay unconditional
+    const double srcs = sw != nullptr ? sdt * double(spsi[xc]) : 0.0;
+    acc_t acc[NQ];
+#pragma unroll
+    for (int jt = 0; jt < NQ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < nk; k0 += 4 * kUpdChunk) {
+      T b[kUpdChunk];
+#pragma unroll
+      for (int u = 0; u < kUpdChunk; ++u) {
+        const int k = k0 + 4 * u + qd;
+        T v = X[size_t(min(k, p - 1)) * ldx + xc];
+        if (sw != nullptr) {
+          const T sv = T(double(sw[size_t(min(max(k - p, 0), n_mat - 1)) * n + xc]) * srcs);
+          v = k < p ? v : sv;
+        }
+        b[u] = (valid && k < ne) ? v : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kUpdChunk; ++u) {
+        if (k0 + 4 * u < nk) {
+          const T *ga = Gs + (k0 + 4 * u + qd) * QS + c;
+#pragma unroll
+          for (int jt = 0; jt < NQ; ++jt) acc[jt] = Mfma<T>::op(ga[16 * jt], b[u], acc[jt]);
+        }
+      }
     }
-    for (int col = cg; col < q; col += kBlock / kUC) {
-      double acc = 0.0;
-      if (Y != nullptr && alpha != 0.0) acc = alpha * double(Y[size_t(col) * ldy + x]);
-      const double *Gc = G + size_t(col) * ldg;
-      double xg = 0.0;
-      for (int a = 0; a < p; ++a) xg += double(Xs[c * ps + a]) * Gc[a];
-      acc += beta * xg;
-      if (sw != nullptr)
-        for (int i = 0; i < n_mat; ++i) acc += src[i] * sC[col + size_t(i) * ldsc];
-      T zv = T(acc);
-      Z[size_t(col) * ldz + x] = zv;
-      if (dose != nullptr) dsum += double(zv) * dc[col];
+    double yv[NQ][4];
+#pragma unroll
+    for (int jt = 0; jt < NQ; ++jt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        yv[jt][v] = (Y != nullptr && alpha != 0.0)
+                        ? alpha * double(Y[size_t(min(16 * jt + Mfma<T>::row(qd, v), q - 1)) *
+                                               ldy + xc])
+                        : 0.0;
+    double dsum = 0.0;
+#pragma unroll
+    for (int jt = 0; jt < NQ; ++jt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * jt + Mfma<T>::row(qd, v);
+        if (valid && j < q) {
+          const T zv = T(double(acc[jt][v]) + yv[jt][v]);
+          Z[size_t(j) * ldz + x] = zv;
+          if (dose != nullptr) dsum += double(zv) * dcs[j];
+        }
+      }
     }
-  }
-  if (dose != nullptr) {
-    dred[tid] = dsum;
-    __syncthreads();
-    if (cg == 0 && x < n) {
-      double tot = 0.0;
-      for (int u = 0; u < kBlock / kUC; ++u) tot += dred[c + u * kUC];
-      dose[x] += dscale * tot;
+    if (dose != nullptr) {
+      dsum += __shfl_xor(dsum, 16);
+      dsum += __shfl_xor(dsum, 32);
+      if (qd == 0 && valid) dose[x] += dscale * dsum;
     }
   }
 }
@@ -424,10 +505,6 @@ __global__ void k_zero_cols(int n, T *X, int ld, int c0, int c1) {
   for (int c = c0; c < c1; ++c) X[size_t(c) * ld + x] = T(0);
 }
 
-int partial_blocks(int n, int tile) {
-  int nt = (n + tile - 1) / tile;
-  return nt < kMaxPartialBlocks ? nt : kMaxPartialBlocks;
-}
 
 }  // namespace
 
@@ -473,13 +550,14 @@ static void contract(const GridDev &g, const T *s, const T *X, int ldx, int p, Y
                      WF wf, int ny, double *partial, size_t partial_elems, hipStream_t st,
                      int &nb_out) {
   const size_t pq = size_t(p) * q;
-  int nb = std::max(1, std::min(kMaxPartialBlocks, (g.n + 255) / 256));
+  const int na = (p + 15) / 16, nbw = (q + 15) / 16;
+  int nb = (kContractWaves + ny * nbw - 1) / (ny * nbw);
+  nb = std::max(1, std::min({nb, kMaxPartialBlocks, (g.n + kCT - 1) / kCT}));
   // partial sums of nb * ny blocks plus the reduced ny blocks behind them
   while (nb > 1 && size_t(nb + 1) * ny * pq > partial_elems) nb /= 2;
   int chunk = (g.n + nb - 1) / nb;
   chunk = (chunk + 3) / 4 * 4;
   nb = (g.n + chunk - 1) / chunk;
-  const int na = (p + 15) / 16, nbw = (q + 15) / 16;
   dim3 grid(nb, ny), block(64 * nbw);
   const size_t shm = size_t(kCT) * (16 * na + 1 + 16 * nbw + 1) * sizeof(Tc);
 #define DLRA_CONTRACT(NA)                                                                  \
@@ -513,7 +591,7 @@ void launch_stencil_projection(const GridDev &g, const T *s, const T *X, int ld,
                          partial_elems, st, nb);
   const size_t per = size_t(ndk) * p * p;
   double *red = partial + size_t(nb) * per;
-  k_reduce_partials<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, nb, int(per), red);
+  reduce_partials(partial, nb, int(per), red, st);
   k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, p, ndk, C, ldc,
                                                             size_t(ldc) * ldc);
 }
@@ -533,7 +611,7 @@ void launch_gram(int n, const T *X, int ldx, int p, const T *Y, int ldy, int q, 
                             partial_elems, st, nb);
   const size_t per = size_t(p) * q;
   double *red = partial + size_t(nb) * per;
-  k_reduce_partials<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, nb, int(per), red);
+  reduce_partials(partial, nb, int(per), red, st);
   k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, q, 1, G, ldg, 0);
 }
 
@@ -548,37 +626,62 @@ void launch_xt_source(int n, const T *X, int ld, int p, const T *w, int n_mat, c
                           partial_elems, st, nb);
   const size_t per = size_t(p) * n_mat;
   double *red = partial + size_t(nb) * per;
-  k_reduce_partials<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, nb, int(per), red);
+  reduce_partials(partial, nb, int(per), red, st);
   k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, n_mat, 1, H, ldh, 0);
 }
 
 template <typename T>
 void launch_sumsq(int n, const T *X, int ld, int q, double *out, double *partial,
                   size_t partial_elems, hipStream_t st) {
-  int nb = partial_blocks(n, kBlock);
+  int nb = std::min((n + kBlock - 1) / kBlock, kSumsqBlocks);
   if (size_t(nb) > partial_elems) nb = int(partial_elems);
   k_sumsq<T><<<nb, kBlock, 0, st>>>(n, X, ld, q, partial);
-  k_reduce_partials<<<1, kBlock, 0, st>>>(partial, nb, 1, out);
+  reduce_partials(partial, nb, 1, out, st);
+}
+
+template <typename T>
+static void update(int n, const T *X, int ldx, int p, const double *G, int ldg, double beta,
+                   const T *Y, int ldy, double alpha, T *Z, int ldz, int q, double *dose,
+                   const double *dc, double dscale, const T *sw, int n_mat, const T *spsi,
+                   const double *sC, int ldsc, double sdt, hipStream_t st) {
+  if (n <= 0 || q <= 0) return;
+  const int nq = (q + 15) / 16;   // q <= 64: ranks are capped at 50
+  const int ne = p + (sw != nullptr ? n_mat : 0);
+  const int nk = (ne + 3) & ~3;
+  const size_t shm = size_t(nk) * 16 * nq * sizeof(T) + size_t(16) * nq * sizeof(double);
+  const int blocks = std::max(1, std::min(kUpdBlocks, (n + 63) / 64));
+#define DLRA_UPDATE(NQ)                                                                     \
+  do {                                                                                      \
+    auto kern = k_update_mfma<T, NQ>;                                                       \
+    if (shm > 65536)                                                                        \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                        \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));     \
+    kern<<<blocks, 256, shm, st>>>(n, X, ldx, p, G, ldg, beta, Y, ldy, alpha, Z, ldz, q,    \
+                                   dose, dc, dscale, sw, n_mat, spsi, sC, ldsc, sdt);       \
+  } while (0)
+  switch (nq) {
+    case 1: DLRA_UPDATE(1); break;
+    case 2: DLRA_UPDATE(2); break;
+    case 3: DLRA_UPDATE(3); break;
+    default: DLRA_UPDATE(4); break;
+  }
+#undef DLRA_UPDATE
 }
 
 template <typename T>
 void launch_update(int n, const T *X, int ldx, int p, const double *G, int ldg, double beta,
                    const T *Y, int ldy, double alpha, T *Z, int ldz, int q, double *dose,
                    const double *dc, double dscale, hipStream_t st) {
-  size_t shm = size_t(kUC) * (p + 1) * sizeof(T);
-  k_update<T><<<(n + kUC - 1) / kUC, kBlock, shm, st>>>(n, X, ldx, p, G, ldg, beta, Y, ldy,
-                                                        alpha, Z, ldz, q, dose, dc, dscale,
-                                                        nullptr, 0, nullptr, nullptr, 0, 0.0);
+  update<T>(n, X, ldx, p, G, ldg, beta, Y, ldy, alpha, Z, ldz, q, dose, dc, dscale, nullptr, 0,
+            nullptr, nullptr, 0, 0.0, st);
 }
 
 template <typename T>
 void launch_source_k(int n, const T *U, int ld, int r, const double *St, int lds, const T *w,
                      int n_mat, const T *psi, const double *Cg, int ldcg, double dt, T *K,
                      hipStream_t st) {
-  size_t shm = size_t(kUC) * (r + 1) * sizeof(T);
-  k_update<T><<<(n + kUC - 1) / kUC, kBlock, shm, st>>>(n, U, ld, r, St, lds, 1.0, nullptr, 0,
-                                                        0.0, K, ld, r, nullptr, nullptr, 0.0, w,
-                                                        n_mat, psi, Cg, ldcg, dt);
+  update<T>(n, U, ld, r, St, lds, 1.0, nullptr, 0, 0.0, K, ld, r, nullptr, nullptr, 0.0, w,
+            n_mat, psi, Cg, ldcg, dt, st);
 }
 
 template <typename T>
@@ -589,8 +692,7 @@ void launch_zero_cols(int n, T *X, int ld, int c0, int c1, hipStream_t st) {
 
 void launch_reduce_partials(const double *partial, int nblocks, int elems, double *out,
                             hipStream_t st) {
-  k_reduce_partials<<<(elems + kBlock - 1) / kBlock, kBlock, 0, st>>>(partial, nblocks, elems,
-                                                                      out);
+  reduce_partials(partial, nblocks, elems, out, st);
 }
 
 #define DLRA_INSTANTIATE(T, Acc)                                                              \
