@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "kernels.hpp"
 
@@ -119,26 +120,17 @@ struct Mfma<double> {
 // lane j + 16 kk and B(kk, i) = D(cell x0 + i, 4t + kk) from lane i + 16 kk
 // (computed in registers from W and s); accumulator rows (outputs j) follow
 // Mfma<T>::row, columns are the cells.
-// Block -> cells map of the stage kernel.  Each block owns 64 cells: 4 waves
-// of 16 consecutive cells.  When nx is a multiple of 16 the 64 cells are a
-// 16 (x) x 4 (y) patch, and blocks are ordered so that (i) the hardware's
-// round-robin of blocks over the 8 XCDs hands every XCD one contiguous range
-// of the logical order and (ii) the logical order sweeps 32 x 32 columns of
-// cells through all z before moving on: the +-2-plane stencil halo of the
-// blocks in flight stays in the XCD's L2.  Otherwise blocks take 64
-// consecutive cells.  Returns the first cell of the calling wave, or -1.
-__device__ __forceinline__ int stage_wave_cell(const GridDev &g, int tiled) {
-  const int wave = threadIdx.x >> 6;
-  const int nblk = gridDim.x;
-  const int b = blockIdx.x;
-  // (i) XCD-contiguous logical block id (a permutation of 0..nblk-1)
-  const int xcd = b & 7, per = nblk >> 3, rem = nblk & 7;
-  const int L = xcd * per + min(xcd, rem) + (b >> 3);
+// Tile -> cells map of the stage kernel.  A tile is 64 cells: 4 waves of 16
+// consecutive cells.  When nx is a multiple of 16 the 64 cells are a 16 (x) x
+// 4 (y) patch and the tile order sweeps columns of 32 x 32 cells through all
+// z before moving on, so the +-2-plane stencil halo of the tiles in flight
+// stays in L2.  Otherwise tiles are 64 consecutive cells.  Returns the first
+// cell of wave `wave` of tile L, or -1.
+__device__ __forceinline__ int tile_wave_cell(const GridDev &g, int L, int wave, int tiled) {
   if (!tiled) {
     const int x0 = (L * 4 + wave) * 16;
     return x0 < g.n ? x0 : -1;
   }
-  // (ii) tile columns of 2 x 8 patches (32 x 32 cells), z innermost over the column
   const int px = g.nx >> 4, py = (g.ny + 3) >> 2;
   const int tpx = min(2, px), tpy = min(8, py);
   const int ntx = (px + tpx - 1) / tpx;
@@ -153,91 +145,324 @@ __device__ __forceinline__ int stage_wave_cell(const GridDev &g, int tiled) {
   return (z * g.ny + y) * g.nx + ix * 16;
 }
 
-template <typename T, int NJ>
+// Persistent launch: gridDim.x is a multiple of 8, the hardware hands block b
+// to XCD b % 8, and XCD i's blocks walk the i-th eighth of the tile order
+// together (block b takes tiles lo + b / 8, lo + b / 8 + gridDim.x / 8, ...),
+// so the tiles in flight on one XCD are neighbours and share its L2.  The
+// couplings are staged in LDS once per block when BLDS.
+template <typename T, int NJ, bool BLDS>
 __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restrict__ s,
                                                     const T *__restrict__ W,
                                                     const T *__restrict__ K0,
                                                     T *__restrict__ out, int ld, int r,
                                                     const T *__restrict__ Bp, double coef,
-                                                    int tiled) {
+                                                    int tiled, int ntiles) {
   constexpr int RB = 16 * NJ;
-  constexpr int KU = 4;            // MFMA k-steps whose loads are issued together
+  constexpr int KS = 4 * NJ;           // MFMA k-steps per difference operator
+  constexpr int KU = KS < 8 ? KS : 8;  // k-steps whose loads are issued together
   using acc_t = typename Mfma<T>::acc_t;
-  const int x0 = stage_wave_cell(g, tiled);
-  if (x0 < 0) return;
-  const int lane = threadIdx.x & 63;
+  extern __shared__ unsigned char smem_raw[];
+  T *Bs = reinterpret_cast<T *>(smem_raw);
+  if constexpr (BLDS) {
+    const int nbk = 2 * g.dim * RB * RB;
+    for (int e = threadIdx.x; e < nbk; e += blockDim.x) Bs[e] = Bp[e];
+    __syncthreads();
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = lane & 15, q = lane >> 4;
-  const int x = x0 + c;
-  const bool valid = x < g.n;
-  // Every load below uses an in-range (clamped) index and is unconditional;
-  // masked terms are zeroed afterwards by their stencil weight or a select.
-  // Loads inside divergent branches would each be followed by a full wait.
-  const int xc = valid ? x : g.n - 1;
-  int cc[3] = {0, 0, 0};
-  cell_coords(g, xc, cc);
-  acc_t acc[NJ];
-#pragma unroll
-  for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+  const int xcd = blockIdx.x & 7, nper = gridDim.x >> 3;
+  const int lo = int((long long)xcd * ntiles / 8), hi = int((long long)(xcd + 1) * ntiles / 8);
   const int size[3] = {g.nx, g.ny, g.nz};
   const int ksteps = (r + 3) >> 2;
-  for (int d = 0; d < g.dim; ++d) {
-    const int st = d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny);
-    const bool m1 = valid && cc[d] >= 1, m2 = valid && cc[d] >= 2;
-    const bool p1 = valid && cc[d] + 1 < size[d], p2 = valid && cc[d] + 2 < size[d];
-    const int im1 = m1 ? xc - st : xc, im2 = m2 ? xc - 2 * st : xc;
-    const int ip1 = p1 ? xc + st : xc, ip2 = p2 ? xc + 2 * st : xc;
-    // s at the stencil points, zero outside the grid (zero ghost cells)
-    T s0 = s[xc], sm1 = s[im1], sm2 = s[im2], sp1 = s[ip1], sp2 = s[ip2];
-    s0 = valid ? s0 : T(0);
-    sm1 = m1 ? sm1 : T(0);
-    sm2 = m2 ? sm2 : T(0);
-    sp1 = p1 ? sp1 : T(0);
-    sp2 = p2 ? sp2 : T(0);
-    const T ih = T(g.inv2h[d]);
-    const T *Bb = Bp + size_t(2 * d) * RB * RB;
-    const T *Bf = Bb + size_t(RB) * RB;
-    for (int k0 = 0; k0 < ksteps; k0 += KU) {
-      T db[KU], df[KU];
+  for (int L = lo + (blockIdx.x >> 3); L < hi; L += nper) {
+    const int x0 = tile_wave_cell(g, L, wave, tiled);
+    if (x0 < 0) continue;
+    const int x = x0 + c;
+    const bool valid = x < g.n;
+    // Every load below uses an in-range (clamped) index and is unconditional;
+    // masked terms are zeroed by their stencil weight or a select.  A load
+    // inside a divergent branch would be followed by a full wait.
+    const int xc = valid ? x : g.n - 1;
+    int cc[3] = {0, 0, 0};
+    cell_coords(g, xc, cc);
+    acc_t acc[NJ];
 #pragma unroll
-      for (int u = 0; u < KU; ++u) {
-        const int k = 4 * (k0 + u) + q;
-        const T *col = W + size_t(min(k, r - 1)) * ld;
-        const T a0 = col[xc], am1 = col[im1], am2 = col[im2], ap1 = col[ip1], ap2 = col[ip2];
-        const T w0 = s0 * a0;
-        const T bk = (T(3) * w0 - T(4) * (sm1 * am1) + sm2 * am2) * ih;
-        const T fk = (T(4) * (sp1 * ap1) - T(3) * w0 - sp2 * ap2) * ih;
-        db[u] = k < r ? bk : T(0);
-        df[u] = k < r ? fk : T(0);
-      }
+    for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+    for (int d = 0; d < g.dim; ++d) {
+      const int st = d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny);
+      const bool m1 = valid && cc[d] >= 1, m2 = valid && cc[d] >= 2;
+      const bool p1 = valid && cc[d] + 1 < size[d], p2 = valid && cc[d] + 2 < size[d];
+      const int im1 = m1 ? xc - st : xc, im2 = m2 ? xc - 2 * st : xc;
+      const int ip1 = p1 ? xc + st : xc, ip2 = p2 ? xc + 2 * st : xc;
+      // s at the stencil points, zero outside the grid (zero ghost cells)
+      T s0 = s[xc], sm1 = s[im1], sm2 = s[im2], sp1 = s[ip1], sp2 = s[ip2];
+      s0 = valid ? s0 : T(0);
+      sm1 = m1 ? sm1 : T(0);
+      sm2 = m2 ? sm2 : T(0);
+      sp1 = p1 ? sp1 : T(0);
+      sp2 = p2 ? sp2 : T(0);
+      const T ih = T(g.inv2h[d]);
+      const int ob = 2 * d * RB * RB, of = ob + RB * RB;
+      for (int k0 = 0; k0 < ksteps; k0 += KU) {
+        T db[KU], df[KU];
 #pragma unroll
-      for (int u = 0; u < KU; ++u) {
-        if (k0 + u < ksteps) {
-          const int brow = (4 * (k0 + u) + q) * RB + c;
+        for (int u = 0; u < KU; ++u) {
+          const int k = 4 * (k0 + u) + q;
+          const T *col = W + size_t(min(k, r - 1)) * ld;
+          const T a0 = col[xc], am1 = col[im1], am2 = col[im2], ap1 = col[ip1],
+                  ap2 = col[ip2];
+          const T w0 = s0 * a0;
+          const T bk = (T(3) * w0 - T(4) * (sm1 * am1) + sm2 * am2) * ih;
+          const T fk = (T(4) * (sp1 * ap1) - T(3) * w0 - sp2 * ap2) * ih;
+          db[u] = k < r ? bk : T(0);
+          df[u] = k < r ? fk : T(0);
+        }
 #pragma unroll
-          for (int jt = 0; jt < NJ; ++jt) {
-            acc[jt] = Mfma<T>::op(Bb[brow + 16 * jt], db[u], acc[jt]);
-            acc[jt] = Mfma<T>::op(Bf[brow + 16 * jt], df[u], acc[jt]);
+        for (int u = 0; u < KU; ++u) {
+          if (k0 + u < ksteps) {
+            const int brow = (4 * (k0 + u) + q) * RB + c;
+#pragma unroll
+            for (int jt = 0; jt < NJ; ++jt) {
+              T bb, bf;
+              if constexpr (BLDS) {
+                bb = Bs[ob + brow + 16 * jt];
+                bf = Bs[of + brow + 16 * jt];
+              } else {
+                bb = Bp[ob + brow + 16 * jt];
+                bf = Bp[of + brow + 16 * jt];
+              }
+              acc[jt] = Mfma<T>::op(bb, db[u], acc[jt]);
+              acc[jt] = Mfma<T>::op(bf, df[u], acc[jt]);
+            }
           }
         }
       }
     }
-  }
-  // the accumulator holds the transposed tile (rows = outputs j, columns =
-  // cells), so 16 consecutive lanes store 16 consecutive cells of one column
-  T k0v[NJ][4];
+    // the accumulator holds the transposed tile (rows = outputs j, columns =
+    // cells), so 16 consecutive lanes store 16 consecutive cells of one column
+    T k0v[NJ][4];
 #pragma unroll
-  for (int jt = 0; jt < NJ; ++jt)
+    for (int jt = 0; jt < NJ; ++jt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      k0v[jt][v] = K0[size_t(min(16 * jt + Mfma<T>::row(q, v), r - 1)) * ld + xc];
+      for (int v = 0; v < 4; ++v)
+        k0v[jt][v] = K0[size_t(min(16 * jt + Mfma<T>::row(q, v), r - 1)) * ld + xc];
 #pragma unroll
-  for (int jt = 0; jt < NJ; ++jt) {
+    for (int jt = 0; jt < NJ; ++jt) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = 16 * jt + Mfma<T>::row(q, v);
-      if (valid && j < r)
-        out[size_t(j) * ld + x] = T(double(k0v[jt][v]) - coef * double(acc[jt][v]));
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * jt + Mfma<T>::row(q, v);
+        if (valid && j < r)
+          out[size_t(j) * ld + x] = T(double(k0v[jt][v]) - coef * double(acc[jt][v]));
+      }
     }
+  }
+}
+
+// K-step stage with an LDS z-march (r <= 32).  A block owns a brick column of
+// 16 (x) x 4 (y) cells and a chunk of z planes and marches through z.  The
+// LDS holds a ring of five planes of v = s o W (planes z-2..z+2, each row with
+// a 2-cell x halo) and the 2-row y halo of the centre plane, all zero outside
+// the grid (zero ghost cells), so every difference operand comes from LDS and
+// every input value is read from L2 about twice instead of once per stencil
+// use.  Wave w computes row w of the centre plane as in k_kstage_mfma (the
+// transposed tile out^T = B^T D^T on 16x16x4 MFMAs, couplings held in
+// registers), while the loads of plane z+3 and of the next y halo are in
+// flight; they are written to LDS between two barriers after the MFMAs.
+constexpr bool kUseBrick = false;            // z-march stage kernel (else the global-load one)
+constexpr int kBrickBY = 4;                  // rows per brick = waves per block
+constexpr int kBrickRW = 16 + 4;             // row width with the x halo
+constexpr int kBrickPC = kBrickBY * kBrickRW;                  // cells per ring plane
+constexpr int kBrickPCP = kBrickPC + (48 - kBrickPC % 32) % 32;  // = 16 mod 32: no bank conflicts
+constexpr int kBrickHC = 4 * 16;                               // y-halo cells
+constexpr int kBrickHCP = kBrickHC + (48 - kBrickHC % 32) % 32;
+
+__host__ __device__ constexpr size_t brick_lds_bytes(int rb, int tsize) {
+  return size_t(rb) * (5 * kBrickPCP + kBrickHCP) * tsize;
+}
+
+template <typename T, int NJ, int DIM>
+__global__ __launch_bounds__(256) void k_kstage_brick(GridDev g, const T *__restrict__ s,
+                                                     const T *__restrict__ W,
+                                                     const T *__restrict__ K0,
+                                                     T *__restrict__ out, int ld, int r,
+                                                     const T *__restrict__ Bp, double coef,
+                                                     int nby, int nzc, int zchunk) {
+  constexpr int RB = 16 * NJ, KS = 4 * NJ;
+  constexpr int RW = kBrickRW, PC = kBrickPC, PCP = kBrickPCP, HC = kBrickHC, HCP = kBrickHCP;
+  constexpr int NPL = (RB * PC + 255) / 256;   // ring-plane elements per thread
+  constexpr int NHL = (RB * HC + 255) / 256;   // y-halo elements per thread
+  using acc_t = typename Mfma<T>::acc_t;
+  extern __shared__ unsigned char smem_raw[];
+  T *ring = reinterpret_cast<T *>(smem_raw);   // [5][RB][PCP]
+  T *halo = ring + 5 * RB * PCP;               // [RB][HCP]
+  // block -> (brick column, z chunk); the hardware's round-robin of blocks
+  // over the 8 XCDs gets one contiguous range of this order per XCD
+  const int nblk = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, per = nblk >> 3, rem = nblk & 7;
+  const int L = xcd * per + min(xcd, rem) + (b >> 3);
+  const int zc = L % nzc, col = L / nzc;
+  const int by = col % nby, bx = col / nby;
+  const int gx0 = 16 * bx, gy0 = kBrickBY * by;
+  const int z0 = zc * zchunk, z1 = min(g.nz, z0 + zchunk);
+  if (z0 >= z1) return;
+  const int tid = threadIdx.x, row = tid >> 6, lane = tid & 63;
+  const int c = lane & 15, q = lane >> 4;
+  const int nx = g.nx, ny = g.ny;
+  // couplings: A operands of all MFMAs of this lane
+  T bq[DIM][KS][NJ][2];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+#pragma unroll
+    for (int kq = 0; kq < KS; ++kq)
+#pragma unroll
+      for (int jt = 0; jt < NJ; ++jt)
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+          bq[d][kq][jt][f] = Bp[size_t(2 * d + f) * RB * RB + (4 * kq + q) * RB + 16 * jt + c];
+  // v = s o W of ring plane z (zero outside the grid) for this thread's elements
+  auto load_plane = [&](int z, T (&buf)[NPL]) {
+    const bool zin = z >= 0 && z < g.nz;
+    const int zcl = min(max(z, 0), g.nz - 1);
+    if (!zin) {   // block-uniform: planes beyond the grid are zero
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) buf[i] = T(0);
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      const int e = tid + 256 * i;
+      const int k = min(e / PC, RB - 1), cell = e % PC;
+      const int gy = gy0 + cell / RW, gx = gx0 + cell % RW - 2;
+      const bool in = gx >= 0 && gx < nx && gy < ny && k < r;
+      const int idx = (zcl * ny + min(gy, ny - 1)) * nx + min(max(gx, 0), nx - 1);
+      const T wv = W[size_t(min(k, r - 1)) * ld + idx], sv = s[idx];
+      buf[i] = in ? sv * wv : T(0);
+    }
+  };
+  auto store_plane = [&](int z, const T (&buf)[NPL]) {
+    T *dst = ring + ((z + 10) % 5) * RB * PCP;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      const int e = tid + 256 * i;
+      if (e < RB * PC) dst[(e / PC) * PCP + e % PC] = buf[i];
+    }
+  };
+  // y halo of plane z: rows gy0-2, gy0-1, gy0+4, gy0+5 (halo rows 0..3)
+  auto load_halo = [&](int z, T (&buf)[NHL]) {
+#pragma unroll
+    for (int i = 0; i < NHL; ++i) {
+      const int e = tid + 256 * i;
+      const int k = min(e / HC, RB - 1), hc = e % HC;
+      const int hr = hc >> 4, gx = gx0 + (hc & 15);
+      const int gy = gy0 + (hr < 2 ? hr - 2 : kBrickBY + hr - 2);
+      const bool in = gy >= 0 && gy < ny && gx < nx && k < r;
+      const int idx = (z * ny + min(max(gy, 0), ny - 1)) * nx + min(gx, nx - 1);
+      const T wv = W[size_t(min(k, r - 1)) * ld + idx], sv = s[idx];
+      buf[i] = in ? sv * wv : T(0);
+    }
+  };
+  auto store_halo = [&](const T (&buf)[NHL]) {
+#pragma unroll
+    for (int i = 0; i < NHL; ++i) {
+      const int e = tid + 256 * i;
+      if (e < RB * HC) halo[(e / HC) * HCP + e % HC] = buf[i];
+    }
+  };
+  {
+    T pbuf[NPL];
+    for (int z = z0 - 2; z <= z0 + 2; ++z) {
+      load_plane(z, pbuf);
+      store_plane(z, pbuf);
+    }
+    T hbuf[NHL];
+    load_halo(z0, hbuf);
+    store_halo(hbuf);
+  }
+  __syncthreads();
+  T ih[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) ih[d] = T(g.inv2h[d]);
+  const int gx = gx0 + c, gy = gy0 + row;
+  const bool valid = gx < nx && gy < ny;
+  const int base = row * RW + c + 2;
+  for (int z = z0; z < z1; ++z) {
+    const bool more = z + 1 < z1;
+    T pbuf[NPL], hbuf[NHL];
+    if (more) {
+      load_plane(z + 3, pbuf);
+      load_halo(z + 1, hbuf);
+    }
+    const int xo = (z * ny + min(gy, ny - 1)) * nx + min(gx, nx - 1);
+    T k0v[NJ][4];
+#pragma unroll
+    for (int jt = 0; jt < NJ; ++jt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        k0v[jt][v] = K0[size_t(min(16 * jt + Mfma<T>::row(q, v), r - 1)) * ld + xo];
+    acc_t acc[NJ];
+#pragma unroll
+    for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+    const T *pc = ring + ((z + 10) % 5) * RB * PCP;
+    const T *pzm1 = ring + ((z + 9) % 5) * RB * PCP, *pzm2 = ring + ((z + 8) % 5) * RB * PCP;
+    const T *pzp1 = ring + ((z + 11) % 5) * RB * PCP, *pzp2 = ring + ((z + 12) % 5) * RB * PCP;
+    // y-neighbour rows row-2, row-1, row+1, row+2: inside the brick from the
+    // ring plane, else from the y halo (wave-uniform choice)
+    const T *yp[4];
+    int ys[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int yr = row + (t < 2 ? t - 2 : t - 1);
+      const bool inb = yr >= 0 && yr < kBrickBY;
+      const int hr = yr < 0 ? yr + 2 : yr - kBrickBY + 2;
+      yp[t] = inb ? pc + yr * RW + c + 2 : halo + hr * 16 + c;
+      ys[t] = inb ? PCP : HCP;
+    }
+#pragma unroll
+    for (int kq = 0; kq < KS; ++kq) {
+      const int k = 4 * kq + q;
+      const int ok = k * PCP;
+      const T v0 = pc[ok + base];
+      T vm1[3], vm2[3], vp1[3], vp2[3];
+      vm2[0] = pc[ok + base - 2];
+      vm1[0] = pc[ok + base - 1];
+      vp1[0] = pc[ok + base + 1];
+      vp2[0] = pc[ok + base + 2];
+      vm2[1] = yp[0][k * ys[0]];
+      vm1[1] = yp[1][k * ys[1]];
+      vp1[1] = yp[2][k * ys[2]];
+      vp2[1] = yp[3][k * ys[3]];
+      if constexpr (DIM == 3) {
+        vm2[2] = pzm2[ok + base];
+        vm1[2] = pzm1[ok + base];
+        vp1[2] = pzp1[ok + base];
+        vp2[2] = pzp2[ok + base];
+      }
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const T db = (T(3) * v0 - T(4) * vm1[d] + vm2[d]) * ih[d];
+        const T df = (T(4) * vp1[d] - T(3) * v0 - vp2[d]) * ih[d];
+#pragma unroll
+        for (int jt = 0; jt < NJ; ++jt) {
+          acc[jt] = Mfma<T>::op(bq[d][kq][jt][0], db, acc[jt]);
+          acc[jt] = Mfma<T>::op(bq[d][kq][jt][1], df, acc[jt]);
+        }
+      }
+    }
+#pragma unroll
+    for (int jt = 0; jt < NJ; ++jt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * jt + Mfma<T>::row(q, v);
+        if (valid && j < r)
+          out[size_t(j) * ld + xo] = T(double(k0v[jt][v]) - coef * double(acc[jt][v]));
+      }
+    }
+    __syncthreads();
+    if (more) {
+      store_plane(z + 3, pbuf);
+      store_halo(hbuf);
+    }
+    __syncthreads();
   }
 }
 
@@ -523,25 +748,95 @@ void launch_pack_couplings(int ndk, int r, const double *B, int ldb, T *Bp, hipS
   k_pack_couplings<T><<<(tot + kBlock - 1) / kBlock, kBlock, 0, st>>>(ndk, r, RB, B, ldb, Bp);
 }
 
+template <typename T, int NJ>
+static void kstage_launch(const GridDev &g, const T *s, const T *W, const T *K0, T *out, int ld,
+                          int r, const T *Bp, double coef, int tiled, int ntiles,
+                          hipStream_t st) {
+  const size_t shm = size_t(2) * g.dim * (16 * NJ) * (16 * NJ) * sizeof(T);
+  const bool lds = shm <= 65536;
+  auto kern = lds ? k_kstage_mfma<T, NJ, true> : k_kstage_mfma<T, NJ, false>;
+  // resident blocks per CU and CU count, queried once per instantiation
+  static std::atomic<int> per_cu_cache[2] = {0, 0};
+  static std::atomic<int> n_cu_cache{0};
+  int n_cu = n_cu_cache.load(std::memory_order_relaxed);
+  if (n_cu <= 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n_cu <= 0)
+      n_cu = 256;
+    n_cu_cache.store(n_cu, std::memory_order_relaxed);
+  }
+  int pc = per_cu_cache[lds ? 1 : 0].load(std::memory_order_relaxed);
+  if (pc <= 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void *>(kern),
+                                                     256, lds ? shm : 0) != hipSuccess ||
+        pc <= 0)
+      pc = 1;
+    per_cu_cache[lds ? 1 : 0].store(pc, std::memory_order_relaxed);
+  }
+  const int cap = std::max(1, pc * n_cu / 8);
+  const int blocks = 8 * std::min(cap, std::max(1, (ntiles + 7) / 8));
+  kern<<<blocks, 256, lds ? shm : 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef, tiled, ntiles);
+}
+
+template <typename T, int NJ, int DIM>
+static void kstage_brick_launch(const GridDev &g, const T *s, const T *W, const T *K0, T *out,
+                                int ld, int r, const T *Bp, double coef, hipStream_t st) {
+  const size_t shm = brick_lds_bytes(16 * NJ, int(sizeof(T)));
+  auto kern = k_kstage_brick<T, NJ, DIM>;
+  static std::atomic<int> blocks_cache{0};
+  int cap = blocks_cache.load(std::memory_order_relaxed);
+  if (cap <= 0) {
+    if (shm > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+    int dev = 0, n_cu = 0, pc = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n_cu <= 0)
+      n_cu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void *>(kern),
+                                                     256, shm) != hipSuccess ||
+        pc <= 0)
+      pc = 1;
+    cap = pc * n_cu;
+    blocks_cache.store(cap, std::memory_order_relaxed);
+  }
+  const int nbx = (g.nx + 15) / 16, nby = (g.ny + kBrickBY - 1) / kBrickBY;
+  const int ncol = nbx * nby;
+  int nzc = std::max(1, std::min(g.nz, (cap + ncol - 1) / ncol));
+  const int zchunk = (g.nz + nzc - 1) / nzc;
+  nzc = (g.nz + zchunk - 1) / zchunk;
+  kern<<<ncol * nzc, 256, shm, st>>>(g, s, W, K0, out, ld, r, Bp, coef, nby, nzc, zchunk);
+}
+
 template <typename T>
 void launch_kstep_stage(const GridDev &g, const T *s, const T *W, const T *K0, T *out, int ld,
                         int r, const T *Bp, double coef, hipStream_t st) {
+  if (kUseBrick && r <= 32) {
+    const bool three = g.dim == 3;
+    if (r <= 16 && three) kstage_brick_launch<T, 1, 3>(g, s, W, K0, out, ld, r, Bp, coef, st);
+    else if (r <= 16) kstage_brick_launch<T, 1, 2>(g, s, W, K0, out, ld, r, Bp, coef, st);
+    else if (three) kstage_brick_launch<T, 2, 3>(g, s, W, K0, out, ld, r, Bp, coef, st);
+    else kstage_brick_launch<T, 2, 2>(g, s, W, K0, out, ld, r, Bp, coef, st);
+    return;
+  }
   const int tiled = (g.nx % 16 == 0) ? 1 : 0;
-  int blocks;
+  int ntiles;
   if (tiled) {
     const int px = g.nx / 16, py = (g.ny + 3) / 4;
     const int tpx = std::min(2, px), tpy = std::min(8, py);
     const int ncol = ((px + tpx - 1) / tpx) * ((py + tpy - 1) / tpy);
-    blocks = ncol * tpx * tpy * g.nz;
+    ntiles = ncol * tpx * tpy * g.nz;
   } else {
-    blocks = (g.n + 63) / 64;
+    ntiles = (g.n + 63) / 64;
   }
-  const int nj = (r + 15) / 16;
-  switch (nj) {
-    case 1: k_kstage_mfma<T, 1><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef, tiled); break;
-    case 2: k_kstage_mfma<T, 2><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef, tiled); break;
-    case 3: k_kstage_mfma<T, 3><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef, tiled); break;
-    default: k_kstage_mfma<T, 4><<<blocks, 256, 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef, tiled); break;
+  switch ((r + 15) / 16) {
+    case 1: kstage_launch<T, 1>(g, s, W, K0, out, ld, r, Bp, coef, tiled, ntiles, st); break;
+    case 2: kstage_launch<T, 2>(g, s, W, K0, out, ld, r, Bp, coef, tiled, ntiles, st); break;
+    case 3: kstage_launch<T, 3>(g, s, W, K0, out, ld, r, Bp, coef, tiled, ntiles, st); break;
+    default: kstage_launch<T, 4>(g, s, W, K0, out, ld, r, Bp, coef, tiled, ntiles, st); break;
   }
 }
 
