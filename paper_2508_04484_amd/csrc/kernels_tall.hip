@@ -260,41 +260,66 @@ __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restr
 
 // K-step stage with an LDS z-march (r <= 32).  A block owns a brick column of
 // 16 (x) x 4 (y) cells and a chunk of z planes and marches through z.  The
-// LDS holds a ring of five planes of v = s o W (planes z-2..z+2, each row with
-// a 2-cell x halo) and the 2-row y halo of the centre plane, all zero outside
-// the grid (zero ghost cells), so every difference operand comes from LDS and
-// every input value is read from L2 about twice instead of once per stencil
-// use.  Wave w computes row w of the centre plane as in k_kstage_mfma (the
-// transposed tile out^T = B^T D^T on 16x16x4 MFMAs, couplings held in
-// registers), while the loads of plane z+3 and of the next y halo are in
-// flight; they are written to LDS between two barriers after the MFMAs.
-constexpr bool kUseBrick = false;            // z-march stage kernel (else the global-load one)
-constexpr int kBrickBY = 4;                  // rows per brick = waves per block
-constexpr int kBrickRW = 16 + 4;             // row width with the x halo
-constexpr int kBrickPC = kBrickBY * kBrickRW;                  // cells per ring plane
-constexpr int kBrickPCP = kBrickPC + (48 - kBrickPC % 32) % 32;  // = 16 mod 32: no bank conflicts
-constexpr int kBrickHC = 4 * 16;                               // y-halo cells
-constexpr int kBrickHCP = kBrickHC + (48 - kBrickHC % 32) % 32;
+// LDS holds a ring of six planes of W (each brick row with a 2-cell x halo;
+// planes z-2..z+2 in use while z+3 arrives) and two buffers of the 2-row y
+// halo, filled by direct global->LDS loads that take no registers, plus the
+// matching values of s, which are zero outside the grid: the zero ghost cells
+// are W read from a clamped in-range cell times s = 0.  Every difference
+// operand thus comes from LDS and each input value is read from L2 about
+// twice instead of once per stencil use.  Wave w computes row w of the centre
+// plane (for WJ = 2 two waves share a row, each owning half of the output
+// columns): the transposed tile out^T = B^T D^T on 16x16x4 MFMAs with the
+// couplings held in registers, each difference of s o W formed as an
+// s-weighted sum of W.
+constexpr bool kUseBrick = false;   // measured slower than the persistent stage kernel
+constexpr int kBrickBY = 4;                    // rows per brick = waves per block
+constexpr int kBrickRW = 16 + 4;               // row width with the x halo
+constexpr int kBrickPC = kBrickBY * kBrickRW;  // cells per ring plane
+constexpr int kBrickHC = 4 * 16;               // y-halo cells (4 rows of 16)
+constexpr int kBrickHS = 80;                   // y-halo stride per column of W
+constexpr int kBrickSlots = 6;
+static_assert(kBrickPC % 32 == 16 && kBrickHS % 32 == 16, "LDS strides avoid bank conflicts");
 
 __host__ __device__ constexpr size_t brick_lds_bytes(int rb, int tsize) {
-  return size_t(rb) * (5 * kBrickPCP + kBrickHCP) * tsize;
+  return (size_t(kBrickSlots) * rb * kBrickPC + size_t(2) * rb * kBrickHS +
+          size_t(kBrickSlots) * kBrickPC + size_t(2) * kBrickHC) *
+         size_t(tsize);
 }
 
-template <typename T, int NJ, int DIM>
-__global__ __launch_bounds__(256) void k_kstage_brick(GridDev g, const T *__restrict__ s,
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt not waited for): this wave's direct
+// global->LDS loads have landed
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+__device__ __forceinline__ void dma_dword(const unsigned *src, unsigned *lds_dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 4, 0,
+                                   0);
+}
+
+template <typename T, int NJ, int DIM, int WJ>
+__global__ __launch_bounds__(64 * kBrickBY * WJ) void k_kstage_brick(GridDev g, const T *__restrict__ s,
                                                      const T *__restrict__ W,
                                                      const T *__restrict__ K0,
                                                      T *__restrict__ out, int ld, int r,
                                                      const T *__restrict__ Bp, double coef,
                                                      int nby, int nzc, int zchunk) {
-  constexpr int RB = 16 * NJ, KS = 4 * NJ;
-  constexpr int RW = kBrickRW, PC = kBrickPC, PCP = kBrickPCP, HC = kBrickHC, HCP = kBrickHCP;
-  constexpr int NPL = (RB * PC + 255) / 256;   // ring-plane elements per thread
-  constexpr int NHL = (RB * HC + 255) / 256;   // y-halo elements per thread
+  constexpr int RB = 16 * NJ, KS = 4 * NJ, DPE = int(sizeof(T)) / 4;
+  constexpr int BY = kBrickBY, RW = kBrickRW, PC = kBrickPC, HC = kBrickHC, HS = kBrickHS;
+  constexpr int NS = kBrickSlots;
+  constexpr int NW = BY * WJ, NT = 64 * NW;    // waves and threads per block
+  constexpr int NJW = NJ / WJ;                 // output column tiles per wave
+  static_assert(NJ % WJ == 0, "whole column tiles per wave");
+  constexpr int PLANE_DW = RB * PC * DPE;      // dwords of one ring plane of W
+  constexpr int HROW_DW = HC * DPE;            // dwords of one y-halo column of W
+  static_assert(PLANE_DW % (64 * NW) == 0 && HROW_DW % 64 == 0 && (RB * HROW_DW) % (64 * NW) == 0,
+                "whole 64-dword loads per wave");
+  constexpr int NPI = PLANE_DW / (64 * NW);    // 64-dword loads per wave per plane
+  constexpr int NHI = RB * HROW_DW / (64 * NW);   // ... per y halo
   using acc_t = typename Mfma<T>::acc_t;
   extern __shared__ unsigned char smem_raw[];
-  T *ring = reinterpret_cast<T *>(smem_raw);   // [5][RB][PCP]
-  T *halo = ring + 5 * RB * PCP;               // [RB][HCP]
+  T *ringW = reinterpret_cast<T *>(smem_raw);  // [NS][RB][PC]
+  T *haloW = ringW + NS * RB * PC;             // [2][RB][HS]
+  T *ringS = haloW + 2 * RB * HS;              // [NS][PC]
+  T *haloS = ringS + NS * PC;                  // [2][HC]
   // block -> (brick column, z chunk); the hardware's round-robin of blocks
   // over the 8 XCDs gets one contiguous range of this order per XCD
   const int nblk = gridDim.x, b = blockIdx.x;
@@ -302,166 +327,183 @@ __global__ __launch_bounds__(256) void k_kstage_brick(GridDev g, const T *__rest
   const int L = xcd * per + min(xcd, rem) + (b >> 3);
   const int zc = L % nzc, col = L / nzc;
   const int by = col % nby, bx = col / nby;
-  const int gx0 = 16 * bx, gy0 = kBrickBY * by;
+  const int gx0 = 16 * bx, gy0 = BY * by;
   const int z0 = zc * zchunk, z1 = min(g.nz, z0 + zchunk);
   if (z0 >= z1) return;
-  const int tid = threadIdx.x, row = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int row = wave % BY, jt0 = (wave / BY) * NJW;
   const int c = lane & 15, q = lane >> 4;
-  const int nx = g.nx, ny = g.ny;
-  // couplings: A operands of all MFMAs of this lane
-  T bq[DIM][KS][NJ][2];
+  const int nx = g.nx, ny = g.ny, nz = g.nz, plane = nx * ny;
+  // couplings: the A operands of all MFMAs of this lane
+  T bq[DIM][KS][NJW][2];
 #pragma unroll
   for (int d = 0; d < DIM; ++d)
 #pragma unroll
     for (int kq = 0; kq < KS; ++kq)
 #pragma unroll
-      for (int jt = 0; jt < NJ; ++jt)
+      for (int jt = 0; jt < NJW; ++jt)
 #pragma unroll
         for (int f = 0; f < 2; ++f)
-          bq[d][kq][jt][f] = Bp[size_t(2 * d + f) * RB * RB + (4 * kq + q) * RB + 16 * jt + c];
-  // v = s o W of ring plane z (zero outside the grid) for this thread's elements
-  auto load_plane = [&](int z, T (&buf)[NPL]) {
-    const bool zin = z >= 0 && z < g.nz;
-    const int zcl = min(max(z, 0), g.nz - 1);
-    if (!zin) {   // block-uniform: planes beyond the grid are zero
+          bq[d][kq][jt][f] =
+              Bp[size_t(2 * d + f) * RB * RB + (4 * kq + q) * RB + 16 * (jt0 + jt) + c];
+  // dword offsets (within one z plane) of this lane's share of the W loads;
+  // cells and columns are clamped into range
+  int poff[NPI], hoff[NHI];
 #pragma unroll
-      for (int i = 0; i < NPL; ++i) buf[i] = T(0);
-      return;
-    }
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) {
-      const int e = tid + 256 * i;
-      const int k = min(e / PC, RB - 1), cell = e % PC;
-      const int gy = gy0 + cell / RW, gx = gx0 + cell % RW - 2;
-      const bool in = gx >= 0 && gx < nx && gy < ny && k < r;
-      const int idx = (zcl * ny + min(gy, ny - 1)) * nx + min(max(gx, 0), nx - 1);
-      const T wv = W[size_t(min(k, r - 1)) * ld + idx], sv = s[idx];
-      buf[i] = in ? sv * wv : T(0);
-    }
-  };
-  auto store_plane = [&](int z, const T (&buf)[NPL]) {
-    T *dst = ring + ((z + 10) % 5) * RB * PCP;
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) {
-      const int e = tid + 256 * i;
-      if (e < RB * PC) dst[(e / PC) * PCP + e % PC] = buf[i];
-    }
-  };
-  // y halo of plane z: rows gy0-2, gy0-1, gy0+4, gy0+5 (halo rows 0..3)
-  auto load_halo = [&](int z, T (&buf)[NHL]) {
-#pragma unroll
-    for (int i = 0; i < NHL; ++i) {
-      const int e = tid + 256 * i;
-      const int k = min(e / HC, RB - 1), hc = e % HC;
-      const int hr = hc >> 4, gx = gx0 + (hc & 15);
-      const int gy = gy0 + (hr < 2 ? hr - 2 : kBrickBY + hr - 2);
-      const bool in = gy >= 0 && gy < ny && gx < nx && k < r;
-      const int idx = (z * ny + min(max(gy, 0), ny - 1)) * nx + min(gx, nx - 1);
-      const T wv = W[size_t(min(k, r - 1)) * ld + idx], sv = s[idx];
-      buf[i] = in ? sv * wv : T(0);
-    }
-  };
-  auto store_halo = [&](const T (&buf)[NHL]) {
-#pragma unroll
-    for (int i = 0; i < NHL; ++i) {
-      const int e = tid + 256 * i;
-      if (e < RB * HC) halo[(e / HC) * HCP + e % HC] = buf[i];
-    }
-  };
-  {
-    T pbuf[NPL];
-    for (int z = z0 - 2; z <= z0 + 2; ++z) {
-      load_plane(z, pbuf);
-      store_plane(z, pbuf);
-    }
-    T hbuf[NHL];
-    load_halo(z0, hbuf);
-    store_halo(hbuf);
+  for (int i = 0; i < NPI; ++i) {
+    const int dw = 64 * (wave + NW * i) + lane;
+    const int e = dw / DPE, k = e / PC, cell = e % PC;
+    const int gy = min(gy0 + cell / RW, ny - 1);
+    const int gx = min(max(gx0 + cell % RW - 2, 0), nx - 1);
+    poff[i] = (min(k, r - 1) * ld + gy * nx + gx) * DPE + dw % DPE;
   }
+#pragma unroll
+  for (int i = 0; i < NHI; ++i) {
+    const int dw = 64 * (wave + NW * i) + lane;
+    const int k = dw / HROW_DW, hd = dw % HROW_DW, hc = hd / DPE, hr = hc >> 4;
+    const int gx = min(gx0 + (hc & 15), nx - 1);
+    const int gy = min(max(gy0 + (hr < 2 ? hr - 2 : BY + hr - 2), 0), ny - 1);
+    hoff[i] = (min(k, r - 1) * ld + gy * nx + gx) * DPE + hd % DPE;
+  }
+  // s: thread t < PC owns ring cell t, PC <= t < PC + HC owns y-halo cell t - PC
+  int soff = 0;
+  bool sxy = false;
+  if (tid < PC) {
+    const int gy = gy0 + tid / RW, gx = gx0 + tid % RW - 2;
+    sxy = gx >= 0 && gx < nx && gy < ny;
+    soff = min(gy, ny - 1) * nx + min(max(gx, 0), nx - 1);
+  } else if (tid < PC + HC) {
+    const int hc = tid - PC, hr = hc >> 4;
+    const int gy = gy0 + (hr < 2 ? hr - 2 : BY + hr - 2), gx = gx0 + (hc & 15);
+    sxy = gy >= 0 && gy < ny && gx < nx;
+    soff = min(max(gy, 0), ny - 1) * nx + min(gx, nx - 1);
+  }
+  const unsigned *Wdw = reinterpret_cast<const unsigned *>(W);
+  auto slot = [](int z) { return (z + 2 * NS) % NS; };
+  auto dma_plane = [&](int z) {   // W of plane z (clamped) into its ring slot
+    const int zoff = min(max(z, 0), nz - 1) * plane * DPE;
+    unsigned *dst = reinterpret_cast<unsigned *>(ringW + slot(z) * RB * PC);
+#pragma unroll
+    for (int i = 0; i < NPI; ++i) dma_dword(Wdw + poff[i] + zoff, dst + 64 * (wave + NW * i));
+  };
+  auto dma_halo = [&](int z) {    // y halo of plane z (in range) into buffer z & 1
+    const int zoff = z * plane * DPE;
+    unsigned *dst = reinterpret_cast<unsigned *>(haloW + (z & 1) * RB * HS);
+#pragma unroll
+    for (int i = 0; i < NHI; ++i) {
+      const int dw0 = 64 * (wave + NW * i);
+      dma_dword(Wdw + hoff[i] + zoff, dst + (dw0 / HROW_DW) * HS * DPE + dw0 % HROW_DW);
+    }
+  };
+  // s of ring plane zr (threads < PC) or of the y halo of plane zh (next HC threads)
+  auto load_s = [&](int zr, int zh) -> T {
+    if (tid < PC) {
+      const bool in = sxy && zr >= 0 && zr < nz;
+      const T v = s[size_t(min(max(zr, 0), nz - 1)) * plane + soff];
+      return in ? v : T(0);
+    }
+    if (tid < PC + HC) {
+      const T v = s[size_t(zh) * plane + soff];
+      return sxy ? v : T(0);
+    }
+    return T(0);
+  };
+  auto store_s = [&](int zr, int zh, T v) {
+    if (tid < PC) ringS[slot(zr) * PC + tid] = v;
+    else if (tid < PC + HC) haloS[(zh & 1) * HC + tid - PC] = v;
+  };
+  // prologue: planes z0-2 .. z0+2 and the y halo of z0
+  for (int z = z0 - 2; z <= z0 + 2; ++z) {
+    dma_plane(z);
+    const T v = load_s(z, z0);
+    if (tid < PC || z == z0) store_s(z, z0, v);
+  }
+  dma_halo(z0);
+  wait_vm_all();
   __syncthreads();
   T ih[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) ih[d] = T(g.inv2h[d]);
+  const T tcoef = T(coef);
   const int gx = gx0 + c, gy = gy0 + row;
   const bool valid = gx < nx && gy < ny;
   const int base = row * RW + c + 2;
   for (int z = z0; z < z1; ++z) {
     const bool more = z + 1 < z1;
-    T pbuf[NPL], hbuf[NHL];
+    T snext = T(0);
     if (more) {
-      load_plane(z + 3, pbuf);
-      load_halo(z + 1, hbuf);
+      dma_plane(z + 3);
+      dma_halo(z + 1);
+      snext = load_s(z + 3, z + 1);
     }
     const int xo = (z * ny + min(gy, ny - 1)) * nx + min(gx, nx - 1);
-    T k0v[NJ][4];
+    T k0v[NJW][4];
 #pragma unroll
-    for (int jt = 0; jt < NJ; ++jt)
+    for (int jt = 0; jt < NJW; ++jt)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        k0v[jt][v] = K0[size_t(min(16 * jt + Mfma<T>::row(q, v), r - 1)) * ld + xo];
-    acc_t acc[NJ];
-#pragma unroll
-    for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
-    const T *pc = ring + ((z + 10) % 5) * RB * PCP;
-    const T *pzm1 = ring + ((z + 9) % 5) * RB * PCP, *pzm2 = ring + ((z + 8) % 5) * RB * PCP;
-    const T *pzp1 = ring + ((z + 11) % 5) * RB * PCP, *pzp2 = ring + ((z + 12) % 5) * RB * PCP;
-    // y-neighbour rows row-2, row-1, row+1, row+2: inside the brick from the
-    // ring plane, else from the y halo (wave-uniform choice)
-    const T *yp[4];
-    int ys[4];
+        k0v[jt][v] = K0[size_t(min(16 * (jt0 + jt) + Mfma<T>::row(q, v), r - 1)) * ld + xo];
+    // stencil points: centre, then (d, -2, -1, +1, +2); y rows outside the
+    // brick come from the halo buffer (a wave-uniform choice)
+    const int sc = slot(z), hb = z & 1;
+    const T *Wc = ringW + sc * RB * PC, *Sc = ringS + sc * PC;
+    const T *wp[DIM][4], *sp[DIM][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int yr = row + (t < 2 ? t - 2 : t - 1);
-      const bool inb = yr >= 0 && yr < kBrickBY;
-      const int hr = yr < 0 ? yr + 2 : yr - kBrickBY + 2;
-      yp[t] = inb ? pc + yr * RW + c + 2 : halo + hr * 16 + c;
-      ys[t] = inb ? PCP : HCP;
+      const int o = t < 2 ? t - 2 : t - 1;
+      wp[0][t] = Wc + base + o;
+      sp[0][t] = Sc + base + o;
+      const int yr = row + o;
+      const bool inb = yr >= 0 && yr < BY;
+      const int hr = yr < 0 ? yr + 2 : yr - BY + 2;
+      wp[1][t] = inb ? Wc + yr * RW + c + 2 : haloW + hb * RB * HS + hr * 16 + c;
+      sp[1][t] = inb ? Sc + yr * RW + c + 2 : haloS + hb * HC + hr * 16 + c;
+      if constexpr (DIM == 3) {
+        wp[2][t] = ringW + slot(z + o) * RB * PC + base;
+        sp[2][t] = ringS + slot(z + o) * PC + base;
+      }
     }
+    // s-weights of the one-sided differences (ih folded in)
+    const T s0 = Sc[base];
+    T cb[DIM][3], cf[DIM][3];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      cb[d][0] = T(3) * ih[d] * s0;
+      cb[d][1] = T(-4) * ih[d] * *sp[d][1];
+      cb[d][2] = ih[d] * *sp[d][0];
+      cf[d][0] = T(-3) * ih[d] * s0;
+      cf[d][1] = T(4) * ih[d] * *sp[d][2];
+      cf[d][2] = -ih[d] * *sp[d][3];
+    }
+    acc_t acc[NJW];
+#pragma unroll
+    for (int jt = 0; jt < NJW; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int kq = 0; kq < KS; ++kq) {
-      const int k = 4 * kq + q;
-      const int ok = k * PCP;
-      const T v0 = pc[ok + base];
-      T vm1[3], vm2[3], vp1[3], vp2[3];
-      vm2[0] = pc[ok + base - 2];
-      vm1[0] = pc[ok + base - 1];
-      vp1[0] = pc[ok + base + 1];
-      vp2[0] = pc[ok + base + 2];
-      vm2[1] = yp[0][k * ys[0]];
-      vm1[1] = yp[1][k * ys[1]];
-      vp1[1] = yp[2][k * ys[2]];
-      vp2[1] = yp[3][k * ys[3]];
-      if constexpr (DIM == 3) {
-        vm2[2] = pzm2[ok + base];
-        vm1[2] = pzm1[ok + base];
-        vp1[2] = pzp1[ok + base];
-        vp2[2] = pzp2[ok + base];
-      }
+      const int ok = (4 * kq + q) * PC;   // column offset (PC == HS)
+      const T w0 = Wc[ok + base];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        const T db = (T(3) * v0 - T(4) * vm1[d] + vm2[d]) * ih[d];
-        const T df = (T(4) * vp1[d] - T(3) * v0 - vp2[d]) * ih[d];
+        const T wm2 = wp[d][0][ok], wm1 = wp[d][1][ok], wp1 = wp[d][2][ok], wp2 = wp[d][3][ok];
+        const T db = cb[d][2] * wm2 + (cb[d][1] * wm1 + cb[d][0] * w0);
+        const T df = cf[d][2] * wp2 + (cf[d][1] * wp1 + cf[d][0] * w0);
 #pragma unroll
-        for (int jt = 0; jt < NJ; ++jt) {
+        for (int jt = 0; jt < NJW; ++jt) {
           acc[jt] = Mfma<T>::op(bq[d][kq][jt][0], db, acc[jt]);
           acc[jt] = Mfma<T>::op(bq[d][kq][jt][1], df, acc[jt]);
         }
       }
     }
 #pragma unroll
-    for (int jt = 0; jt < NJ; ++jt) {
+    for (int jt = 0; jt < NJW; ++jt) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * jt + Mfma<T>::row(q, v);
-        if (valid && j < r)
-          out[size_t(j) * ld + xo] = T(double(k0v[jt][v]) - coef * double(acc[jt][v]));
+        const int j = 16 * (jt0 + jt) + Mfma<T>::row(q, v);
+        if (valid && j < r) out[size_t(j) * ld + xo] = k0v[jt][v] - tcoef * acc[jt][v];
       }
     }
-    __syncthreads();
-    if (more) {
-      store_plane(z + 3, pbuf);
-      store_halo(hbuf);
-    }
+    if (more) store_s(z + 3, z + 1, snext);
+    wait_vm_all();
     __syncthreads();
   }
 }
@@ -783,8 +825,10 @@ static void kstage_launch(const GridDev &g, const T *s, const T *W, const T *K0,
 template <typename T, int NJ, int DIM>
 static void kstage_brick_launch(const GridDev &g, const T *s, const T *W, const T *K0, T *out,
                                 int ld, int r, const T *Bp, double coef, hipStream_t st) {
+  constexpr int WJ = NJ;   // one wave per row and 16-column tile
+  constexpr int NT = 64 * kBrickBY * WJ;
   const size_t shm = brick_lds_bytes(16 * NJ, int(sizeof(T)));
-  auto kern = k_kstage_brick<T, NJ, DIM>;
+  auto kern = k_kstage_brick<T, NJ, DIM, WJ>;
   static std::atomic<int> blocks_cache{0};
   int cap = blocks_cache.load(std::memory_order_relaxed);
   if (cap <= 0) {
@@ -797,7 +841,7 @@ static void kstage_brick_launch(const GridDev &g, const T *s, const T *W, const 
         n_cu <= 0)
       n_cu = 256;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void *>(kern),
-                                                     256, shm) != hipSuccess ||
+                                                     NT, shm) != hipSuccess ||
         pc <= 0)
       pc = 1;
     cap = pc * n_cu;
@@ -808,18 +852,21 @@ static void kstage_brick_launch(const GridDev &g, const T *s, const T *W, const 
   int nzc = std::max(1, std::min(g.nz, (cap + ncol - 1) / ncol));
   const int zchunk = (g.nz + nzc - 1) / nzc;
   nzc = (g.nz + zchunk - 1) / zchunk;
-  kern<<<ncol * nzc, 256, shm, st>>>(g, s, W, K0, out, ld, r, Bp, coef, nby, nzc, zchunk);
+  kern<<<ncol * nzc, NT, shm, st>>>(g, s, W, K0, out, ld, r, Bp, coef, nby, nzc, zchunk);
 }
 
 template <typename T>
 void launch_kstep_stage(const GridDev &g, const T *s, const T *W, const T *K0, T *out, int ld,
                         int r, const T *Bp, double coef, hipStream_t st) {
-  if (kUseBrick && r <= 32) {
+  // z-march kernel where its LDS fits: r <= 32 in FP32, r <= 16 in FP64
+  if (kUseBrick && r <= (sizeof(T) == 4 ? 32 : 16)) {
     const bool three = g.dim == 3;
     if (r <= 16 && three) kstage_brick_launch<T, 1, 3>(g, s, W, K0, out, ld, r, Bp, coef, st);
     else if (r <= 16) kstage_brick_launch<T, 1, 2>(g, s, W, K0, out, ld, r, Bp, coef, st);
-    else if (three) kstage_brick_launch<T, 2, 3>(g, s, W, K0, out, ld, r, Bp, coef, st);
-    else kstage_brick_launch<T, 2, 2>(g, s, W, K0, out, ld, r, Bp, coef, st);
+    else if constexpr (sizeof(T) == 4) {
+      if (three) kstage_brick_launch<T, 2, 3>(g, s, W, K0, out, ld, r, Bp, coef, st);
+      else kstage_brick_launch<T, 2, 2>(g, s, W, K0, out, ld, r, Bp, coef, st);
+    }
     return;
   }
   const int tiled = (g.nx % 16 == 0) ? 1 : 0;
