@@ -13,6 +13,7 @@ namespace {
 
 constexpr int kT = 16;
 constexpr int kWG = 512;   // threads of the single-workgroup kernels
+constexpr int kTruncLdsDoubles = 19200;   // LDS room of k_truncate (150 KiB)
 
 // ------------------------------------------------------------------ small GEMM
 __global__ void k_small_gemm(int ta, int tb, int M, int N, int K, double alpha,
@@ -80,6 +81,34 @@ __device__ void blk_gemm(int ta, int tb, int M, int N, int K, double alpha, cons
     }
     double *c = C + i + size_t(j) * ldc;
     *c = alpha * s + (beta == 0.0 ? 0.0 : beta * *c);
+  }
+  __syncthreads();
+}
+
+// coef[j] = sum_t Q(t, j) v(t) for j < cnt: one wave per column, the lanes
+// stride over t and a fixed shuffle tree reduces (deterministic).
+__device__ void blk_coefs(const double *Q, int ldq, int p, int cnt, const double *v,
+                          double *coef) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = wv; j < cnt; j += nw) {
+    double s = 0.0;
+    for (int t = lane; t < p; t += 64) s += Q[t + size_t(j) * ldq] * v[t];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) coef[j] = s;
+  }
+  __syncthreads();
+}
+
+// C(M x N) = alpha A^T B (A: K x M, B: K x N, long K) with one wave per output.
+__device__ void blk_gemm_tn(int M, int N, int K, double alpha, const double *A, int lda,
+                            const double *B, int ldb, double *C, int ldc) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int e = wv; e < M * N; e += nw) {
+    const int i = e % M, j = e / M;
+    double s = 0.0;
+    for (int t = lane; t < K; t += 64) s += A[t + size_t(i) * lda] * B[t + size_t(j) * ldb];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) C[i + size_t(j) * ldc] = alpha * s;
   }
   __syncthreads();
 }
@@ -183,12 +212,7 @@ __device__ int blk_fill(double *Q, int ldq, int p, int cnt, int need, int ncand,
     for (int t = threadIdx.x; t < p; t += blockDim.x) v[t] = (t == cand) ? 1.0 : 0.0;
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
-      for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
-        double s = 0.0;
-        for (int t = 0; t < p; ++t) s += Q[t + size_t(j) * ldq] * v[t];
-        coef[j] = s;
-      }
-      __syncthreads();
+      blk_coefs(Q, ldq, p, cnt, v, coef);
       for (int t = threadIdx.x; t < p; t += blockDim.x) {
         double s = v[t];
         for (int j = 0; j < cnt; ++j) s -= Q[t + size_t(j) * ldq] * coef[j];
@@ -285,9 +309,11 @@ __global__ __launch_bounds__(kWG) void k_gram_orth(int q, const double *__restri
   __shared__ int flag;
   __shared__ int order[128];
   __shared__ double sig[128];
+  extern __shared__ double dyn[];
   const int qq = restrict_count ? *restrict_count : q;
-  double *A = work;               // qq x qq copy of W
-  double *V = work + q * q;       // eigenvectors
+  double *A = dyn;                // qq x qq copy of W (LDS)
+  double *V = dyn + q * q;        // eigenvectors (LDS)
+  (void)work;
   for (int e = threadIdx.x; e < qq * qq; e += blockDim.x) {
     int i = e % qq, j = e / qq;
     A[i + j * qq] = W[i + j * q];
@@ -319,11 +345,12 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
   __shared__ int flag;
   __shared__ int order[128];
   __shared__ double sig[128];
+  extern __shared__ double dyn[];
   double *R = work;                    // m x r
-  double *G = R + size_t(m) * r;       // r x r
-  double *W = G + r * r;               // r x r
-  double *Q = W + r * r;               // r x r
-  double *X = Q + r * r;               // m x r
+  double *X = R + size_t(m) * r;       // m x r
+  double *G = dyn;                     // r x r (LDS)
+  double *W = G + r * r;               // r x r (LDS)
+  double *Q = W + r * r;               // r x r (LDS)
   // ||L||_F^2
   double nl = 0.0;
   for (int e = threadIdx.x; e < m * r; e += blockDim.x) nl += L[e] * L[e];
@@ -331,7 +358,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
   for (int e = threadIdx.x; e < m * r; e += blockDim.x) R[e] = L[e];
   __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {
-    blk_gemm(1, 0, r, r, m, 1.0, Vh, ldv, R, m, 0.0, G, r);              // G = V^T R
+    blk_gemm_tn(r, r, m, 1.0, Vh, ldv, R, m, G, r);                      // G = V^T R
     for (int e = threadIdx.x; e < m * r; e += blockDim.x) {              // R -= V G
       int i = e % m, j = e / m;
       double s = 0.0;
@@ -340,7 +367,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
     }
     __syncthreads();
   }
-  blk_gemm(1, 0, r, r, m, 1.0, R, m, R, m, 0.0, W, r);                   // W = R^T R
+  blk_gemm_tn(r, r, m, 1.0, R, m, R, m, W, r);                           // W = R^T R
   blk_jacobi(W, r, r, r, Q, r, &flag);
   __syncthreads();
   blk_colnorms_sorted(W, r, r, r, sig, order);
@@ -359,7 +386,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
   __syncthreads();
   if (kept > 0) {
     // second pass: project once more against V, then X = X1 Q2 diag(lambda2^-1/2)
-    blk_gemm(1, 0, r, kept, m, 1.0, Vh, ldv, X, m, 0.0, G, r);
+    blk_gemm_tn(r, kept, m, 1.0, Vh, ldv, X, m, G, r);
     for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
       int i = e % m, j = e / m;
       double s = 0.0;
@@ -367,7 +394,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
       X[e] -= s;
     }
     __syncthreads();
-    blk_gemm(1, 0, kept, kept, m, 1.0, X, m, X, m, 0.0, W, kept);
+    blk_gemm_tn(kept, kept, m, 1.0, X, m, X, m, W, kept);
     blk_jacobi(W, kept, kept, kept, Q, kept, &flag);
     __syncthreads();
     blk_colnorms_sorted(W, kept, kept, kept, sig, order);
@@ -395,14 +422,16 @@ __global__ __launch_bounds__(kWG) void k_truncate(const double *__restrict__ Sh,
   __shared__ int flag;
   __shared__ int order[128];
   __shared__ double sig[128];
+  __shared__ double v[128], coef[128];
+  extern __shared__ double dyn[];
   const int pU = r_base + (kU ? *kU : 0);
   const int pV = r_base + (kV ? *kV : 0);
   const bool cols = pU >= pV;                 // Jacobi on columns of Sh or of Sh^T
   const int p = cols ? pU : pV, q = cols ? pV : pU;
-  double *A = work;                           // p x q
-  double *V = A + P * P;                      // q x q
-  double *v = V + P * P;                      // P
-  double *coef = v + P;                       // P
+  // p x q matrix and q x q rotations in LDS when the launch provided room
+  const bool in_lds = size_t(P) * P * 2 <= size_t(kTruncLdsDoubles);
+  double *A = in_lds ? dyn : work;
+  double *V = A + P * P;
   for (int e = threadIdx.x; e < p * q; e += blockDim.x) {
     int i = e % p, j = e / p;
     A[i + j * p] = cols ? Sh[i + j * P] : Sh[j + i * P];
@@ -522,8 +551,10 @@ __global__ __launch_bounds__(kWG) void k_qr_complete(int m, int r, const double 
                                                     double fill_tol, double *Vt, double *St,
                                                     int lds, Ctl *ctl, double *work) {
   __shared__ double red[16];
-  double *v = work;
-  double *coef = work + m;
+  extern __shared__ double dyn[];
+  double *v = dyn;                  // m (LDS)
+  double *coef = dyn + m;           // r (LDS)
+  (void)work;
   double nl = 0.0;
   for (int e = threadIdx.x; e < m * r; e += blockDim.x) nl += L1[e] * L1[e];
   const double thr = tol * sqrt(blk_sum(nl, red));
@@ -535,12 +566,7 @@ __global__ __launch_bounds__(kWG) void k_qr_complete(int m, int r, const double 
       for (int t = threadIdx.x; t < m; t += blockDim.x) v[t] = cand[t + size_t(c) * m];
       __syncthreads();
       for (int pass = 0; pass < 2; ++pass) {
-        for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
-          double s = 0.0;
-          for (int t = 0; t < m; ++t) s += Vt[t + size_t(j) * m] * v[t];
-          coef[j] = s;
-        }
-        __syncthreads();
+        blk_coefs(Vt, m, m, cnt, v, coef);
         for (int t = threadIdx.x; t < m; t += blockDim.x) {
           double s = v[t];
           for (int j = 0; j < cnt; ++j) s -= Vt[t + size_t(j) * m] * coef[j];
@@ -560,12 +586,7 @@ __global__ __launch_bounds__(kWG) void k_qr_complete(int m, int r, const double 
   }
   if (cnt != r && threadIdx.x == 0) atomicOr(&ctl->flags, kFlagCompletion);
   // S~ = L1^T V~
-  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
-    int i = e % r, j = e / r;
-    double s = 0.0;
-    for (int t = 0; t < m; ++t) s += L1[t + size_t(i) * m] * Vt[t + size_t(j) * m];
-    St[i + j * lds] = s;
-  }
+  blk_gemm_tn(r, r, m, 1.0, L1, m, Vt, m, St, lds);
 }
 
 __global__ void k_check_finite(const double *__restrict__ x, int count, Ctl *ctl) {
@@ -655,18 +676,27 @@ void launch_copy_block(int rows, int cols, const double *src, int lds, double *d
 void launch_gram_orth(int q, const double *W, double *T, int ldt, double tol2,
                       const double *normsq, int *count, const int *restrict_count, double *work,
                       hipStream_t st) {
-  k_gram_orth<<<1, kWG, 0, st>>>(q, W, T, ldt, tol2, normsq, count, restrict_count, work);
+  const size_t shm = size_t(2) * q * q * sizeof(double);   // q <= 50: 40 KiB
+  k_gram_orth<<<1, kWG, shm, st>>>(q, W, T, ldt, tol2, normsq, count, restrict_count, work);
 }
 
 void launch_vaug(int m, int r, double *Vh, int ldv, const double *L, double tol, int *count,
                  double *work, hipStream_t st) {
-  k_vaug<<<1, kWG, 0, st>>>(m, r, Vh, ldv, L, tol, count, work);
+  const size_t shm = size_t(3) * r * r * sizeof(double);   // r <= 50: 60 KiB
+  k_vaug<<<1, kWG, shm, st>>>(m, r, Vh, ldv, L, tol, count, work);
 }
 
 void launch_truncate(const double *Sh, int P, const int *kU, const int *kV, int r_base,
                      TruncOpt opt, double *Pp, double *Qp, double *Sp, int lds, Ctl *ctl,
                      double *work, hipStream_t st) {
-  k_truncate<<<1, kWG, 0, st>>>(Sh, P, kU, kV, r_base, opt, Pp, Qp, Sp, lds, ctl, work);
+  const size_t shm = size_t(P) * P * 2 <= size_t(kTruncLdsDoubles)
+                         ? size_t(P) * P * 2 * sizeof(double)
+                         : 0;
+  if (shm > 60 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_truncate),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(kTruncLdsDoubles * sizeof(double)));
+  k_truncate<<<1, kWG, shm, st>>>(Sh, P, kU, kV, r_base, opt, Pp, Qp, Sp, lds, ctl, work);
 }
 
 void launch_collided_solve(int N, int m, int r, int n_mat, const double *M, const double *a,
@@ -677,7 +707,8 @@ void launch_collided_solve(int N, int m, int r, int n_mat, const double *M, cons
 void launch_qr_complete(int m, int r, const double *L1, const double *V, double tol,
                         double fill_tol, double *Vt, double *St, int lds, Ctl *ctl,
                         double *work, hipStream_t st) {
-  k_qr_complete<<<1, kWG, 0, st>>>(m, r, L1, V, tol, fill_tol, Vt, St, lds, ctl, work);
+  const size_t shm = size_t(m + r) * sizeof(double);
+  k_qr_complete<<<1, kWG, shm, st>>>(m, r, L1, V, tol, fill_tol, Vt, St, lds, ctl, work);
 }
 
 void launch_check_finite(const double *x, int count, Ctl *ctl, hipStream_t st) {
