@@ -32,7 +32,7 @@ METRIC = "DLRA energy-steps/s at 128³ r=30; beams/s batched vs plain; adjoint/f
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}   # dense FP32 / FP64 matrix peaks
 KSTAGE_SOURCE = os.path.join(ROOT, "paper_2508_04484_amd", "csrc", "kernels_tall.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kstage_traffic_c3.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kstage_traffic_c3.json")   # per-config name
 
 
 def source_sha():
@@ -41,11 +41,59 @@ def source_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
+def _counter_rows(path):
+    """Rows of a rocprofv3 counter_collection.csv (a file or a directory holding one)."""
+    import csv
+    import glob
+    if os.path.isdir(path):
+        hits = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+        if not hits:
+            raise SystemExit(f"no counter_collection.csv under {path}")
+        path = hits[0]
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_counters(fetch_path, write_path, probe_mib, config, out_path):
+    """HBM bytes per K-stage launch from a FETCH_SIZE and a WRITE_SIZE pass
+    (KiB per dispatch), each scaled so that the largest copy kernel of the run
+    (the known-size probe copy of probe_mib MiB) reads and writes exactly its
+    size; writes the summary that measured_traffic() reads."""
+    import statistics
+
+    def per_kernel(rows, ctr):
+        by = {}
+        for r in rows:
+            if r.get("Counter_Name") == ctr:
+                by.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return by
+
+    probe = probe_mib * 1024 * 1024
+    out = {"config": config, "source_sha256": source_sha(), "probe_bytes": probe}
+    total = 0.0
+    for ctr, path in (("FETCH_SIZE", fetch_path), ("WRITE_SIZE", write_path)):
+        by = per_kernel(_counter_rows(path), ctr)
+        stage = [v for k, v in by.items() if "k_kstage" in k]
+        copies = [max(v) for k, v in by.items() if "copyBuffer" in k]
+        if not stage or not copies:
+            raise SystemExit(f"{ctr}: stage kernel or probe copy missing in {path}")
+        kib = statistics.mean(stage[0])
+        scale = probe / (max(copies) * 1024.0)
+        out[ctr] = {"stage_kib_per_dispatch": kib, "dispatches": len(stage[0]),
+                    "probe_kib": max(copies), "scale": scale,
+                    "stage_bytes_per_launch": kib * 1024.0 * scale}
+        total += kib * 1024.0 * scale
+    out["bytes_per_launch"] = total
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def measured_traffic(config):
     """HBM bytes per K-stage launch from the committed counter summary, or None
     when it is missing, for another workload, or older than the kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE.replace("_c3", f"_{config}")) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -134,7 +182,15 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (a known-size "
                          "reference for hardware byte counters)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the K-stage HBM-traffic summary from two rocprofv3 --pmc "
+                         "passes (FETCH_SIZE, WRITE_SIZE) of this script run with "
+                         "--copy-probe-mib, then exit")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, max(args.copy_probe_mib, 1),
+                           args.config, TRAFFIC_FILE.replace("_c3", f"_{args.config}"))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
               "(the path runs on a single MI355X)", file=sys.stderr)
@@ -208,7 +264,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(frac_hbm, 4), "traffic": traffic}
-    roof.update({"kernel": "k_kstage_mfma", "avg_launch_ms": round(avg * 1e3, 4),
+    roof.update({"kernel": "K-step RK4 stage (k_kstage_*)", "avg_launch_ms": round(avg * 1e3, 4),
                  "launches": ks_n, "algorithmic_flops_per_launch": flops,
                  "algorithmic_bytes_per_launch": nbytes,
                  "hbm_frac": round(frac_hbm, 4), "mfma_frac": round(frac_mfma, 4)})

@@ -258,68 +258,118 @@ __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restr
   }
 }
 
-// K-step stage with an LDS z-march (r <= 32).  A block owns a brick column of
-// 16 (x) x 4 (y) cells and a chunk of z planes and marches through z.  The
-// LDS holds a ring of six planes of W (each brick row with a 2-cell x halo;
-// planes z-2..z+2 in use while z+3 arrives) and two buffers of the 2-row y
-// halo, filled by direct global->LDS loads that take no registers, plus the
-// matching values of s, which are zero outside the grid: the zero ghost cells
-// are W read from a clamped in-range cell times s = 0.  Every difference
-// operand thus comes from LDS and each input value is read from L2 about
-// twice instead of once per stencil use.  Wave w computes row w of the centre
-// plane (for WJ = 2 two waves share a row, each owning half of the output
-// columns): the transposed tile out^T = B^T D^T on 16x16x4 MFMAs with the
-// couplings held in registers, each difference of s o W formed as an
-// s-weighted sum of W.
-constexpr bool kUseBrick = false;   // measured slower than the persistent stage kernel
+// K-step stage with an LDS z-march (r <= 32 in FP32, r <= 16 in FP64).  A
+// block owns a brick column of 16 (x) x 4 (y) cells and a chunk of z planes
+// and marches through z.  The LDS holds a ring of seven planes of W (each
+// brick row with a 2-cell x halo; planes z-2..z+2 in use, z+3 landed, z+4
+// arriving), three buffers of the 2-row y halo, the matching values of s and
+// three tiles of K0, all filled by direct buffer->LDS loads issued two steps
+// ahead of their use.  No global load returns to registers inside the march,
+// so the only waits on memory are the explicit ones before the per-step
+// barrier, which leave the newest loads in flight.  Cells outside the grid
+// are read clamped into range and their s is masked to zero when used (the
+// zero ghost cells of the stencil).  Every difference operand comes from
+// LDS, so each input value is read from L2 about twice instead of once per
+// stencil use.  Wave w computes row w of the centre plane: the transposed
+// tile out^T = B^T D^T on 16x16x4 MFMAs with the couplings in registers,
+// each difference of s o W formed as an s-weighted sum of W.
+constexpr bool kUseBrick = true;
 constexpr int kBrickBY = 4;                    // rows per brick = waves per block
 constexpr int kBrickRW = 16 + 4;               // row width with the x halo
 constexpr int kBrickPC = kBrickBY * kBrickRW;  // cells per ring plane
 constexpr int kBrickHC = 4 * 16;               // y-halo cells (4 rows of 16)
 constexpr int kBrickHS = 80;                   // y-halo stride per column of W
-constexpr int kBrickSlots = 6;
+constexpr int kBrickKS = 68;                   // K0-tile stride per column
+constexpr int kBrickSlots = 7;                 // ring planes
+constexpr int kBrickBufs = 3;                  // y-halo / K0-tile buffers
+constexpr unsigned kBufWord3 = 0x00020000u;    // raw (untyped) buffer resource
 static_assert(kBrickPC % 32 == 16 && kBrickHS % 32 == 16, "LDS strides avoid bank conflicts");
+static_assert(kBrickPC == kBrickHS, "one column stride for ring and halo");
+
+// dwords of the s region of one ring plane (a whole number of 64-dword loads)
+__host__ __device__ constexpr int brick_s_dwords(int dpe) {
+  return (kBrickPC * dpe + 63) / 64 * 64;
+}
 
 __host__ __device__ constexpr size_t brick_lds_bytes(int rb, int tsize) {
-  return (size_t(kBrickSlots) * rb * kBrickPC + size_t(2) * rb * kBrickHS +
-          size_t(kBrickSlots) * kBrickPC + size_t(2) * kBrickHC) *
-         size_t(tsize);
+  return size_t(4) * (size_t(kBrickSlots) * rb * kBrickPC * (tsize / 4) +
+                      size_t(kBrickBufs) * rb * kBrickHS * (tsize / 4) +
+                      size_t(kBrickSlots) * brick_s_dwords(tsize / 4) +
+                      size_t(kBrickBufs) * kBrickHC * (tsize / 4) +
+                      size_t(kBrickBufs) * rb * kBrickKS * (tsize / 4) + 64);
 }
 
-// s_waitcnt vmcnt(0) (expcnt and lgkmcnt not waited for): this wave's direct
-// global->LDS loads have landed
-__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
-__device__ __forceinline__ void dma_dword(const unsigned *src, unsigned *lds_dst) {
-  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 4, 0,
-                                   0);
+// s_waitcnt vmcnt(N) (expcnt and lgkmcnt not waited for): at most N of this
+// wave's vector memory operations are still outstanding, i.e. all but the
+// newest N have completed (direct buffer->LDS loads included)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <typename T, int NJ, int DIM, int WJ>
-__global__ __launch_bounds__(64 * kBrickBY * WJ) void k_kstage_brick(GridDev g, const T *__restrict__ s,
-                                                     const T *__restrict__ W,
-                                                     const T *__restrict__ K0,
-                                                     T *__restrict__ out, int ld, int r,
-                                                     const T *__restrict__ Bp, double coef,
-                                                     int nby, int nzc, int zchunk) {
-  constexpr int RB = 16 * NJ, KS = 4 * NJ, DPE = int(sizeof(T)) / 4;
+// Workgroup barrier without the memory fence of __syncthreads(), whose
+// release would wait for every outstanding load of the wave, including the
+// direct buffer->LDS loads meant to stay in flight.  The LDS data the barrier
+// publishes is written only by those loads, and their landing is ensured by
+// an explicit wait_vm before it; the signal fences keep the compiler from
+// moving LDS accesses across it.
+__device__ __forceinline__ void block_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), short(0), int(bytes),
+                                           int(kBufWord3));
+}
+
+// one dword per lane from the buffer (byte offset vo + so) into LDS at
+// dst + 4 * lane (dst wave-uniform)
+__device__ __forceinline__ void dma_dword(__amdgpu_buffer_rsrc_t rs, void *dst, int vo, int so) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)dst, 4,
+                                           vo, so, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, int vo, int so) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+  } else {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, vo, so, 0);
+  }
+}
+
+template <typename T, int NJ, int DIM>
+__global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
+    GridDev g, const T *__restrict__ s, const T *__restrict__ W, const T *__restrict__ K0,
+    T *__restrict__ out, int ld, int r, const T *__restrict__ Bp, double coef, int nby, int nzc,
+    int zchunk) {
+  constexpr int RB = 16 * NJ, KS = 4 * NJ, DPE = int(sizeof(T)) / 4, TB = int(sizeof(T));
   constexpr int BY = kBrickBY, RW = kBrickRW, PC = kBrickPC, HC = kBrickHC, HS = kBrickHS;
-  constexpr int NS = kBrickSlots;
-  constexpr int NW = BY * WJ, NT = 64 * NW;    // waves and threads per block
-  constexpr int NJW = NJ / WJ;                 // output column tiles per wave
-  static_assert(NJ % WJ == 0, "whole column tiles per wave");
-  constexpr int PLANE_DW = RB * PC * DPE;      // dwords of one ring plane of W
-  constexpr int HROW_DW = HC * DPE;            // dwords of one y-halo column of W
-  static_assert(PLANE_DW % (64 * NW) == 0 && HROW_DW % 64 == 0 && (RB * HROW_DW) % (64 * NW) == 0,
-                "whole 64-dword loads per wave");
-  constexpr int NPI = PLANE_DW / (64 * NW);    // 64-dword loads per wave per plane
-  constexpr int NHI = RB * HROW_DW / (64 * NW);   // ... per y halo
+  constexpr int KST = kBrickKS, NS = kBrickSlots, NB = kBrickBufs, NW = BY;
+  constexpr int SPD = brick_s_dwords(DPE);           // dwords of one s ring plane
+  constexpr int SP = SPD / DPE;                      // ... in elements
+  constexpr int NPI = RB * PC * DPE / (64 * NW);     // W-plane loads per wave and step
+  constexpr int NHI = RB * HC * DPE / (64 * NW);     // W y-halo loads ...
+  constexpr int NKI = RB * 64 * DPE / (64 * NW);     // K0-tile loads ...
+  constexpr int NSX = SPD / 64 + HC * DPE / 64;      // s loads (plane + y halo)
+  constexpr int NSI = (NSX + NW - 1) / NW;           // ... per wave (padded with dummies)
+  static_assert((RB * PC * DPE) % (64 * NW) == 0 && (RB * HC * DPE) % (64 * NW) == 0 &&
+                    (RB * 64 * DPE) % (64 * NW) == 0,
+                "equal whole 64-dword loads per wave");
+  constexpr int NLOADS = NPI + NHI + NKI + NSI;      // per wave and step
+  static_assert(NLOADS < 64, "fits vmcnt");
   using acc_t = typename Mfma<T>::acc_t;
   extern __shared__ unsigned char smem_raw[];
-  T *ringW = reinterpret_cast<T *>(smem_raw);  // [NS][RB][PC]
-  T *haloW = ringW + NS * RB * PC;             // [2][RB][HS]
-  T *ringS = haloW + 2 * RB * HS;              // [NS][PC]
-  T *haloS = ringS + NS * PC;                  // [2][HC]
+  T *ringW = reinterpret_cast<T *>(smem_raw);        // [NS][RB][PC]
+  T *haloW = ringW + NS * RB * PC;                   // [NB][RB][HS]
+  T *ringS = haloW + NB * RB * HS;                   // [NS][SP]
+  T *haloS = ringS + NS * SP;                        // [NB][HC]
+  T *K0t = haloS + NB * HC;                          // [NB][RB][KST]
+  unsigned char *pad = reinterpret_cast<unsigned char *>(K0t + NB * RB * KST);   // 64 dwords
   // block -> (brick column, z chunk); the hardware's round-robin of blocks
   // over the 8 XCDs gets one contiguous range of this order per XCD
   const int nblk = gridDim.x, b = blockIdx.x;
@@ -330,96 +380,107 @@ __global__ __launch_bounds__(64 * kBrickBY * WJ) void k_kstage_brick(GridDev g, 
   const int gx0 = 16 * bx, gy0 = BY * by;
   const int z0 = zc * zchunk, z1 = min(g.nz, z0 + zchunk);
   if (z0 >= z1) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int row = wave % BY, jt0 = (wave / BY) * NJW;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // = brick row
+  const int row = wave;
   const int c = lane & 15, q = lane >> 4;
   const int nx = g.nx, ny = g.ny, nz = g.nz, plane = nx * ny;
+  const size_t tall_bytes = size_t(ld) * r * TB;
+  const __amdgpu_buffer_rsrc_t rW = make_rsrc(W, tall_bytes), rK = make_rsrc(K0, tall_bytes);
+  const __amdgpu_buffer_rsrc_t rO = make_rsrc(out, tall_bytes);
+  const __amdgpu_buffer_rsrc_t rS = make_rsrc(s, size_t(g.n) * TB);
+  auto clampy = [&](int y) { return min(max(y, 0), ny - 1); };
+  auto clampx = [&](int x) { return min(max(x, 0), nx - 1); };
+  auto clampz = [&](int z) { return min(max(z, 0), nz - 1); };
+  auto halo_y = [&](int hr) { return gy0 + (hr < 2 ? hr - 2 : BY + hr - 2); };
   // couplings: the A operands of all MFMAs of this lane
-  T bq[DIM][KS][NJW][2];
+  T bq[DIM][KS][NJ][2];
 #pragma unroll
   for (int d = 0; d < DIM; ++d)
 #pragma unroll
     for (int kq = 0; kq < KS; ++kq)
 #pragma unroll
-      for (int jt = 0; jt < NJW; ++jt)
+      for (int jt = 0; jt < NJ; ++jt)
 #pragma unroll
         for (int f = 0; f < 2; ++f)
-          bq[d][kq][jt][f] =
-              Bp[size_t(2 * d + f) * RB * RB + (4 * kq + q) * RB + 16 * (jt0 + jt) + c];
-  // dword offsets (within one z plane) of this lane's share of the W loads;
-  // cells and columns are clamped into range
-  int poff[NPI], hoff[NHI];
+          bq[d][kq][jt][f] = Bp[size_t(2 * d + f) * RB * RB + (4 * kq + q) * RB + 16 * jt + c];
+  // per-lane byte offsets (within one z plane) of every load of the march
+  int poff[NPI], hoff[NHI], koff[NKI], soff[NSI];
 #pragma unroll
   for (int i = 0; i < NPI; ++i) {
     const int dw = 64 * (wave + NW * i) + lane;
     const int e = dw / DPE, k = e / PC, cell = e % PC;
-    const int gy = min(gy0 + cell / RW, ny - 1);
-    const int gx = min(max(gx0 + cell % RW - 2, 0), nx - 1);
-    poff[i] = (min(k, r - 1) * ld + gy * nx + gx) * DPE + dw % DPE;
+    const int gy = clampy(gy0 + cell / RW), gx = clampx(gx0 + cell % RW - 2);
+    poff[i] = ((min(k, r - 1) * ld + gy * nx + gx) * DPE + dw % DPE) * 4;
   }
 #pragma unroll
   for (int i = 0; i < NHI; ++i) {
     const int dw = 64 * (wave + NW * i) + lane;
-    const int k = dw / HROW_DW, hd = dw % HROW_DW, hc = hd / DPE, hr = hc >> 4;
-    const int gx = min(gx0 + (hc & 15), nx - 1);
-    const int gy = min(max(gy0 + (hr < 2 ? hr - 2 : BY + hr - 2), 0), ny - 1);
-    hoff[i] = (min(k, r - 1) * ld + gy * nx + gx) * DPE + hd % DPE;
+    const int k = dw / (HC * DPE), hd = dw % (HC * DPE), hc = hd / DPE;
+    const int gy = clampy(halo_y(hc >> 4)), gx = clampx(gx0 + (hc & 15));
+    hoff[i] = ((min(k, r - 1) * ld + gy * nx + gx) * DPE + hd % DPE) * 4;
   }
-  // s: thread t < PC owns ring cell t, PC <= t < PC + HC owns y-halo cell t - PC
-  int soff = 0;
-  bool sxy = false;
-  if (tid < PC) {
-    const int gy = gy0 + tid / RW, gx = gx0 + tid % RW - 2;
-    sxy = gx >= 0 && gx < nx && gy < ny;
-    soff = min(gy, ny - 1) * nx + min(max(gx, 0), nx - 1);
-  } else if (tid < PC + HC) {
-    const int hc = tid - PC, hr = hc >> 4;
-    const int gy = gy0 + (hr < 2 ? hr - 2 : BY + hr - 2), gx = gx0 + (hc & 15);
-    sxy = gy >= 0 && gy < ny && gx < nx;
-    soff = min(max(gy, 0), ny - 1) * nx + min(gx, nx - 1);
-  }
-  const unsigned *Wdw = reinterpret_cast<const unsigned *>(W);
-  auto slot = [](int z) { return (z + 2 * NS) % NS; };
-  auto dma_plane = [&](int z) {   // W of plane z (clamped) into its ring slot
-    const int zoff = min(max(z, 0), nz - 1) * plane * DPE;
-    unsigned *dst = reinterpret_cast<unsigned *>(ringW + slot(z) * RB * PC);
 #pragma unroll
-    for (int i = 0; i < NPI; ++i) dma_dword(Wdw + poff[i] + zoff, dst + 64 * (wave + NW * i));
-  };
-  auto dma_halo = [&](int z) {    // y halo of plane z (in range) into buffer z & 1
-    const int zoff = z * plane * DPE;
-    unsigned *dst = reinterpret_cast<unsigned *>(haloW + (z & 1) * RB * HS);
+  for (int i = 0; i < NKI; ++i) {
+    const int dw = 64 * (wave + NW * i) + lane;
+    const int j = dw / (64 * DPE), cd = dw % (64 * DPE), cell = cd / DPE;
+    const int gy = clampy(gy0 + (cell >> 4)), gx = clampx(gx0 + (cell & 15));
+    koff[i] = ((min(j, r - 1) * ld + gy * nx + gx) * DPE + cd % DPE) * 4;
+  }
+#pragma unroll
+  for (int i = 0; i < NSI; ++i) {
+    const int idx = wave + NW * i;   // s load: plane part, y-halo part or dummy
+    int gy = 0, gx = 0, half = 0;
+    if (idx < SPD / 64) {
+      const int dw = 64 * idx + lane, cell = min(dw / DPE, PC - 1);
+      half = dw % DPE;
+      gy = clampy(gy0 + cell / RW);
+      gx = clampx(gx0 + cell % RW - 2);
+    } else if (idx < NSX) {
+      const int dw = 64 * (idx - SPD / 64) + lane, hc = dw / DPE;
+      half = dw % DPE;
+      gy = clampy(halo_y(hc >> 4));
+      gx = clampx(gx0 + (hc & 15));
+    }
+    soff[i] = ((gy * nx + gx) * DPE + half) * 4;
+  }
+  auto slot = [](int z) { return (z + 2 * NS) % NS; };
+  // W of ring plane zp, W y halo of plane zh, K0 tile of plane zh, s of both
+  auto issue = [&](int zp, int zh) {
+    const int pb = clampz(zp) * plane * TB, hb = clampz(zh) * plane * TB;
+    unsigned char *dp = reinterpret_cast<unsigned char *>(ringW + slot(zp) * RB * PC);
+    unsigned char *dh = reinterpret_cast<unsigned char *>(haloW + (zh % NB) * RB * HS);
+    unsigned char *dk = reinterpret_cast<unsigned char *>(K0t + (zh % NB) * RB * KST);
+    unsigned char *dsp = reinterpret_cast<unsigned char *>(ringS + slot(zp) * SP);
+    unsigned char *dsh = reinterpret_cast<unsigned char *>(haloS + (zh % NB) * HC);
+#pragma unroll
+    for (int i = 0; i < NPI; ++i) dma_dword(rW, dp + 256 * (wave + NW * i), poff[i], pb);
 #pragma unroll
     for (int i = 0; i < NHI; ++i) {
       const int dw0 = 64 * (wave + NW * i);
-      dma_dword(Wdw + hoff[i] + zoff, dst + (dw0 / HROW_DW) * HS * DPE + dw0 % HROW_DW);
+      dma_dword(rW, dh + 4 * ((dw0 / (HC * DPE)) * HS * DPE + dw0 % (HC * DPE)), hoff[i], hb);
+    }
+#pragma unroll
+    for (int i = 0; i < NKI; ++i) {
+      const int dw0 = 64 * (wave + NW * i);
+      dma_dword(rK, dk + 4 * ((dw0 / (64 * DPE)) * KST * DPE + dw0 % (64 * DPE)), koff[i], hb);
+    }
+#pragma unroll
+    for (int i = 0; i < NSI; ++i) {
+      const int idx = wave + NW * i;
+      if (idx < SPD / 64) dma_dword(rS, dsp + 256 * idx, soff[i], pb);
+      else if (idx < NSX) dma_dword(rS, dsh + 256 * (idx - SPD / 64), soff[i], hb);
+      else dma_dword(rS, pad, soff[i], 0);
     }
   };
-  // s of ring plane zr (threads < PC) or of the y halo of plane zh (next HC threads)
-  auto load_s = [&](int zr, int zh) -> T {
-    if (tid < PC) {
-      const bool in = sxy && zr >= 0 && zr < nz;
-      const T v = s[size_t(min(max(zr, 0), nz - 1)) * plane + soff];
-      return in ? v : T(0);
-    }
-    if (tid < PC + HC) {
-      const T v = s[size_t(zh) * plane + soff];
-      return sxy ? v : T(0);
-    }
-    return T(0);
-  };
-  auto store_s = [&](int zr, int zh, T v) {
-    if (tid < PC) ringS[slot(zr) * PC + tid] = v;
-    else if (tid < PC + HC) haloS[(zh & 1) * HC + tid - PC] = v;
-  };
-  // prologue: planes z0-2 .. z0+2 and the y halo of z0
-  for (int z = z0 - 2; z <= z0 + 2; ++z) {
-    dma_plane(z);
-    const T v = load_s(z, z0);
-    if (tid < PC || z == z0) store_s(z, z0, v);
-  }
-  dma_halo(z0);
-  wait_vm_all();
+  // prologue: ring planes z0-2 .. z0+3, y halos / K0 tiles of z0 and z0+1
+  issue(z0 - 2, z0);
+  issue(z0 - 1, z0 + 1);
+  issue(z0, z0);
+  issue(z0 + 1, z0);
+  issue(z0 + 2, z0);
+  issue(z0 + 3, z0 + 1);
+  wait_vm<0>();
   __syncthreads();
   T ih[DIM];
 #pragma unroll
@@ -427,40 +488,36 @@ __global__ __launch_bounds__(64 * kBrickBY * WJ) void k_kstage_brick(GridDev g, 
   const T tcoef = T(coef);
   const int gx = gx0 + c, gy = gy0 + row;
   const bool valid = gx < nx && gy < ny;
+  const int xyo = (clampy(gy) * nx + clampx(gx)) * TB;
+  // in-grid masks of the x and y stencil neighbours of this lane's cell
+  bool mx[4], my[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int o = t < 2 ? t - 2 : t - 1;
+    mx[t] = gx + o >= 0 && gx + o < nx;
+    my[t] = gy + o >= 0 && gy + o < ny;
+  }
   const int base = row * RW + c + 2;
   for (int z = z0; z < z1; ++z) {
-    const bool more = z + 1 < z1;
-    T snext = T(0);
-    if (more) {
-      dma_plane(z + 3);
-      dma_halo(z + 1);
-      snext = load_s(z + 3, z + 1);
-    }
-    const int xo = (z * ny + min(gy, ny - 1)) * nx + min(gx, nx - 1);
-    T k0v[NJW][4];
-#pragma unroll
-    for (int jt = 0; jt < NJW; ++jt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        k0v[jt][v] = K0[size_t(min(16 * (jt0 + jt) + Mfma<T>::row(q, v), r - 1)) * ld + xo];
-    // stencil points: centre, then (d, -2, -1, +1, +2); y rows outside the
-    // brick come from the halo buffer (a wave-uniform choice)
-    const int sc = slot(z), hb = z & 1;
-    const T *Wc = ringW + sc * RB * PC, *Sc = ringS + sc * PC;
-    const T *wp[DIM][4], *sp[DIM][4];
+    const int sc = slot(z), hb = z % NB;
+    const T *Wc = ringW + sc * RB * PC, *Sc = ringS + sc * SP;
+    const T *wp[DIM][4];
+    T sv[DIM][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int o = t < 2 ? t - 2 : t - 1;
       wp[0][t] = Wc + base + o;
-      sp[0][t] = Sc + base + o;
+      sv[0][t] = mx[t] ? Sc[base + o] : T(0);
       const int yr = row + o;
       const bool inb = yr >= 0 && yr < BY;
       const int hr = yr < 0 ? yr + 2 : yr - BY + 2;
       wp[1][t] = inb ? Wc + yr * RW + c + 2 : haloW + hb * RB * HS + hr * 16 + c;
-      sp[1][t] = inb ? Sc + yr * RW + c + 2 : haloS + hb * HC + hr * 16 + c;
+      const T syv = inb ? Sc[yr * RW + c + 2] : haloS[hb * HC + hr * 16 + c];
+      sv[1][t] = my[t] ? syv : T(0);
       if constexpr (DIM == 3) {
         wp[2][t] = ringW + slot(z + o) * RB * PC + base;
-        sp[2][t] = ringS + slot(z + o) * PC + base;
+        const bool mz = z + o >= 0 && z + o < nz;
+        sv[2][t] = mz ? ringS[slot(z + o) * SP + base] : T(0);
       }
     }
     // s-weights of the one-sided differences (ih folded in)
@@ -469,15 +526,15 @@ __global__ __launch_bounds__(64 * kBrickBY * WJ) void k_kstage_brick(GridDev g, 
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       cb[d][0] = T(3) * ih[d] * s0;
-      cb[d][1] = T(-4) * ih[d] * *sp[d][1];
-      cb[d][2] = ih[d] * *sp[d][0];
+      cb[d][1] = T(-4) * ih[d] * sv[d][1];
+      cb[d][2] = ih[d] * sv[d][0];
       cf[d][0] = T(-3) * ih[d] * s0;
-      cf[d][1] = T(4) * ih[d] * *sp[d][2];
-      cf[d][2] = -ih[d] * *sp[d][3];
+      cf[d][1] = T(4) * ih[d] * sv[d][2];
+      cf[d][2] = -ih[d] * sv[d][3];
     }
-    acc_t acc[NJW];
+    acc_t acc[NJ];
 #pragma unroll
-    for (int jt = 0; jt < NJW; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+    for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int kq = 0; kq < KS; ++kq) {
       const int ok = (4 * kq + q) * PC;   // column offset (PC == HS)
@@ -488,24 +545,32 @@ __global__ __launch_bounds__(64 * kBrickBY * WJ) void k_kstage_brick(GridDev g, 
         const T db = cb[d][2] * wm2 + (cb[d][1] * wm1 + cb[d][0] * w0);
         const T df = cf[d][2] * wp2 + (cf[d][1] * wp1 + cf[d][0] * w0);
 #pragma unroll
-        for (int jt = 0; jt < NJW; ++jt) {
+        for (int jt = 0; jt < NJ; ++jt) {
           acc[jt] = Mfma<T>::op(bq[d][kq][jt][0], db, acc[jt]);
           acc[jt] = Mfma<T>::op(bq[d][kq][jt][1], df, acc[jt]);
         }
       }
     }
+    const T *Kt = K0t + hb * RB * KST + row * 16 + c;
+    const int zb = z * plane * TB;
 #pragma unroll
-    for (int jt = 0; jt < NJW; ++jt) {
+    for (int jt = 0; jt < NJ; ++jt) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * (jt0 + jt) + Mfma<T>::row(q, v);
-        if (valid && j < r) out[size_t(j) * ld + xo] = k0v[jt][v] - tcoef * acc[jt][v];
+        const int j = 16 * jt + Mfma<T>::row(q, v);
+        const T k0 = Kt[j * KST];
+        if (valid && j < r) buf_store(k0 - tcoef * acc[jt][v], rO, xyo + j * ld * TB, zb);
       }
     }
-    if (more) store_s(z + 3, z + 1, snext);
-    wait_vm_all();
-    __syncthreads();
+    // two steps ahead: ring plane z+4, y halo / K0 tile / s of z+2; the loads
+    // issued one step ago must have landed before the barrier, this step's
+    // may stay in flight (past the chunk end they are clamped into the grid
+    // and fill buffers no later step reads)
+    issue(z + 4, z + 2);
+    wait_vm<NLOADS>();
+    block_barrier();
   }
+  wait_vm<0>();   // no load into LDS outlives the block
 }
 
 // Tall-skinny contractions on the matrix cores.  Per block a chunk of cells,
@@ -825,10 +890,9 @@ static void kstage_launch(const GridDev &g, const T *s, const T *W, const T *K0,
 template <typename T, int NJ, int DIM>
 static void kstage_brick_launch(const GridDev &g, const T *s, const T *W, const T *K0, T *out,
                                 int ld, int r, const T *Bp, double coef, hipStream_t st) {
-  constexpr int WJ = NJ;   // one wave per row and 16-column tile
-  constexpr int NT = 64 * kBrickBY * WJ;
+  constexpr int NT = 64 * kBrickBY;
   const size_t shm = brick_lds_bytes(16 * NJ, int(sizeof(T)));
-  auto kern = k_kstage_brick<T, NJ, DIM, WJ>;
+  auto kern = k_kstage_brick<T, NJ, DIM>;
   static std::atomic<int> blocks_cache{0};
   int cap = blocks_cache.load(std::memory_order_relaxed);
   if (cap <= 0) {
@@ -858,8 +922,10 @@ static void kstage_brick_launch(const GridDev &g, const T *s, const T *W, const 
 template <typename T>
 void launch_kstep_stage(const GridDev &g, const T *s, const T *W, const T *K0, T *out, int ld,
                         int r, const T *Bp, double coef, hipStream_t st) {
-  // z-march kernel where its LDS fits: r <= 32 in FP32, r <= 16 in FP64
-  if (kUseBrick && r <= (sizeof(T) == 4 ? 32 : 16)) {
+  // z-march kernel where its LDS fits (r <= 32 in FP32, r <= 16 in FP64) and
+  // its buffer offsets fit 31 bits
+  if (kUseBrick && r <= (sizeof(T) == 4 ? 32 : 16) &&
+      size_t(ld) * 16 * ((r + 15) / 16) * sizeof(T) < (size_t(1) << 31)) {
     const bool three = g.dim == 3;
     if (r <= 16 && three) kstage_brick_launch<T, 1, 3>(g, s, W, K0, out, ld, r, Bp, coef, st);
     else if (r <= 16) kstage_brick_launch<T, 1, 2>(g, s, W, K0, out, ld, r, Bp, coef, st);
