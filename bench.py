@@ -116,7 +116,7 @@ def kstage_algorithmic(problem):
     return flops, nbytes
 
 
-def cpu_baseline(problem, budget_planes=8):
+def cpu_baseline(problem, budget_planes=32):
     """Time one reference (CPU, FP64) step on a z-slab of the phantom from a
     seeded random rank-r state at the step whose substep count is closest to
     the run's mean, and scale to the whole phantom."""
