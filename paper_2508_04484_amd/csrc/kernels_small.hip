@@ -115,10 +115,21 @@ __device__ void blk_gemm_tn(int M, int N, int K, double alpha, const double *A, 
 
 // One-sided Jacobi: orthogonalise the q columns (length p) of A, accumulating
 // the rotations in V (q x q, initialised here).  Parallel round-robin
-// ordering, 8 lanes per column pair.
-__device__ void blk_jacobi(double *A, int lda, int p, int q, double *V, int ldv, int *flag) {
+// ordering, 8 lanes per column pair.  A pair is rotated when its inner
+// product is above 1e-15 of the columns' norms and above 1e-30 ||A||_F^2:
+// pairs of columns that are both negligible against the matrix (singular
+// values below ~1e-15 of the largest) carry only rounding noise, and
+// rotating them would keep the sweeps from terminating.
+__device__ void blk_jacobi(double *A, int lda, int p, int q, double *V, int ldv, int *flag,
+                           double *red) {
   const int tid = threadIdx.x;
   for (int e = tid; e < q * q; e += blockDim.x) V[(e % q) + size_t(e / q) * ldv] = (e % q == e / q) ? 1.0 : 0.0;
+  double fro = 0.0;
+  for (int e = tid; e < p * q; e += blockDim.x) {
+    const double a = A[(e % p) + size_t(e / p) * lda];
+    fro += a * a;
+  }
+  const double tiny = 1e-30 * blk_sum(fro, red);
   __syncthreads();
   const int qe = q + (q & 1);
   if (qe < 2) return;
@@ -158,7 +169,8 @@ __device__ void blk_jacobi(double *A, int lda, int p, int q, double *V, int ldv,
           be += __shfl_xor(be, o, 8);
           ga += __shfl_xor(ga, o, 8);
         }
-        if (valid && al > 0.0 && be > 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+        if (valid && al > 0.0 && be > 0.0 && fabs(ga) > 1e-15 * sqrt(al * be) &&
+            fabs(ga) > tiny) {
           double zeta = (be - al) / (2.0 * ga);
           double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
@@ -246,31 +258,41 @@ __global__ __launch_bounds__(256) void k_sstep_stage(int P, int ld, int ndk,
                                                     const double *__restrict__ Ch,
                                                     const double *__restrict__ Bh,
                                                     const double *S0, const double *__restrict__ W,
-                                                    double *out, double coef) {
+                                                    double *out, double coef, int c_in_lds) {
   extern __shared__ double smem_d[];
   double *Ws = smem_d;                 // P x P
-  double *Ts = smem_d + P * P;         // P x kSJ
+  double *Ts = Ws + P * P;             // P x kSJ
+  double *Bs = Ts + P * kSJ;           // P x kSJ
+  double *Cs = Bs + P * kSJ;           // P x P (when c_in_lds)
   const int j0 = blockIdx.x * kSJ;
   const int nj = min(kSJ, P - j0);
   for (int e = threadIdx.x; e < P * P; e += blockDim.x) Ws[e] = W[(e % P) + size_t(e / P) * ld];
   double F[(kSMaxOut + 255) / 256];
   for (int u = 0; u < (kSMaxOut + 255) / 256; ++u) F[u] = 0.0;
-  __syncthreads();
   for (int dk = 0; dk < ndk; ++dk) {
     const double *C = Ch + size_t(dk) * ld * ld;
     const double *B = Bh + size_t(dk) * ld * ld;
+    // stage this term's coupling columns B(:, J) and, when it fits, C in LDS
+    // (coalesced, all loads in flight together)
+    for (int e = threadIdx.x; e < P * nj; e += blockDim.x)
+      Bs[e] = B[(e % P) + size_t(j0 + e / P) * ld];
+    if (c_in_lds)
+      for (int e = threadIdx.x; e < P * P; e += blockDim.x) Cs[e] = C[(e % P) + size_t(e / P) * ld];
+    __syncthreads();
     for (int e = threadIdx.x; e < P * nj; e += blockDim.x) {
-      int i = e % P, jj = e / P;
-      const double *Bj = B + size_t(j0 + jj) * ld;
+      const int i = e % P, jj = e / P;
       double acc = 0.0;
-      for (int k = 0; k < P; ++k) acc += Ws[i + k * P] * Bj[k];
+      for (int k = 0; k < P; ++k) acc += Ws[i + k * P] * Bs[k + jj * P];
       Ts[i + jj * P] = acc;
     }
     __syncthreads();
     for (int u = 0, e = threadIdx.x; e < P * nj; ++u, e += blockDim.x) {
-      int i = e % P, jj = e / P;
+      const int i = e % P, jj = e / P;
       double acc = 0.0;
-      for (int k = 0; k < P; ++k) acc += C[i + size_t(k) * ld] * Ts[k + jj * P];
+      if (c_in_lds)
+        for (int k = 0; k < P; ++k) acc += Cs[i + k * P] * Ts[k + jj * P];
+      else
+        for (int k = 0; k < P; ++k) acc += C[i + size_t(k) * ld] * Ts[k + jj * P];
       F[u] -= acc;
     }
     __syncthreads();
@@ -320,7 +342,7 @@ __global__ __launch_bounds__(kWG) void k_gram_orth(int q, const double *__restri
   }
   for (int e = threadIdx.x; e < q * q; e += blockDim.x) T[(e % q) + size_t(e / q) * ldt] = 0.0;
   __syncthreads();
-  blk_jacobi(A, qq, qq, qq, V, qq, &flag);
+  blk_jacobi(A, qq, qq, qq, V, qq, &flag, red);
   __syncthreads();
   // for the PSD W, the column norms of W V are its eigenvalues
   blk_colnorms_sorted(A, qq, qq, qq, sig, order);
@@ -334,7 +356,6 @@ __global__ __launch_bounds__(kWG) void k_gram_orth(int q, const double *__restri
     T[i + size_t(c) * ldt] = V[i + j * qq] / sqrt(sig[j]);
   }
   if (threadIdx.x == 0 && count != nullptr && restrict_count == nullptr) *count = kept;
-  (void)red;
 }
 
 // ------------------------------------------------------------------ V augmentation
@@ -368,7 +389,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
     __syncthreads();
   }
   blk_gemm_tn(r, r, m, 1.0, R, m, R, m, W, r);                           // W = R^T R
-  blk_jacobi(W, r, r, r, Q, r, &flag);
+  blk_jacobi(W, r, r, r, Q, r, &flag, red);
   __syncthreads();
   blk_colnorms_sorted(W, r, r, r, sig, order);
   const double thresh = tol * tol * nl;
@@ -395,7 +416,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
     }
     __syncthreads();
     blk_gemm_tn(kept, kept, m, 1.0, X, m, X, m, W, kept);
-    blk_jacobi(W, kept, kept, kept, Q, kept, &flag);
+    blk_jacobi(W, kept, kept, kept, Q, kept, &flag, red);
     __syncthreads();
     blk_colnorms_sorted(W, kept, kept, kept, sig, order);
     for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
@@ -437,7 +458,7 @@ __global__ __launch_bounds__(kWG) void k_truncate(const double *__restrict__ Sh,
     A[i + j * p] = cols ? Sh[i + j * P] : Sh[j + i * P];
   }
   __syncthreads();
-  blk_jacobi(A, p, p, q, V, q, &flag);
+  blk_jacobi(A, p, p, q, V, q, &flag, red);
   __syncthreads();
   blk_colnorms_sorted(A, p, p, q, sig, order);
   // rank
@@ -637,7 +658,9 @@ void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C,
 void launch_sstep(int p, int ld, int ndk, const double *Ch, const double *Bh, double *S,
                   double *work, double h, int n_sub, hipStream_t st) {
   double *Wa = work, *Wb = work + size_t(ld) * ld;
-  const size_t shm = (size_t(p) * p + size_t(p) * kSJ) * sizeof(double);
+  size_t shm = (size_t(p) * p + 2 * size_t(p) * kSJ) * sizeof(double);
+  const int c_in_lds = shm + size_t(p) * p * sizeof(double) <= 150 * 1024 ? 1 : 0;
+  if (c_in_lds) shm += size_t(p) * p * sizeof(double);
   if (shm > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sstep_stage),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
@@ -648,7 +671,7 @@ void launch_sstep(int p, int ld, int ndk, const double *Ch, const double *Bh, do
     double *outs[4] = {Wa, Wb, Wa, S};
     for (int stage = 0; stage < 4; ++stage) {
       k_sstep_stage<<<blocks, 256, shm, st>>>(p, ld, ndk, Ch, Bh, S, in, outs[stage],
-                                              cf[stage] * h);
+                                              cf[stage] * h, c_in_lds);
       in = outs[stage];
     }
   }

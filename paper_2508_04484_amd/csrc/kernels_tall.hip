@@ -656,6 +656,108 @@ __global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__res
   }
 }
 
+// Stencil projections C_dk = X^T D_dk(s o X) of one direction d (blockIdx.y)
+// on the matrix cores: both one-sided differences (dk = 2d, 2d + 1) come from
+// the same five stencil points, so a block stages the X tile once and the two
+// difference tiles from one set of loads (clamped, unconditional, masked by a
+// select).  Four waves; wave w owns the 16-column tiles w, w + 4 of the right
+// factor for all 16-row tiles of the left one.  Partial sums of block bx go
+// to partial[(bx * 2 dim + dk) * p * p].
+template <typename T, typename Tc, int NA>
+__global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__restrict__ s,
+                                                     const T *__restrict__ X, int ldx, int p,
+                                                     int chunk, double *__restrict__ partial) {
+  using acc_t = typename Mfma<Tc>::acc_t;
+  constexpr int CT = sizeof(Tc) == 8 ? 32 : 64;   // cells per staged tile
+  constexpr int PA = 16 * NA + 1;                 // row length (odd: no bank conflicts)
+  constexpr int NBT = (NA + 3) / 4;               // right-factor tiles per wave
+  constexpr int PER = CT * 16 * NA / 256;         // staged elements per thread
+  static_assert((CT * 16 * NA) % 256 == 0, "whole staging rounds");
+  extern __shared__ unsigned char smem_raw[];
+  Tc *Xs = reinterpret_cast<Tc *>(smem_raw);      // [CT][PA]
+  Tc *Yb = Xs + CT * PA;                          // [CT][PA]
+  Tc *Yf = Yb + CT * PA;                          // [CT][PA]
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int c = lane & 15, qq = lane >> 4;
+  const int d = blockIdx.y;
+  const int st = d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny);
+  const int size = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+  const T ih = T(g.inv2h[d]);
+  acc_t ab[NBT][NA], af[NBT][NA];
+#pragma unroll
+  for (int bt = 0; bt < NBT; ++bt)
+#pragma unroll
+    for (int at = 0; at < NA; ++at) ab[bt][at] = af[bt][at] = acc_t{0, 0, 0, 0};
+  const int x_begin = blockIdx.x * chunk;
+  const int x_end = min(g.n, x_begin + chunk);
+  for (int x0 = x_begin; x0 < x_end; x0 += CT) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + 256 * i, cc = e % CT, a = e / CT;
+      const int x = x0 + cc, xc = min(x, x_end - 1);
+      const Tc v = Tc(X[size_t(min(a, p - 1)) * ldx + xc]);
+      Xs[cc * PA + a] = (x < x_end && a < p) ? v : Tc(0);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + 256 * i, cc = e % CT, b = e / CT;
+      const int x = x0 + cc, xc = min(x, x_end - 1);
+      const int cd = d == 0 ? xc % g.nx : (d == 1 ? (xc / g.nx) % g.ny : xc / (g.nx * g.ny));
+      const bool m1 = cd >= 1, m2 = cd >= 2, p1 = cd + 1 < size, p2 = cd + 2 < size;
+      const int im1 = m1 ? xc - st : xc, im2 = m2 ? xc - 2 * st : xc;
+      const int ip1 = p1 ? xc + st : xc, ip2 = p2 ? xc + 2 * st : xc;
+      const T *col = X + size_t(min(b, p - 1)) * ldx;
+      const T v0 = s[xc] * col[xc];
+      const T am1 = s[im1] * col[im1], am2 = s[im2] * col[im2];
+      const T ap1 = s[ip1] * col[ip1], ap2 = s[ip2] * col[ip2];
+      const T vm1 = m1 ? am1 : T(0), vm2 = m2 ? am2 : T(0);
+      const T vp1 = p1 ? ap1 : T(0), vp2 = p2 ? ap2 : T(0);
+      const T db = (T(3) * v0 - T(4) * vm1 + vm2) * ih;
+      const T df = -(T(3) * v0 - T(4) * vp1 + vp2) * ih;
+      const bool ok = x < x_end && b < p;
+      Yb[cc * PA + b] = ok ? Tc(db) : Tc(0);
+      Yf[cc * PA + b] = ok ? Tc(df) : Tc(0);
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int k4 = 0; k4 < CT / 4; ++k4) {
+      const int cell = 4 * k4 + qq;
+#pragma unroll
+      for (int bt = 0; bt < NBT; ++bt) {
+        const int btile = w + 4 * bt;
+        if (btile < NA) {
+          const Tc yb = Yb[cell * PA + btile * 16 + c], yf = Yf[cell * PA + btile * 16 + c];
+#pragma unroll
+          for (int at = 0; at < NA; ++at) {
+            const Tc xa = Xs[cell * PA + at * 16 + c];
+            ab[bt][at] = Mfma<Tc>::op(xa, yb, ab[bt][at]);
+            af[bt][at] = Mfma<Tc>::op(xa, yf, af[bt][at]);
+          }
+        }
+      }
+    }
+  }
+  const size_t pq = size_t(p) * p;
+  double *outb = partial + (size_t(blockIdx.x) * 2 * gridDim.y + 2 * d) * pq;
+  double *outf = outb + pq;
+#pragma unroll
+  for (int bt = 0; bt < NBT; ++bt) {
+    const int b = (w + 4 * bt) * 16 + c;
+#pragma unroll
+    for (int at = 0; at < NA; ++at) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = at * 16 + Mfma<Tc>::row(qq, v);
+        if (a < p && b < p) {
+          outb[a + size_t(b) * p] = double(ab[bt][at][v]);
+          outf[a + size_t(b) * p] = double(af[bt][at][v]);
+        }
+      }
+    }
+  }
+}
+
 // Bp[(dk RB + k) RB + j] = B_dk(k, j) (zero padded to RB), from the
 // column-major double couplings (leading dimension ldb, blocks ldb^2 apart).
 template <typename T>
@@ -989,14 +1091,40 @@ static void contract(const GridDev &g, const T *s, const T *X, int ldx, int p, Y
   nb_out = nb;
 }
 
+template <typename T, typename Acc, int NA>
+static void stencil_proj_launch(const GridDev &g, const T *s, const T *X, int ld, int p, int nb,
+                                int chunk, double *partial, hipStream_t st) {
+  constexpr int CT = sizeof(Acc) == 8 ? 32 : 64;
+  const size_t shm = size_t(3) * CT * (16 * NA + 1) * sizeof(Acc);
+  auto kern = k_stencil_proj<T, Acc, NA>;
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+  kern<<<dim3(nb, g.dim), 256, shm, st>>>(g, s, X, ld, p, chunk, partial);
+}
+
 template <typename T, typename Acc>
 void launch_stencil_projection(const GridDev &g, const T *s, const T *X, int ld, int p,
                                double *C, int ldc, double *partial, size_t partial_elems,
                                hipStream_t st) {
   const int ndk = 2 * g.dim;
-  int nb = 0;
-  contract<T, Acc, true>(g, s, X, ld, p, YMat<T>{X, ld}, p, WOne<T>{}, ndk, partial,
-                         partial_elems, st, nb);
+  const size_t pq = size_t(p) * p;
+  constexpr int CT = sizeof(Acc) == 8 ? 32 : 64;
+  int nb = (kContractWaves + 4 * g.dim - 1) / (4 * g.dim);
+  nb = std::max(1, std::min({nb, kMaxPartialBlocks, (g.n + CT - 1) / CT}));
+  while (nb > 1 && size_t(nb + 1) * ndk * pq > partial_elems) nb /= 2;
+  int chunk = (g.n + nb - 1) / nb;
+  chunk = (chunk + CT - 1) / CT * CT;
+  nb = (g.n + chunk - 1) / chunk;
+  switch ((p + 15) / 16) {
+    case 1: stencil_proj_launch<T, Acc, 1>(g, s, X, ld, p, nb, chunk, partial, st); break;
+    case 2: stencil_proj_launch<T, Acc, 2>(g, s, X, ld, p, nb, chunk, partial, st); break;
+    case 3: stencil_proj_launch<T, Acc, 3>(g, s, X, ld, p, nb, chunk, partial, st); break;
+    case 4: stencil_proj_launch<T, Acc, 4>(g, s, X, ld, p, nb, chunk, partial, st); break;
+    case 5: stencil_proj_launch<T, Acc, 5>(g, s, X, ld, p, nb, chunk, partial, st); break;
+    case 6: stencil_proj_launch<T, Acc, 6>(g, s, X, ld, p, nb, chunk, partial, st); break;
+    default: stencil_proj_launch<T, Acc, 7>(g, s, X, ld, p, nb, chunk, partial, st); break;
+  }
   const size_t per = size_t(ndk) * p * p;
   double *red = partial + size_t(nb) * per;
   reduce_partials(partial, nb, int(per), red, st);
