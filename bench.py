@@ -172,12 +172,94 @@ def cpu_baseline(problem, budget_planes=32):
     }
 
 
+def bench_batch(problem, args):
+    """beams/s of B beams of a treatment plan: one after another through the
+    single-beam path (plain) and all together through the batch scheduler
+    (each beam on its own stream, one host thread per beam).  Per beam: ray
+    trace + all energy steps; inputs resident before timing; doses checked
+    bitwise equal between the two runs."""
+    import torch
+
+    import paper_2508_04484_amd as dl
+    B = max(1, min(args.beams, len(problem.beams)))
+    idx = list(range(B))
+    # warm-up (code objects, allocator): one beam, a few steps
+    s = dl.BeamSolver(problem, 0)
+    s.raytrace()
+    for _ in range(min(3, problem.options.n_steps)):
+        s.step()
+    s.sync()
+    s.close()
+    del s
+    torch.cuda.synchronize()
+    plain_dose = []
+    t_plain = 0.0
+    for b in idx:
+        s = dl.BeamSolver(problem, b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.raytrace()
+        s.run()
+        torch.cuda.synchronize()
+        dt_b = time.perf_counter() - t0
+        t_plain += dt_b
+        print(f"plain beam {b}: {problem.beams[b].E0:.1f} MeV, {dt_b:.2f} s", file=sys.stderr,
+              flush=True)
+        plain_dose.append(s.dose().cpu())
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    solvers = dl.batch_solvers(problem, idx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_steps = problem.options.n_steps
+    for k0 in range(0, n_steps, 50):   # chunks of 50 energy steps (progress lines)
+        dl.run_batch(solvers, n_steps=min(50, n_steps - k0))
+        print(f"batched: steps {k0}..{min(k0 + 50, n_steps) - 1} done, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"batched: {B} beams, {t_batch:.2f} s", file=sys.stderr, flush=True)
+    same = all(torch.equal(s.dose().cpu(), plain_dose[b]) for b, s in enumerate(solvers))
+    for s in solvers:
+        s.close()
+    o = problem.options
+    g = problem.grid
+    out = {
+        "metric": "beams/s batched vs plain",
+        "value": round(B / t_batch, 5),
+        "unit": "beams/s",
+        "n_gpus": 1,
+        "steps": o.n_steps,
+        "warmup": 1,
+        "ms_per_step": round(1000.0 * t_batch / o.n_steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if o.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"{problem.name}: {B} of the plan's beams on {g.nx}x{g.ny}x{g.nz} "
+                                f"voxels of {g.dx * 10:g} mm, P_{o.pn_degree}, adaptive rank "
+                                f"[{o.r_min}, {o.r_max}], {o.n_steps} energy steps per beam, "
+                                f"{o.precision}"),
+                   "beams": B,
+                   "energies_MeV": [round(problem.beams[b].E0, 1) for b in idx]},
+        "plain_beams_per_s": round(B / t_plain, 5),
+        "batched_over_plain": round(t_plain / t_batch, 4),
+        "plain_s": round(t_plain, 3), "batched_s": round(t_batch, 3),
+        "doses_bitwise_equal": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=250)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4_axis"])
+    ap.add_argument("--beams", type=int, default=8,
+                    help="c4_axis: number of the plan's beams timed plain and batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (a known-size "
@@ -210,6 +292,8 @@ def main():
         del a, b
     problem = configs.CONFIGS[args.config]()
     o = problem.options
+    if args.config == "c4_axis":
+        return bench_batch(problem, args)
     K = min(args.steps, o.n_steps)
 
     # warm-up: a separate solver runs W steps (code objects, allocator, caches)

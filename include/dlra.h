@@ -182,6 +182,23 @@ int dlra_substeps(dlra_ctx *ctx, int k, int *n_sub);
 /* Waits for the context's stream. */
 int dlra_sync(dlra_ctx *ctx);
 
+/* Batched beams.  The paper treats one pencil beam per solve; a treatment
+ * plan has many independent beams (Sec. 1, Sec. 4).  This entry point
+ * advances several contexts (one beam each, each on its own stream) at once so
+ * that the kernels of different beams overlap on the device: host thread t of
+ * n_threads (n_threads <= 0: one thread per context) drives contexts t,
+ * t + n_threads, ...; each context that has not yet traced its uncollided
+ * flux does so first, then up to n_steps energy steps follow, interleaved
+ * across the thread's contexts (a context stops at its last step), and
+ * finally every stream is waited for.  The result of every context is the
+ * one dlra_step alone would give (no data is shared between contexts).
+ *   ctxs      host array of n_ctx distinct contexts, not used by other
+ *             threads during the call; n_ctx >= 0, n_steps >= 0
+ *   returns   DLRA_OK, or the first error raised in any context (the other
+ *             workers stop at their next step; the message is available
+ *             from dlra_last_error() in the calling thread). */
+int dlra_run_batch(dlra_ctx *const *ctxs, int n_ctx, int n_steps, int n_threads);
+
 /* Timing of the library's own work with HIP events recorded on the context's
  * stream (measurement support; adds one event pair per timed launch).
  *   dlra_profile(ctx, on): on = 1 starts recording, 0 stops; counters are

@@ -23,8 +23,8 @@ DOSE_UNCOLLIDED, DOSE_COLLIDED, DOSE_PER_MASS = 1, 2, 4
 
 EXPORTS = ["dlra_workspace_size", "dlra_init", "uncollided_raytrace", "dlra_step",
            "dose_deposit", "dlra_get_state", "dlra_set_state", "dlra_get_uncollided",
-           "dlra_substeps", "dlra_sync", "dlra_profile", "dlra_profile_read", "dlra_destroy",
-           "dlra_last_error"]
+           "dlra_substeps", "dlra_sync", "dlra_profile", "dlra_profile_read", "dlra_run_batch",
+           "dlra_destroy", "dlra_last_error"]
 PHASES = ["kstage", "projection", "lstep", "augment", "sstep", "truncate", "collided", "source",
           "step", "raytrace"]
 
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
     lib.dlra_sync.argtypes = [P]
     lib.dlra_profile.argtypes = [P, I]
     lib.dlra_profile_read.argtypes = [P, I, D, C.POINTER(C.c_longlong)]
+    lib.dlra_run_batch.argtypes = [C.POINTER(P), I, I, I]
     lib.dlra_destroy.argtypes = [P]
     lib.dlra_destroy.restype = None
     lib.dlra_last_error.restype = C.c_char_p
@@ -243,6 +244,25 @@ class BeamSolver:
         Du = np.zeros(self.n)
         check(self.lib.dlra_get_uncollided(self.ctx, _dptr(ps), _dptr(Du)))
         return ps, Du
+
+
+def run_batch(solvers, n_steps=None, n_threads=0):
+    """Advance several BeamSolvers (each on its own stream) together through the
+    library's batch scheduler: ray traces first where missing, then n_steps
+    energy steps (default: all), concurrently; returns when all are done."""
+    if not solvers:
+        return
+    lib = solvers[0].lib
+    n_steps = max(s.problem.options.n_steps for s in solvers) if n_steps is None else n_steps
+    arr = (C.c_void_p * len(solvers))(*[s.ctx.value for s in solvers])
+    check(lib.dlra_run_batch(arr, len(solvers), int(n_steps), int(n_threads)))
+
+
+def batch_solvers(problem, beam_indices=None):
+    """One BeamSolver per beam, each on a stream of its own (default priority)."""
+    import torch
+    idx = range(len(problem.beams)) if beam_indices is None else beam_indices
+    return [BeamSolver(problem, b, stream=torch.cuda.Stream()) for b in idx]
 
 
 def solve(problem, n_steps=None):

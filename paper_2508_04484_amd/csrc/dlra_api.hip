@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
@@ -9,6 +10,8 @@
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <thread>
+#include <mutex>
 #include <vector>
 
 #include "dlra.h"
@@ -204,6 +207,7 @@ struct dlra_ctx {
   GridDev gdev;
   hipStream_t st = nullptr;
   hipStream_t st2 = nullptr;            // side stream of the L-step (default priority)
+  int device = 0;                       // HIP device the context was created on
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   char *base = nullptr;
   // host-side state
@@ -892,6 +896,7 @@ int dlra_init(const dlra_grid *grid, const dlra_materials *mat, const dlra_beam 
   c->opt = *opt;
   c->beam = *beam;
   c->st = reinterpret_cast<hipStream_t>(stream);
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
   if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
@@ -1088,6 +1093,59 @@ int dlra_profile_read(dlra_ctx *c, int phase, double *total_ms, long long *count
 }
 
 void dlra_destroy(dlra_ctx *c) { delete c; }
+
+int dlra_run_batch(dlra_ctx *const *ctxs, int n_ctx, int n_steps, int n_threads) {
+  if (!ctxs || n_ctx < 0 || n_steps < 0) return fail(DLRA_E_INVALID, "bad batch arguments");
+  for (int i = 0; i < n_ctx; ++i) {
+    if (!ctxs[i]) return fail(DLRA_E_INVALID, "ctx is NULL");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(DLRA_E_INVALID, "a context appears twice in the batch");
+  }
+  if (n_ctx == 0) return DLRA_OK;
+  const int nt = n_threads <= 0 ? n_ctx : std::min(n_threads, n_ctx);
+  std::atomic<bool> stop{false};
+  std::mutex mu;
+  int first_rc = DLRA_OK;
+  std::string first_msg;
+  auto record = [&](int rc) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (first_rc == DLRA_OK) {
+      first_rc = rc;
+      first_msg = g_err;   // this worker's message
+    }
+    stop = true;
+  };
+  // worker t drives contexts t, t + nt, ...: ray trace, then the energy
+  // steps interleaved across its contexts, then a wait on their streams
+  auto worker = [&](int t) {
+    if (hipSetDevice(ctxs[t]->device) != hipSuccess) {
+      g_err = "hipSetDevice failed";
+      record(DLRA_E_HIP);
+      return;
+    }
+    for (int i = t; i < n_ctx && !stop; i += nt)
+      if (!ctxs[i]->traced) {
+        const int rc = uncollided_raytrace(ctxs[i]);
+        if (rc != DLRA_OK) return record(rc);
+      }
+    for (int k = 0; k < n_steps && !stop; ++k)
+      for (int i = t; i < n_ctx && !stop; i += nt)
+        if (ctxs[i]->step < ctxs[i]->d.n_steps) {
+          const int rc = dlra_step(ctxs[i], nullptr);
+          if (rc != DLRA_OK) return record(rc);
+        }
+    for (int i = t; i < n_ctx; i += nt) {
+      const int rc = dlra_sync(ctxs[i]);
+      if (rc != DLRA_OK) return record(rc);
+    }
+  };
+  std::vector<std::thread> pool;
+  pool.reserve(nt);
+  for (int t = 0; t < nt; ++t) pool.emplace_back(worker, t);
+  for (auto &th : pool) th.join();
+  if (first_rc != DLRA_OK) g_err = first_msg;
+  return first_rc;
+}
 
 const char *dlra_last_error(void) { return g_err.c_str(); }
 

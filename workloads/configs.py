@@ -17,6 +17,7 @@ beams with 1% energy spread, Sec. 4) at the sizes of the benchmark workloads:
       fixed rank 30, 250 steps, mixed precision
   c4  c3's phantom with 64 beams: energies U[70, 230] MeV, axial angles
       U[0, 2 pi), spot sigma U[3, 6] mm, adaptive ranks in [10, 50]
+  c4_axis  c4 with the beam directions snapped to the nearest axial grid axis
   c5  c2's phantom with 9 beams of 100 + 10 b MeV at 40 b degrees aimed at the
       centre (adjoint workload)
 
@@ -162,6 +163,25 @@ def c4(n_beams=64, **opt) -> Problem:
     return Problem(p.grid, p.materials, beams, o, name="c4", meta=p.meta)
 
 
+def c4_axis(n_beams=64, **opt) -> Problem:
+    """c4 with every beam direction snapped to the nearest grid axis of the
+    axial plane (+x, +y, -x, -y), entering at the centre of that face; the
+    energies, spot sizes and rank options are c4's draws."""
+    p = c4(n_beams=n_beams, **opt)
+    rng = np.random.Generator(np.random.PCG64(4))
+    rng.uniform(70.0, 230.0, n_beams)
+    ang = rng.uniform(0.0, 2.0 * math.pi, n_beams)
+    c = (6.4, 6.4, 6.4)
+    axes = [(1.0, 0.0), (0.0, 1.0), (-1.0, 0.0), (0.0, -1.0)]
+    beams = []
+    for b, beam in enumerate(p.beams):
+        ux, uy = axes[int(round(ang[b] / (math.pi / 2.0))) % 4]
+        pos = (c[0] - 6.4 * ux, c[1] - 6.4 * uy, c[2])
+        beams.append(Beam(E0=beam.E0, sigma_E=beam.sigma_E, spot_sigma=beam.spot_sigma,
+                          pos=pos, dir=(ux, uy, 0.0)))
+    return Problem(p.grid, p.materials, beams, p.options, name="c4_axis", meta=p.meta)
+
+
 def c5(**opt) -> Problem:
     p = c2(**opt)
     c = (5.0, 5.0, 0.0)
@@ -169,7 +189,7 @@ def c5(**opt) -> Problem:
     return Problem(p.grid, p.materials, beams, p.options, name="c5")
 
 
-CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c4_axis": c4_axis, "c5": c5}
 
 
 # ---------------------------------------------------------------- small cases
