@@ -260,11 +260,11 @@ __global__ __launch_bounds__(256) void k_kstage_mfma(GridDev g, const T *__restr
 
 // K-step stage with an LDS z-march (r <= 32 in FP32, r <= 16 in FP64).  A
 // block owns a brick column of 16 (x) x 4 (y) cells and a chunk of z planes
-// and marches through z.  The LDS holds a ring of seven planes of W (each
-// brick row with a 2-cell x halo; planes z-2..z+2 in use, z+3 landed, z+4
-// arriving), three buffers of the 2-row y halo, the matching values of s and
-// three tiles of K0, all filled by direct buffer->LDS loads issued two steps
-// ahead of their use.  No global load returns to registers inside the march,
+// and marches through z.  The LDS holds a ring of 5 + A planes of W (each
+// brick row with a 2-cell x halo; planes z-2..z+2 in use, z+3 .. z+2+A landed
+// or arriving), 1 + A buffers of the 2-row y halo, the matching values of s
+// and 1 + A tiles of K0, all filled by direct buffer->LDS loads issued A = 2
+// steps ahead of their use (130 KiB of LDS at r <= 32 in FP32).  No global load returns to registers inside the march,
 // so the only waits on memory are the explicit ones before the per-step
 // barrier, which leave the newest loads in flight.  Cells outside the grid
 // are read clamped into range and their s is masked to zero when used (the
@@ -280,8 +280,11 @@ constexpr int kBrickPC = kBrickBY * kBrickRW;  // cells per ring plane
 constexpr int kBrickHC = 4 * 16;               // y-halo cells (4 rows of 16)
 constexpr int kBrickHS = 80;                   // y-halo stride per column of W
 constexpr int kBrickKS = 68;                   // K0-tile stride per column
-constexpr int kBrickSlots = 7;                 // ring planes
-constexpr int kBrickBufs = 3;                  // y-halo / K0-tile buffers
+// steps between a load and its use, ring planes, y-halo / K0-tile buffers
+// (two suffice: three measured no faster at 128^3, rank 30)
+__host__ __device__ constexpr int brick_ahead(int tsize) { return tsize > 0 ? 2 : 2; }
+__host__ __device__ constexpr int brick_slots(int tsize) { return 5 + brick_ahead(tsize); }
+__host__ __device__ constexpr int brick_bufs(int tsize) { return 1 + brick_ahead(tsize); }
 constexpr unsigned kBufWord3 = 0x00020000u;    // raw (untyped) buffer resource
 static_assert(kBrickPC % 32 == 16 && kBrickHS % 32 == 16, "LDS strides avoid bank conflicts");
 static_assert(kBrickPC == kBrickHS, "one column stride for ring and halo");
@@ -292,11 +295,11 @@ __host__ __device__ constexpr int brick_s_dwords(int dpe) {
 }
 
 __host__ __device__ constexpr size_t brick_lds_bytes(int rb, int tsize) {
-  return size_t(4) * (size_t(kBrickSlots) * rb * kBrickPC * (tsize / 4) +
-                      size_t(kBrickBufs) * rb * kBrickHS * (tsize / 4) +
-                      size_t(kBrickSlots) * brick_s_dwords(tsize / 4) +
-                      size_t(kBrickBufs) * kBrickHC * (tsize / 4) +
-                      size_t(kBrickBufs) * rb * kBrickKS * (tsize / 4) + 64);
+  return size_t(4) * (size_t(brick_slots(tsize)) * rb * kBrickPC * (tsize / 4) +
+                      size_t(brick_bufs(tsize)) * rb * kBrickHS * (tsize / 4) +
+                      size_t(brick_slots(tsize)) * brick_s_dwords(tsize / 4) +
+                      size_t(brick_bufs(tsize)) * kBrickHC * (tsize / 4) +
+                      size_t(brick_bufs(tsize)) * rb * kBrickKS * (tsize / 4) + 64);
 }
 
 // s_waitcnt vmcnt(N) (expcnt and lgkmcnt not waited for): at most N of this
@@ -349,7 +352,9 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
     int zchunk) {
   constexpr int RB = 16 * NJ, KS = 4 * NJ, DPE = int(sizeof(T)) / 4, TB = int(sizeof(T));
   constexpr int BY = kBrickBY, RW = kBrickRW, PC = kBrickPC, HC = kBrickHC, HS = kBrickHS;
-  constexpr int KST = kBrickKS, NS = kBrickSlots, NB = kBrickBufs, NW = BY;
+  constexpr int KST = kBrickKS, NW = BY;
+  constexpr int AH = brick_ahead(TB), NS = brick_slots(TB), NB = brick_bufs(TB);
+  static_assert(brick_lds_bytes(RB, TB) <= 160 * 1024, "fits the LDS");
   constexpr int SPD = brick_s_dwords(DPE);           // dwords of one s ring plane
   constexpr int SP = SPD / DPE;                      // ... in elements
   constexpr int NPI = RB * PC * DPE / (64 * NW);     // W-plane loads per wave and step
@@ -361,7 +366,7 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
                     (RB * 64 * DPE) % (64 * NW) == 0,
                 "equal whole 64-dword loads per wave");
   constexpr int NLOADS = NPI + NHI + NKI + NSI;      // per wave and step
-  static_assert(NLOADS < 64, "fits vmcnt");
+  static_assert((AH - 1) * NLOADS < 64, "fits vmcnt");
   using acc_t = typename Mfma<T>::acc_t;
   extern __shared__ unsigned char smem_raw[];
   T *ringW = reinterpret_cast<T *>(smem_raw);        // [NS][RB][PC]
@@ -473,13 +478,8 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
       else dma_dword(rS, pad, soff[i], 0);
     }
   };
-  // prologue: ring planes z0-2 .. z0+3, y halos / K0 tiles of z0 and z0+1
-  issue(z0 - 2, z0);
-  issue(z0 - 1, z0 + 1);
-  issue(z0, z0);
-  issue(z0 + 1, z0);
-  issue(z0 + 2, z0);
-  issue(z0 + 3, z0 + 1);
+  // prologue: ring planes z0-2 .. z0+1+AH, y halos / K0 tiles of z0 .. z0+AH-1
+  for (int i = 0; i < AH + 4; ++i) issue(z0 - 2 + i, z0 + min(i, AH - 1));
   wait_vm<0>();
   __syncthreads();
   T ih[DIM];
@@ -562,12 +562,12 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
         if (valid && j < r) buf_store(k0 - tcoef * acc[jt][v], rO, xyo + j * ld * TB, zb);
       }
     }
-    // two steps ahead: ring plane z+4, y halo / K0 tile / s of z+2; the loads
-    // issued one step ago must have landed before the barrier, this step's
-    // may stay in flight (past the chunk end they are clamped into the grid
-    // and fill buffers no later step reads)
-    issue(z + 4, z + 2);
-    wait_vm<NLOADS>();
+    // AH steps ahead: ring plane z+2+AH, y halo / K0 tile / s of z+AH; the
+    // loads issued AH-1 steps ago must have landed before the barrier, those
+    // of the last AH-1 steps may stay in flight (past the chunk end they are
+    // clamped into the grid and fill buffers no later step reads)
+    issue(z + 2 + AH, z + AH);
+    wait_vm<(AH - 1) * NLOADS>();
     block_barrier();
   }
   wait_vm<0>();   // no load into LDS outlives the block
