@@ -195,6 +195,56 @@ __device__ void blk_jacobi(double *A, int lda, int p, int q, double *V, int ldv,
   }
 }
 
+// Cholesky-based orthonormalisation of a well-conditioned Gram matrix:
+// A = L L^T in place (A: q x q SPD, lower part used and overwritten), then
+// T = L^{-T} (q x q upper triangular, leading dimension ldt) so that X T has
+// orthonormal columns when A = X^T X.  Returns false (T untouched) when a
+// pivot is not above 1e-12 of the largest diagonal entry; the caller then
+// falls back to the eigen-decomposition.
+__device__ bool blk_chol_orth(double *A, int lda, int q, double *T, int ldt, double *red,
+                              int *flag) {
+  const int tid = threadIdx.x;
+  double dmax = 0.0;
+  for (int i = tid; i < q; i += blockDim.x) dmax = fmax(dmax, A[i + size_t(i) * lda]);
+  // block maximum (values are >= 0): reduce through red
+  for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o));
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = dmax;
+  if (tid == 0) *flag = 1;
+  __syncthreads();
+  dmax = 0.0;
+  for (int w = 0; w < int(blockDim.x >> 6); ++w) dmax = fmax(dmax, red[w]);
+  __syncthreads();
+  for (int k = 0; k < q; ++k) {
+    if (tid == 0) {
+      const double d = A[k + size_t(k) * lda];
+      if (!(d > 1e-12 * dmax)) *flag = 0;
+      A[k + size_t(k) * lda] = d > 0.0 ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    const double piv = A[k + size_t(k) * lda];
+    for (int i = k + 1 + tid; i < q; i += blockDim.x) A[i + size_t(k) * lda] /= piv;
+    __syncthreads();
+    const int nt = q - k - 1;
+    for (int e = tid; e < nt * nt; e += blockDim.x) {
+      const int i = k + 1 + e % nt, j = k + 1 + e / nt;
+      if (j <= i) A[i + size_t(j) * lda] -= A[i + size_t(k) * lda] * A[j + size_t(k) * lda];
+    }
+    __syncthreads();
+  }
+  if (!*flag) return false;
+  // column c of L^{-1} by forward substitution (one thread per column); T = its transpose
+  for (int c = tid; c < q; c += blockDim.x) {
+    for (int i = 0; i < q; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) v -= A[i + size_t(k) * lda] * T[c + size_t(k) * ldt];
+      T[c + size_t(i) * ldt] = i < c ? 0.0 : v / A[i + size_t(i) * lda];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
 // column norms of A (p x q) -> sig[q]; order[] = indices sorted by sig descending
 __device__ void blk_colnorms_sorted(const double *A, int lda, int p, int q, double *sig,
                                     int *order) {
@@ -342,6 +392,17 @@ __global__ __launch_bounds__(kWG) void k_gram_orth(int q, const double *__restri
   }
   for (int e = threadIdx.x; e < q * q; e += blockDim.x) T[(e % q) + size_t(e / q) * ldt] = 0.0;
   __syncthreads();
+  if (restrict_count) {
+    // second pass on an already orthonormalised block: Cholesky suffices (only
+    // the span matters downstream); the eigen path remains the fallback
+    if (blk_chol_orth(A, qq, qq, T, ldt, red, &flag)) return;
+    for (int e = threadIdx.x; e < qq * qq; e += blockDim.x) {
+      int i = e % qq, j = e / qq;
+      A[i + j * qq] = W[i + j * q];
+    }
+    for (int e = threadIdx.x; e < q * q; e += blockDim.x) T[(e % q) + size_t(e / q) * ldt] = 0.0;
+    __syncthreads();
+  }
   blk_jacobi(A, qq, qq, qq, V, qq, &flag, red);
   __syncthreads();
   // for the PSD W, the column norms of W V are its eigenvalues
@@ -416,15 +477,27 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
     }
     __syncthreads();
     blk_gemm_tn(kept, kept, m, 1.0, X, m, X, m, W, kept);
-    blk_jacobi(W, kept, kept, kept, Q, kept, &flag, red);
-    __syncthreads();
-    blk_colnorms_sorted(W, kept, kept, kept, sig, order);
-    for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
-      int i = e % m, c = e / m;
-      int j = order[c];
-      double s = 0.0;
-      for (int k = 0; k < kept; ++k) s += X[i + size_t(k) * m] * Q[k + j * kept];
-      Vh[i + size_t(r + c) * ldv] = s / sqrt(sig[j]);
+    // second pass: Cholesky of the well-conditioned Gram (span unchanged),
+    // the eigen-decomposition as the fallback
+    if (blk_chol_orth(W, kept, kept, Q, kept, red, &flag)) {
+      for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
+        int i = e % m, c = e / m;
+        double s = 0.0;
+        for (int k = 0; k <= c; ++k) s += X[i + size_t(k) * m] * Q[k + c * kept];
+        Vh[i + size_t(r + c) * ldv] = s;
+      }
+    } else {
+      blk_gemm_tn(kept, kept, m, 1.0, X, m, X, m, W, kept);
+      blk_jacobi(W, kept, kept, kept, Q, kept, &flag, red);
+      __syncthreads();
+      blk_colnorms_sorted(W, kept, kept, kept, sig, order);
+      for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
+        int i = e % m, c = e / m;
+        int j = order[c];
+        double s = 0.0;
+        for (int k = 0; k < kept; ++k) s += X[i + size_t(k) * m] * Q[k + j * kept];
+        Vh[i + size_t(r + c) * ldv] = s / sqrt(sig[j]);
+      }
     }
   }
   for (int e = threadIdx.x; e < m * (r - kept); e += blockDim.x) {
