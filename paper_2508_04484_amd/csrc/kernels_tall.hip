@@ -659,25 +659,34 @@ __global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__res
 // Stencil projections C_dk = X^T D_dk(s o X) of one direction d (blockIdx.y)
 // on the matrix cores: both one-sided differences (dk = 2d, 2d + 1) come from
 // the same five stencil points, so a block stages the X tile once and the two
-// difference tiles from one set of loads (clamped, unconditional, masked by a
-// select).  Four waves; wave w owns the 16-column tiles w, w + 4 of the right
-// factor for all 16-row tiles of the left one.  Partial sums of block bx go
-// to partial[(bx * 2 dim + dk) * p * p].
+// difference tiles from one set of loads.  The X tile carries a 2-cell halo
+// on each side (for d = 0 the x neighbours then come from LDS, and for every
+// d the centre value is the tile's own), s at the five stencil points of
+// each tile cell is staged once per tile, and only the y or z neighbours of
+// W = X are loaded per element (clamped, unconditional, masked by a select).
+// Four waves; wave w owns the 16-column tiles w, w + 4 of the right factor
+// for all 16-row tiles of the left one.  Partial sums of block bx go to
+// partial[(bx * 2 dim + dk) * p * p].
 template <typename T, typename Tc, int NA>
 __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__restrict__ s,
                                                      const T *__restrict__ X, int ldx, int p,
                                                      int chunk, double *__restrict__ partial) {
   using acc_t = typename Mfma<Tc>::acc_t;
   constexpr int CT = sizeof(Tc) == 8 ? 32 : 64;   // cells per staged tile
+  constexpr int CH = CT + 4;                      // with a 2-cell halo on each side
   constexpr int PA = 16 * NA + 1;                 // row length (odd: no bank conflicts)
   constexpr int NBT = (NA + 3) / 4;               // right-factor tiles per wave
   constexpr int PER = CT * 16 * NA / 256;         // staged elements per thread
+  constexpr int PERH = (CH * 16 * NA + 255) / 256;
   static_assert((CT * 16 * NA) % 256 == 0, "whole staging rounds");
   extern __shared__ unsigned char smem_raw[];
-  Tc *Xs = reinterpret_cast<Tc *>(smem_raw);      // [CT][PA]
-  Tc *Yb = Xs + CT * PA;                          // [CT][PA]
+  T *Xh = reinterpret_cast<T *>(smem_raw);        // [CH][PA] X with halo (storage type)
+  T *Sw = Xh + CH * PA;                           // [5][CT] s at the stencil points (0 outside)
+  Tc *Yb = reinterpret_cast<Tc *>(Sw + 5 * CT);   // [CT][PA]
   Tc *Yf = Yb + CT * PA;                          // [CT][PA]
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  Tc *Xs = Yf + CT * PA;                          // [CT][PA] left factor in the MFMA type
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int c = lane & 15, qq = lane >> 4;
   const int d = blockIdx.y;
   const int st = d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny);
@@ -692,32 +701,65 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
   const int x_end = min(g.n, x_begin + chunk);
   for (int x0 = x_begin; x0 < x_end; x0 += CT) {
     __syncthreads();
+    // X on cells x0-2 .. x0+CT+1 (clamped into the grid; only in-tile cells
+    // and, for d = 0, in-grid x neighbours of in-tile cells are used)
+#pragma unroll
+    for (int i = 0; i < PERH; ++i) {
+      const int e = tid + 256 * i;
+      if (e < CH * 16 * NA) {
+        const int hc = e % CH, a = e / CH;
+        const int xc = min(max(x0 - 2 + hc, 0), g.n - 1);
+        Xh[hc * PA + a] = X[size_t(min(a, p - 1)) * ldx + xc];
+      }
+    }
+    // s at the stencil points of every tile cell, zero outside the grid
+    for (int e = tid; e < 5 * CT; e += 256) {
+      const int t = e / CT, cc = e % CT;
+      const int xc = min(x0 + cc, x_end - 1);
+      const int cd = d == 0 ? xc % g.nx : (d == 1 ? (xc / g.nx) % g.ny : xc / (g.nx * g.ny));
+      const int o = t == 0 ? 0 : (t < 3 ? -t : t - 2);   // 0, -1, -2, +1, +2
+      const bool in = cd + o >= 0 && cd + o < size;
+      const T v = s[in ? xc + o * st : xc];
+      Sw[t * CT + cc] = in ? v : T(0);
+    }
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = tid + 256 * i, cc = e % CT, a = e / CT;
-      const int x = x0 + cc, xc = min(x, x_end - 1);
-      const Tc v = Tc(X[size_t(min(a, p - 1)) * ldx + xc]);
-      Xs[cc * PA + a] = (x < x_end && a < p) ? v : Tc(0);
+      const bool ok = x0 + cc < x_end && a < p;
+      Xs[cc * PA + a] = ok ? Tc(Xh[(cc + 2) * PA + a]) : Tc(0);
     }
+    // each thread keeps one cell (cc = tid % CT) and walks the columns b
+    {
+      const int cc = tid % CT, x = x0 + cc, xc = min(x, x_end - 1);
+      const bool xin = x < x_end;
+      const T s0 = Sw[cc], sm1 = Sw[CT + cc], sm2 = Sw[2 * CT + cc];
+      const T sp1 = Sw[3 * CT + cc], sp2 = Sw[4 * CT + cc];
+      auto put = [&](int b, T w0, T wm1, T wm2, T wp1, T wp2) {
+        const T v0 = s0 * w0;
+        const T db = (T(3) * v0 - T(4) * (sm1 * wm1) + sm2 * wm2) * ih;
+        const T df = -(T(3) * v0 - T(4) * (sp1 * wp1) + sp2 * wp2) * ih;
+        const bool ok = xin && b < p;
+        Yb[cc * PA + b] = ok ? Tc(db) : Tc(0);
+        Yf[cc * PA + b] = ok ? Tc(df) : Tc(0);
+      };
+      if (d == 0) {   // x neighbours from the halo'd tile
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + 256 * i, cc = e % CT, b = e / CT;
-      const int x = x0 + cc, xc = min(x, x_end - 1);
-      const int cd = d == 0 ? xc % g.nx : (d == 1 ? (xc / g.nx) % g.ny : xc / (g.nx * g.ny));
-      const bool m1 = cd >= 1, m2 = cd >= 2, p1 = cd + 1 < size, p2 = cd + 2 < size;
-      const int im1 = m1 ? xc - st : xc, im2 = m2 ? xc - 2 * st : xc;
-      const int ip1 = p1 ? xc + st : xc, ip2 = p2 ? xc + 2 * st : xc;
-      const T *col = X + size_t(min(b, p - 1)) * ldx;
-      const T v0 = s[xc] * col[xc];
-      const T am1 = s[im1] * col[im1], am2 = s[im2] * col[im2];
-      const T ap1 = s[ip1] * col[ip1], ap2 = s[ip2] * col[ip2];
-      const T vm1 = m1 ? am1 : T(0), vm2 = m2 ? am2 : T(0);
-      const T vp1 = p1 ? ap1 : T(0), vp2 = p2 ? ap2 : T(0);
-      const T db = (T(3) * v0 - T(4) * vm1 + vm2) * ih;
-      const T df = -(T(3) * v0 - T(4) * vp1 + vp2) * ih;
-      const bool ok = x < x_end && b < p;
-      Yb[cc * PA + b] = ok ? Tc(db) : Tc(0);
-      Yf[cc * PA + b] = ok ? Tc(df) : Tc(0);
+        for (int i = 0; i < PER; ++i) {
+          const int b = tid / CT + (256 / CT) * i;
+          put(b, Xh[(cc + 2) * PA + b], Xh[(cc + 1) * PA + b], Xh[cc * PA + b],
+              Xh[(cc + 3) * PA + b], Xh[(cc + 4) * PA + b]);
+        }
+      } else {        // y or z neighbours from memory (clamped; masked by s = 0)
+        const int im1 = max(xc - st, 0), im2 = max(xc - 2 * st, 0);
+        const int ip1 = min(xc + st, g.n - 1), ip2 = min(xc + 2 * st, g.n - 1);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+          const int b = tid / CT + (256 / CT) * i;
+          const T *col = X + size_t(min(b, p - 1)) * ldx;
+          put(b, Xh[(cc + 2) * PA + b], col[im1], col[im2], col[ip1], col[ip2]);
+        }
+      }
     }
     __syncthreads();
 #pragma unroll 2
@@ -725,15 +767,15 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
       const int cell = 4 * k4 + qq;
 #pragma unroll
       for (int bt = 0; bt < NBT; ++bt) {
-        const int btile = w + 4 * bt;
-        if (btile < NA) {
-          const Tc yb = Yb[cell * PA + btile * 16 + c], yf = Yf[cell * PA + btile * 16 + c];
+        // a wave without a tile of its own repeats the last one (no branch
+        // around the MFMAs; its sums are not written out)
+        const int btile = min(w + 4 * bt, NA - 1);
+        const Tc yb = Yb[cell * PA + btile * 16 + c], yf = Yf[cell * PA + btile * 16 + c];
 #pragma unroll
-          for (int at = 0; at < NA; ++at) {
-            const Tc xa = Xs[cell * PA + at * 16 + c];
-            ab[bt][at] = Mfma<Tc>::op(xa, yb, ab[bt][at]);
-            af[bt][at] = Mfma<Tc>::op(xa, yf, af[bt][at]);
-          }
+        for (int at = 0; at < NA; ++at) {
+          const Tc xa = Xs[cell * PA + at * 16 + c];
+          ab[bt][at] = Mfma<Tc>::op(xa, yb, ab[bt][at]);
+          af[bt][at] = Mfma<Tc>::op(xa, yf, af[bt][at]);
         }
       }
     }
@@ -743,7 +785,7 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
   double *outf = outb + pq;
 #pragma unroll
   for (int bt = 0; bt < NBT; ++bt) {
-    const int b = (w + 4 * bt) * 16 + c;
+    const int b = (w + 4 * bt) * 16 + c;   // >= p for a repeated tile
 #pragma unroll
     for (int at = 0; at < NA; ++at) {
 #pragma unroll
@@ -756,6 +798,14 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
       }
     }
   }
+}
+
+// dynamic LDS of k_stencil_proj
+template <typename T, typename Tc, int NA>
+constexpr size_t stencil_proj_lds() {
+  constexpr int CT = sizeof(Tc) == 8 ? 32 : 64;
+  return size_t(CT + 4) * (16 * NA + 1) * sizeof(T) + size_t(5) * CT * sizeof(T) +
+         size_t(3) * CT * (16 * NA + 1) * sizeof(Tc);
 }
 
 // Bp[(dk RB + k) RB + j] = B_dk(k, j) (zero padded to RB), from the
@@ -1094,8 +1144,7 @@ static void contract(const GridDev &g, const T *s, const T *X, int ldx, int p, Y
 template <typename T, typename Acc, int NA>
 static void stencil_proj_launch(const GridDev &g, const T *s, const T *X, int ld, int p, int nb,
                                 int chunk, double *partial, hipStream_t st) {
-  constexpr int CT = sizeof(Acc) == 8 ? 32 : 64;
-  const size_t shm = size_t(3) * CT * (16 * NA + 1) * sizeof(Acc);
+  const size_t shm = stencil_proj_lds<T, Acc, NA>();
   auto kern = k_stencil_proj<T, Acc, NA>;
   if (shm > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
