@@ -808,6 +808,81 @@ constexpr size_t stencil_proj_lds() {
          size_t(3) * CT * (16 * NA + 1) * sizeof(Tc);
 }
 
+// Weighted Grams G(a, b) = sum_x X(x, a) wt(x) Y(x, b) on the matrix cores
+// (Y = yf(x, b), wt = wf(x)).  Per block a chunk of cells in tiles of 64:
+// every thread stages one cell of the tile (the weight is evaluated once per
+// cell) for a fixed stride of columns, all loads of the tile in flight
+// together; then the 4 waves share the NA x NB output tiles (a wave without a
+// tile of its own repeats the last one and does not write it).  Partial sums
+// of block bx go to partial[bx * p * q].
+constexpr int kGramBlocks = 2048;
+
+template <typename T, typename Tc, int NA, int NB, typename YF, typename WF>
+__global__ __launch_bounds__(256) void k_gram_mfma(int n, const T *__restrict__ X, int ldx, int p,
+                                                  YF yf, int q, WF wf, int chunk,
+                                                  double *__restrict__ partial) {
+  using acc_t = typename Mfma<Tc>::acc_t;
+  constexpr int CT = 64;
+  constexpr int PA = 16 * NA + 1, PB = 16 * NB + 1;   // odd row lengths
+  constexpr int NT = NA * NB, TPW = (NT + 3) / 4;     // output tiles, per wave
+  constexpr int PERA = CT * 16 * NA / 256, PERB = CT * 16 * NB / 256;
+  extern __shared__ unsigned char smem_raw[];
+  Tc *Xs = reinterpret_cast<Tc *>(smem_raw);          // [CT][PA]
+  Tc *Ys = Xs + CT * PA;                              // [CT][PB]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c = lane & 15, qq = lane >> 4;
+  acc_t acc[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) acc[u] = acc_t{0, 0, 0, 0};
+  const int x_begin = blockIdx.x * chunk;
+  const int x_end = min(n, x_begin + chunk);
+  const int cc = tid % CT, col0 = tid / CT;
+  for (int x0 = x_begin; x0 < x_end; x0 += CT) {
+    __syncthreads();
+    {
+      const int x = x0 + cc, xc = min(x, x_end - 1);
+      const bool xin = x < x_end;
+      const Tc wt = Tc(wf(xc));
+#pragma unroll
+      for (int i = 0; i < PERA; ++i) {
+        const int a = col0 + 4 * i;
+        const Tc v = Tc(X[size_t(min(a, p - 1)) * ldx + xc]) * wt;
+        Xs[cc * PA + a] = (xin && a < p) ? v : Tc(0);
+      }
+#pragma unroll
+      for (int i = 0; i < PERB; ++i) {
+        const int b = col0 + 4 * i;
+        const Tc v = Tc(yf(xc, min(b, q - 1)));
+        Ys[cc * PB + b] = (xin && b < q) ? v : Tc(0);
+      }
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int k4 = 0; k4 < CT / 4; ++k4) {
+      const int cell = 4 * k4 + qq;
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int t = min(w + 4 * u, NT - 1), ta = t % NA, tb = t / NA;
+        acc[u] = Mfma<Tc>::op(Xs[cell * PA + ta * 16 + c], Ys[cell * PB + tb * 16 + c], acc[u]);
+      }
+    }
+  }
+  double *out = partial + size_t(blockIdx.x) * p * q;
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    const int t = w + 4 * u;
+    if (t < NT) {
+      const int ta = t % NA, tb = t / NA, b = tb * 16 + c;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = ta * 16 + Mfma<Tc>::row(qq, v);
+        if (a < p && b < q) out[a + size_t(b) * p] = double(acc[u][v]);
+      }
+    }
+  }
+}
+
 // Bp[(dk RB + k) RB + j] = B_dk(k, j) (zero padded to RB), from the
 // column-major double couplings (leading dimension ldb, blocks ldb^2 apart).
 template <typename T>
@@ -1141,6 +1216,44 @@ static void contract(const GridDev &g, const T *s, const T *X, int ldx, int p, Y
   nb_out = nb;
 }
 
+// Gram launch: SQUARE (q == p) uses NB = NA tiles, otherwise q <= 16 (NB = 1);
+// p <= 112 (NA <= 7) in both cases, which the callers check.
+template <typename T, typename Tc, int NA, int NB, typename YF, typename WF>
+static void gram_launch_na(int n, const T *X, int ldx, int p, YF yf, int q, WF wf, int nb,
+                           int chunk, double *partial, hipStream_t st) {
+  const size_t shm = size_t(64) * (16 * NA + 1 + 16 * NB + 1) * sizeof(Tc);
+  auto kern = k_gram_mfma<T, Tc, NA, NB, YF, WF>;
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+  kern<<<nb, 256, shm, st>>>(n, X, ldx, p, yf, q, wf, chunk, partial);
+}
+
+template <typename T, typename Tc, bool SQUARE, typename YF, typename WF>
+static void gram(int n, const T *X, int ldx, int p, YF yf, int q, WF wf, double *partial,
+                 size_t partial_elems, hipStream_t st, int &nb_out) {
+  const size_t pq = size_t(p) * q;
+  int nb = std::max(1, std::min(kGramBlocks, (n + 63) / 64));
+  while (nb > 1 && size_t(nb + 1) * pq > partial_elems) nb /= 2;
+  int chunk = std::max(1, (n + nb - 1) / nb);
+  chunk = (chunk + 63) / 64 * 64;
+  nb = (n + chunk - 1) / chunk;
+  const int na = (p + 15) / 16;
+#define DLRA_GRAM(NA)                                                                       \
+  gram_launch_na<T, Tc, NA, SQUARE ? NA : 1>(n, X, ldx, p, yf, q, wf, nb, chunk, partial, st)
+  switch (na) {
+    case 1: DLRA_GRAM(1); break;
+    case 2: DLRA_GRAM(2); break;
+    case 3: DLRA_GRAM(3); break;
+    case 4: DLRA_GRAM(4); break;
+    case 5: DLRA_GRAM(5); break;
+    case 6: DLRA_GRAM(6); break;
+    default: DLRA_GRAM(7); break;
+  }
+#undef DLRA_GRAM
+  nb_out = nb;
+}
+
 template <typename T, typename Acc, int NA>
 static void stencil_proj_launch(const GridDev &g, const T *s, const T *X, int ld, int p, int nb,
                                 int chunk, double *partial, hipStream_t st) {
@@ -1188,12 +1301,20 @@ void launch_gram(int n, const T *X, int ldx, int p, const T *Y, int ldy, int q, 
   GridDev g{};
   g.n = n;
   int nb = 0;
-  if (wmat != nullptr)
+  if (p == q && p <= 112) {
+    if (wmat != nullptr)
+      gram<T, Acc, true>(n, X, ldx, p, YMat<T>{Y, ldy}, q, WMatS<T>{wmat, s}, partial,
+                         partial_elems, st, nb);
+    else
+      gram<T, Acc, true>(n, X, ldx, p, YMat<T>{Y, ldy}, q, WOne<T>{}, partial, partial_elems,
+                         st, nb);
+  } else if (wmat != nullptr) {
     contract<T, Acc, false>(g, s, X, ldx, p, YMat<T>{Y, ldy}, q, WMatS<T>{wmat, s}, 1, partial,
                             partial_elems, st, nb);
-  else
+  } else {
     contract<T, Acc, false>(g, s, X, ldx, p, YMat<T>{Y, ldy}, q, WOne<T>{}, 1, partial,
                             partial_elems, st, nb);
+  }
   const size_t per = size_t(p) * q;
   double *red = partial + size_t(nb) * per;
   reduce_partials(partial, nb, int(per), red, st);
@@ -1204,11 +1325,16 @@ template <typename T, typename Acc>
 void launch_xt_source(int n, const T *X, int ld, int p, const T *w, int n_mat, const T *psi,
                       double *H, int ldh, double *partial, size_t partial_elems,
                       hipStream_t st) {
-  GridDev g{};
-  g.n = n;
   int nb = 0;
-  contract<T, Acc, false>(g, nullptr, X, ld, p, YSrc<T>{w, psi, n}, n_mat, WOne<T>{}, 1, partial,
-                          partial_elems, st, nb);
+  if (p <= 112 && n_mat <= 16) {
+    gram<T, Acc, false>(n, X, ld, p, YSrc<T>{w, psi, n}, n_mat, WOne<T>{}, partial,
+                        partial_elems, st, nb);
+  } else {
+    GridDev g{};
+    g.n = n;
+    contract<T, Acc, false>(g, nullptr, X, ld, p, YSrc<T>{w, psi, n}, n_mat, WOne<T>{}, 1,
+                            partial, partial_elems, st, nb);
+  }
   const size_t per = size_t(p) * n_mat;
   double *red = partial + size_t(nb) * per;
   reduce_partials(partial, nb, int(per), red, st);
