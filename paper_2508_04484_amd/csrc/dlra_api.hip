@@ -177,7 +177,8 @@ Plan make_plan(const Dims &d) {
   p.work = p.take((4 * P * P + 3 * m * P + 4 * P + 64) * 8);
   size_t ntile = (n + 31) / 32;
   size_t nb = std::min<size_t>(kPartialBlocks, ntile);
-  p.partial_elems = (nb + 1) * std::max<size_t>(d.ndk * P * P, 64);
+  // partial blocks, their sum and up to 64 segment sums of the reduction
+  p.partial_elems = (nb + 1 + 64) * std::max<size_t>(d.ndk * P * P, 64);
   p.partial = p.take(p.partial_elems * 8);
   p.ctl = p.take(sizeof(Ctl));
   const size_t G = d.G;

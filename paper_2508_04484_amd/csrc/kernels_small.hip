@@ -354,6 +354,79 @@ __global__ __launch_bounds__(256) void k_sstep_stage(int P, int ld, int ndk,
   }
 }
 
+// The same stage on the FP64 matrix cores for P <= 64: workgroup (it, jt)
+// owns the 16 x 16 output tile (I, J) = (16 it.., 16 jt..), wave dk of it the
+// term dk.  The wave forms T_dk(:, J) = W B_dk(:, J) (A operands: W staged in
+// LDS, zero padded to 64 x 64; B operands: B_dk in registers), keeps it in
+// LDS, multiplies C_dk(I, :) (registers) by it, and the ndk tiles are summed
+// in order dk = 0, 1, ...  16x16x4 f64 MFMA operand layout: A lane l holds
+// (row l % 16, k l / 16), B lane l holds (k l / 16, column l % 16), register
+// v of the accumulator is (row l / 16 + 4 v, column l % 16).
+typedef double sd4 __attribute__((ext_vector_type(4)));
+constexpr int kSmP = 64;        // padded order
+constexpr int kSmLW = 80;       // LDS row stride of W (doubles): 2 * 80 = 32 mod 64 banks
+constexpr int kSmMaxDk = 6;
+
+__global__ __launch_bounds__(64 * kSmMaxDk) void k_sstep_mfma(
+    int P, int ld, int ndk, const double *__restrict__ Ch, const double *__restrict__ Bh,
+    const double *S0, const double *__restrict__ W, double *out, double coef) {
+  extern __shared__ double smem_d[];
+  double *Ws = smem_d;                       // [kSmP k][kSmLW]: W(i, k) at k * kSmLW + i
+  double *Ts = Ws + kSmP * kSmLW;            // [ndk][kSmP][16]
+  double *Rs = Ts + kSmMaxDk * kSmP * 16;    // [ndk][16][16]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int dk = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c = lane & 15, q = lane >> 4;
+  const int I0 = 16 * blockIdx.x, J0 = 16 * blockIdx.y;
+  const int KS = (P + 3) / 4;                // k steps of 4
+  const double *B = Bh + size_t(dk) * ld * ld, *C = Ch + size_t(dk) * ld * ld;
+  // operands of this wave, all loads in flight together (clamped, masked)
+  double bop[16], cop[16];
+  const int jB = min(J0 + c, P - 1), iC = min(I0 + c, P - 1);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int k = 4 * s + q, kc = min(k, P - 1);
+    const double bv = B[kc + size_t(jB) * ld];
+    const double cv = C[iC + size_t(kc) * ld];
+    bop[s] = k < P ? bv : 0.0;
+    cop[s] = k < P ? cv : 0.0;
+  }
+  for (int e = tid; e < kSmP * kSmP; e += blockDim.x) {
+    const int i = e % kSmP, k = e / kSmP;
+    const double v = W[min(i, P - 1) + size_t(min(k, P - 1)) * ld];
+    Ws[k * kSmLW + i] = (i < P && k < P) ? v : 0.0;
+  }
+  __syncthreads();
+  // T_dk(:, J), row tiles it = 0 .. 3
+  double *T = Ts + dk * kSmP * 16;
+#pragma unroll
+  for (int it = 0; it < kSmP / 16; ++it) {
+    sd4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < KS; ++s)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(4 * s + q) * kSmLW + 16 * it + c], bop[s],
+                                                 acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[(16 * it + q + 4 * v) * 16 + c] = acc[v];
+  }
+  __syncthreads();
+  sd4 f = {0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < KS; ++s)
+    f = __builtin_amdgcn_mfma_f64_16x16x4f64(cop[s], T[(4 * s + q) * 16 + c], f, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Rs[(dk * 16 + q + 4 * v) * 16 + c] = f[v];
+  __syncthreads();
+  for (int e = tid; e < 256; e += blockDim.x) {
+    const int i = e & 15, j = e >> 4;
+    double F = 0.0;
+    for (int d = 0; d < ndk; ++d) F -= Rs[(d * 16 + i) * 16 + j];
+    const int gi = I0 + i, gj = J0 + j;
+    if (gi < P && gj < P) {
+      const size_t o = gi + size_t(gj) * ld;
+      out[o] = S0[o] + coef * F;
+    }
+  }
+}
+
 // L-step stage combine: out = L0 - coef sum_dk T_dk C_dk^T, T_dk = A_dk in
 // (m x r blocks, leading dim m, strided by ts).
 __global__ void k_lstep_combine(int m, int r, int ndk, const double *__restrict__ T, size_t ts,
@@ -739,6 +812,23 @@ void launch_sstep(int p, int ld, int ndk, const double *Ch, const double *Bh, do
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
   const int blocks = (p + kSJ - 1) / kSJ;
   const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
+  if (p <= kSmP && ndk <= kSmMaxDk) {
+    const size_t shm_m =
+        (size_t(kSmP) * kSmLW + size_t(kSmMaxDk) * kSmP * 16 + size_t(kSmMaxDk) * 256) * 8;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sstep_mfma),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm_m));
+    const dim3 grid((p + 15) / 16, (p + 15) / 16);
+    for (int sub = 0; sub < n_sub; ++sub) {
+      const double *in = S;
+      double *outs[4] = {Wa, Wb, Wa, S};
+      for (int stage = 0; stage < 4; ++stage) {
+        k_sstep_mfma<<<grid, 64 * ndk, shm_m, st>>>(p, ld, ndk, Ch, Bh, S, in, outs[stage],
+                                                    cf[stage] * h);
+        in = outs[stage];
+      }
+    }
+    return;
+  }
   for (int sub = 0; sub < n_sub; ++sub) {
     const double *in = S;
     double *outs[4] = {Wa, Wb, Wa, S};

@@ -535,21 +535,44 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
     acc_t acc[NJ];
 #pragma unroll
     for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
-#pragma unroll
-    for (int kq = 0; kq < KS; ++kq) {
+    // software pipeline over the column blocks kq: the LDS reads of block
+    // kq + 1 are issued before the MFMAs of block kq and its differences are
+    // formed after them, so the reads complete under the matrix work
+    T sten[1 + 4 * DIM];
+    auto read_sten = [&](int kq) {
       const int ok = (4 * kq + q) * PC;   // column offset (PC == HS)
-      const T w0 = Wc[ok + base];
+      sten[0] = Wc[ok + base];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) sten[1 + 4 * d + t] = wp[d][t][ok];
+    };
+    T db[DIM], df[DIM];
+    auto diffs = [&]() {
+      const T w0 = sten[0];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        const T wm2 = wp[d][0][ok], wm1 = wp[d][1][ok], wp1 = wp[d][2][ok], wp2 = wp[d][3][ok];
-        const T db = cb[d][2] * wm2 + (cb[d][1] * wm1 + cb[d][0] * w0);
-        const T df = cf[d][2] * wp2 + (cf[d][1] * wp1 + cf[d][0] * w0);
+        const T wm2 = sten[1 + 4 * d], wm1 = sten[2 + 4 * d];
+        const T wp1 = sten[3 + 4 * d], wp2 = sten[4 + 4 * d];
+        db[d] = cb[d][2] * wm2 + (cb[d][1] * wm1 + cb[d][0] * w0);
+        df[d] = cf[d][2] * wp2 + (cf[d][1] * wp1 + cf[d][0] * w0);
+      }
+    };
+    read_sten(0);
+    diffs();
+#pragma unroll
+    for (int kq = 0; kq < KS; ++kq) {
+      if (kq + 1 < KS) read_sten(kq + 1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
 #pragma unroll
         for (int jt = 0; jt < NJ; ++jt) {
-          acc[jt] = Mfma<T>::op(bq[d][kq][jt][0], db, acc[jt]);
-          acc[jt] = Mfma<T>::op(bq[d][kq][jt][1], df, acc[jt]);
+          acc[jt] = Mfma<T>::op(bq[d][kq][jt][0], db[d], acc[jt]);
+          acc[jt] = Mfma<T>::op(bq[d][kq][jt][1], df[d], acc[jt]);
         }
-      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (kq + 1 < KS) diffs();
     }
     const T *Kt = K0t + hb * RB * KST + row * 16 + c;
     const int zb = z * plane * TB;
@@ -916,9 +939,56 @@ __global__ __launch_bounds__(kRedE * kRedG) void k_reduce_partials(
   }
 }
 
-void reduce_partials(const double *partial, int nblocks, int elems, double *out,
-                     hipStream_t st) {
+// doubles of a buffer of `total` left after `blocks` blocks of `per`
+static size_t room_after(size_t total, size_t blocks, size_t per) {
+  return total > blocks * per ? total - blocks * per : 0;
+}
+
+// First level of the partial-sum reduction: segment blockIdx.y of the
+// nblocks partial blocks, 64 elements per workgroup, the four waves take
+// every fourth block of the segment (four independent sums per lane).
+__global__ __launch_bounds__(256) void k_reduce_partials_seg(const double *__restrict__ partial,
+                                                             int nblocks, int elems, int nseg,
+                                                             double *__restrict__ seg_out) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane, sg = blockIdx.y;
+  const int b0 = int(int64_t(sg) * nblocks / nseg), b1 = int(int64_t(sg + 1) * nblocks / nseg);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (e < elems) {
+    const double *src = partial + e;
+    int b = b0 + w;
+    for (; b + 12 < b1; b += 16) {
+      s0 += src[size_t(b) * elems];
+      s1 += src[size_t(b + 4) * elems];
+      s2 += src[size_t(b + 8) * elems];
+      s3 += src[size_t(b + 12) * elems];
+    }
+    for (; b < b1; b += 4) s0 += src[size_t(b) * elems];
+  }
+  red[w][lane] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (w == 0 && e < elems)
+    seg_out[size_t(sg) * elems + e] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+// out[e] = sum_b partial[b * elems + e] in a fixed order.  Given room for
+// scratch_elems doubles at scratch (disjoint from partial and out), the
+// blocks are first summed in up to 64 segments (many workgroups), then the
+// segment sums.
+void reduce_partials(const double *partial, int nblocks, int elems, double *out, hipStream_t st,
+                     double *scratch = nullptr, size_t scratch_elems = 0) {
   if (elems <= 0) return;
+  int nseg = std::min(64, nblocks / 16);
+  if (scratch == nullptr) nseg = 0;
+  nseg = int(std::min<size_t>(size_t(std::max(nseg, 0)), scratch_elems / size_t(elems)));
+  if (nseg >= 2) {
+    double *seg = scratch;
+    k_reduce_partials_seg<<<dim3((elems + 63) / 64, nseg), 256, 0, st>>>(partial, nblocks, elems,
+                                                                        nseg, seg);
+    partial = seg;
+    nblocks = nseg;
+  }
   k_reduce_partials<<<(elems + kRedE - 1) / kRedE, kRedE * kRedG, 0, st>>>(partial, nblocks,
                                                                          elems, out);
 }
@@ -1289,7 +1359,7 @@ void launch_stencil_projection(const GridDev &g, const T *s, const T *X, int ld,
   }
   const size_t per = size_t(ndk) * p * p;
   double *red = partial + size_t(nb) * per;
-  reduce_partials(partial, nb, int(per), red, st);
+  reduce_partials(partial, nb, int(per), red, st, red + per, room_after(partial_elems, nb + 1, per));
   k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, p, ndk, C, ldc,
                                                             size_t(ldc) * ldc);
 }
@@ -1317,7 +1387,7 @@ void launch_gram(int n, const T *X, int ldx, int p, const T *Y, int ldy, int q, 
   }
   const size_t per = size_t(p) * q;
   double *red = partial + size_t(nb) * per;
-  reduce_partials(partial, nb, int(per), red, st);
+  reduce_partials(partial, nb, int(per), red, st, red + per, room_after(partial_elems, nb + 1, per));
   k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, q, 1, G, ldg, 0);
 }
 
@@ -1337,7 +1407,7 @@ void launch_xt_source(int n, const T *X, int ld, int p, const T *w, int n_mat, c
   }
   const size_t per = size_t(p) * n_mat;
   double *red = partial + size_t(nb) * per;
-  reduce_partials(partial, nb, int(per), red, st);
+  reduce_partials(partial, nb, int(per), red, st, red + per, room_after(partial_elems, nb + 1, per));
   k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, n_mat, 1, H, ldh, 0);
 }
 
@@ -1347,7 +1417,7 @@ void launch_sumsq(int n, const T *X, int ld, int q, double *out, double *partial
   int nb = std::min((n + kBlock - 1) / kBlock, kSumsqBlocks);
   if (size_t(nb) > partial_elems) nb = int(partial_elems);
   k_sumsq<T><<<nb, kBlock, 0, st>>>(n, X, ld, q, partial);
-  reduce_partials(partial, nb, 1, out, st);
+  reduce_partials(partial, nb, 1, out, st, partial + nb, room_after(partial_elems, nb, 1));
 }
 
 template <typename T>
