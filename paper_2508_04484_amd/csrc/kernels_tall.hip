@@ -280,12 +280,16 @@ constexpr int kBrickPC = kBrickBY * kBrickRW;  // cells per ring plane
 constexpr int kBrickHC = 4 * 16;               // y-halo cells (4 rows of 16)
 constexpr int kBrickHS = 80;                   // y-halo stride per column of W
 constexpr int kBrickKS = 68;                   // K0-tile stride per column
-// steps between a load and its use, ring planes, y-halo / K0-tile buffers
-// (two suffice: three measured no faster at 128^3, rank 30)
-__host__ __device__ constexpr int brick_ahead(int tsize) { return tsize > 0 ? 2 : 2; }
-__host__ __device__ constexpr int brick_slots(int tsize) { return 5 + brick_ahead(tsize); }
-__host__ __device__ constexpr int brick_bufs(int tsize) { return 1 + brick_ahead(tsize); }
+// steps between a load and its use, ring planes, y-halo / K0-tile buffers.
+// The loads of step z + AH are issued after the barrier that ends step z, so
+// the ring slot of plane z - 2 and the buffers of step z are free again.
+__host__ __device__ constexpr int brick_ahead(int) { return 3; }
+__host__ __device__ constexpr int brick_slots(int tsize) { return 4 + brick_ahead(tsize); }
+__host__ __device__ constexpr int brick_bufs(int tsize) { return brick_ahead(tsize); }
 constexpr unsigned kBufWord3 = 0x00020000u;    // raw (untyped) buffer resource
+// waves per brick row for two output tiles (FP32, 16 < r <= 32): with two,
+// each wave computes one tile and two waves share every SIMD
+constexpr int kBrickSplit = 2;
 static_assert(kBrickPC % 32 == 16 && kBrickHS % 32 == 16, "LDS strides avoid bank conflicts");
 static_assert(kBrickPC == kBrickHS, "one column stride for ring and halo");
 
@@ -345,14 +349,15 @@ __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, int vo,
   }
 }
 
-template <typename T, int NJ, int DIM>
-__global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
+template <typename T, int NJ, int DIM, int JS>
+__global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     GridDev g, const T *__restrict__ s, const T *__restrict__ W, const T *__restrict__ K0,
     T *__restrict__ out, int ld, int r, const T *__restrict__ Bp, double coef, int nby, int nzc,
     int zchunk) {
   constexpr int RB = 16 * NJ, KS = 4 * NJ, DPE = int(sizeof(T)) / 4, TB = int(sizeof(T));
   constexpr int BY = kBrickBY, RW = kBrickRW, PC = kBrickPC, HC = kBrickHC, HS = kBrickHS;
-  constexpr int KST = kBrickKS, NW = BY;
+  constexpr int KST = kBrickKS, NW = BY * JS, NJW = NJ / JS;
+  static_assert(NJ % JS == 0, "whole output tiles per wave");
   constexpr int AH = brick_ahead(TB), NS = brick_slots(TB), NB = brick_bufs(TB);
   static_assert(brick_lds_bytes(RB, TB) <= 160 * 1024, "fits the LDS");
   constexpr int SPD = brick_s_dwords(DPE);           // dwords of one s ring plane
@@ -366,7 +371,7 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
                     (RB * 64 * DPE) % (64 * NW) == 0,
                 "equal whole 64-dword loads per wave");
   constexpr int NLOADS = NPI + NHI + NKI + NSI;      // per wave and step
-  static_assert((AH - 1) * NLOADS < 64, "fits vmcnt");
+  static_assert(AH >= 2 && (AH - 2) * NLOADS < 64, "fits vmcnt");
   using acc_t = typename Mfma<T>::acc_t;
   extern __shared__ unsigned char smem_raw[];
   T *ringW = reinterpret_cast<T *>(smem_raw);        // [NS][RB][PC]
@@ -386,8 +391,9 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
   const int z0 = zc * zchunk, z1 = min(g.nz, z0 + zchunk);
   if (z0 >= z1) return;
   const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // = brick row
-  const int row = wave;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int row = wave % BY;                    // brick row of this wave
+  const int jh = wave / BY;                     // its output tiles jh NJW ..
   const int c = lane & 15, q = lane >> 4;
   const int nx = g.nx, ny = g.ny, nz = g.nz, plane = nx * ny;
   const size_t tall_bytes = size_t(ld) * r * TB;
@@ -399,16 +405,17 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
   auto clampz = [&](int z) { return min(max(z, 0), nz - 1); };
   auto halo_y = [&](int hr) { return gy0 + (hr < 2 ? hr - 2 : BY + hr - 2); };
   // couplings: the A operands of all MFMAs of this lane
-  T bq[DIM][KS][NJ][2];
+  T bq[DIM][KS][NJW][2];
 #pragma unroll
   for (int d = 0; d < DIM; ++d)
 #pragma unroll
     for (int kq = 0; kq < KS; ++kq)
 #pragma unroll
-      for (int jt = 0; jt < NJ; ++jt)
+      for (int jt = 0; jt < NJW; ++jt)
 #pragma unroll
         for (int f = 0; f < 2; ++f)
-          bq[d][kq][jt][f] = Bp[size_t(2 * d + f) * RB * RB + (4 * kq + q) * RB + 16 * jt + c];
+          bq[d][kq][jt][f] = Bp[size_t(2 * d + f) * RB * RB + (4 * kq + q) * RB +
+                                16 * (jh * NJW + jt) + c];
   // per-lane byte offsets (within one z plane) of every load of the march
   int poff[NPI], hoff[NHI], koff[NKI], soff[NSI];
 #pragma unroll
@@ -532,9 +539,9 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
       cf[d][1] = T(4) * ih[d] * sv[d][2];
       cf[d][2] = -ih[d] * sv[d][3];
     }
-    acc_t acc[NJ];
+    acc_t acc[NJW];
 #pragma unroll
-    for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+    for (int jt = 0; jt < NJW; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
     // software pipeline over the column blocks kq: the LDS reads of block
     // kq + 1 are issued before the MFMAs of block kq and its differences are
     // formed after them, so the reads complete under the matrix work
@@ -567,7 +574,7 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
 #pragma unroll
-        for (int jt = 0; jt < NJ; ++jt) {
+        for (int jt = 0; jt < NJW; ++jt) {
           acc[jt] = Mfma<T>::op(bq[d][kq][jt][0], db[d], acc[jt]);
           acc[jt] = Mfma<T>::op(bq[d][kq][jt][1], df[d], acc[jt]);
         }
@@ -577,21 +584,22 @@ __global__ __launch_bounds__(64 * kBrickBY) void k_kstage_brick(
     const T *Kt = K0t + hb * RB * KST + row * 16 + c;
     const int zb = z * plane * TB;
 #pragma unroll
-    for (int jt = 0; jt < NJ; ++jt) {
+    for (int jt = 0; jt < NJW; ++jt) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * jt + Mfma<T>::row(q, v);
+        const int j = 16 * (jh * NJW + jt) + Mfma<T>::row(q, v);
         const T k0 = Kt[j * KST];
         if (valid && j < r) buf_store(k0 - tcoef * acc[jt][v], rO, xyo + j * ld * TB, zb);
       }
     }
-    // AH steps ahead: ring plane z+2+AH, y halo / K0 tile / s of z+AH; the
-    // loads issued AH-1 steps ago must have landed before the barrier, those
-    // of the last AH-1 steps may stay in flight (past the chunk end they are
-    // clamped into the grid and fill buffers no later step reads)
-    issue(z + 2 + AH, z + AH);
-    wait_vm<(AH - 1) * NLOADS>();
+    // the loads of step z + 1 (issued after the barrier of step z + 1 - AH)
+    // must have landed before the barrier, those of the later AH - 2 steps may
+    // stay in flight; then AH steps ahead: ring plane z+2+AH, y halo / K0
+    // tile / s of z+AH (past the chunk end they are clamped into the grid and
+    // fill buffers no later step reads)
+    wait_vm<(AH - 2) * NLOADS>();
     block_barrier();
+    issue(z + 2 + AH, z + AH);
   }
   wait_vm<0>();   // no load into LDS outlives the block
 }
@@ -1184,12 +1192,12 @@ static void kstage_launch(const GridDev &g, const T *s, const T *W, const T *K0,
   kern<<<blocks, 256, lds ? shm : 0, st>>>(g, s, W, K0, out, ld, r, Bp, coef, tiled, ntiles);
 }
 
-template <typename T, int NJ, int DIM>
+template <typename T, int NJ, int DIM, int JS = 1>
 static void kstage_brick_launch(const GridDev &g, const T *s, const T *W, const T *K0, T *out,
                                 int ld, int r, const T *Bp, double coef, hipStream_t st) {
-  constexpr int NT = 64 * kBrickBY;
+  constexpr int NT = 64 * kBrickBY * JS;
   const size_t shm = brick_lds_bytes(16 * NJ, int(sizeof(T)));
-  auto kern = k_kstage_brick<T, NJ, DIM>;
+  auto kern = k_kstage_brick<T, NJ, DIM, JS>;
   static std::atomic<int> blocks_cache{0};
   int cap = blocks_cache.load(std::memory_order_relaxed);
   if (cap <= 0) {
@@ -1227,8 +1235,8 @@ void launch_kstep_stage(const GridDev &g, const T *s, const T *W, const T *K0, T
     if (r <= 16 && three) kstage_brick_launch<T, 1, 3>(g, s, W, K0, out, ld, r, Bp, coef, st);
     else if (r <= 16) kstage_brick_launch<T, 1, 2>(g, s, W, K0, out, ld, r, Bp, coef, st);
     else if constexpr (sizeof(T) == 4) {
-      if (three) kstage_brick_launch<T, 2, 3>(g, s, W, K0, out, ld, r, Bp, coef, st);
-      else kstage_brick_launch<T, 2, 2>(g, s, W, K0, out, ld, r, Bp, coef, st);
+      if (three) kstage_brick_launch<T, 2, 3, kBrickSplit>(g, s, W, K0, out, ld, r, Bp, coef, st);
+      else kstage_brick_launch<T, 2, 2, kBrickSplit>(g, s, W, K0, out, ld, r, Bp, coef, st);
     }
     return;
   }

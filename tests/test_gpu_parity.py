@@ -36,6 +36,8 @@ CASES = {
     "adaptive2d": lambda **k: configs.small_2d(mats="slab", rank_mode="adaptive", r=4, r_min=2,
                                                r_max=12, trunc_tol=1e-4, **k),
     "random3d": lambda **k: configs.small_3d(n=8, r=6, **k),
+    # rank 20: two 16-column output tiles in the K-step (ragged 11^3 grid)
+    "rank20_3d": lambda **k: configs.small_3d(n=11, N=7, r=20, n_steps=6, **k),
 }
 
 
@@ -98,7 +100,7 @@ def test_single_step_from_injected_state(name):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["slab2d", "random3d"])
+@pytest.mark.parametrize("name", ["slab2d", "random3d", "rank20_3d"])
 def test_mixed_precision_dose(name):
     dl = _gpu()
     p = CASES[name](precision="mixed", aug_tol=1e-4, floor_tol=1e-5)
