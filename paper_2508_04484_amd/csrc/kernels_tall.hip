@@ -281,8 +281,9 @@ constexpr int kBrickHC = 4 * 16;               // y-halo cells (4 rows of 16)
 constexpr int kBrickHS = 80;                   // y-halo stride per column of W
 constexpr int kBrickKS = 68;                   // K0-tile stride per column
 // steps between a load and its use, ring planes, y-halo / K0-tile buffers.
-// The loads of step z + AH are issued after the barrier that ends step z, so
-// the ring slot of plane z - 2 and the buffers of step z are free again.
+// Step z (after the barrier that ended step z - 1) loads ring plane z+1+AH
+// into the slot of plane z - 3 and the y halo / K0 tile of step z+AH-1 into
+// the buffers of step z - 1, interleaved with its MFMAs.
 __host__ __device__ constexpr int brick_ahead(int) { return 3; }
 __host__ __device__ constexpr int brick_slots(int tsize) { return 4 + brick_ahead(tsize); }
 __host__ __device__ constexpr int brick_bufs(int tsize) { return brick_ahead(tsize); }
@@ -458,35 +459,46 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
   }
   auto slot = [](int z) { return (z + 2 * NS) % NS; };
   // W of ring plane zp, W y halo of plane zh, K0 tile of plane zh, s of both
-  auto issue = [&](int zp, int zh) {
+  // loads lo .. hi-1 of the NLOADS of one step (W plane, W y halo, K0 tile,
+  // s), so that a step's loads can be spread over the column blocks
+  auto issue_part = [&](int lo, int hi, int zp, int zh) {
     const int pb = clampz(zp) * plane * TB, hb = clampz(zh) * plane * TB;
     unsigned char *dp = reinterpret_cast<unsigned char *>(ringW + slot(zp) * RB * PC);
     unsigned char *dh = reinterpret_cast<unsigned char *>(haloW + (zh % NB) * RB * HS);
     unsigned char *dk = reinterpret_cast<unsigned char *>(K0t + (zh % NB) * RB * KST);
     unsigned char *dsp = reinterpret_cast<unsigned char *>(ringS + slot(zp) * SP);
     unsigned char *dsh = reinterpret_cast<unsigned char *>(haloS + (zh % NB) * HC);
+    auto in = [&](int i) { return i >= lo && i < hi; };
 #pragma unroll
-    for (int i = 0; i < NPI; ++i) dma_dword(rW, dp + 256 * (wave + NW * i), poff[i], pb);
+    for (int i = 0; i < NPI; ++i)
+      if (in(i)) dma_dword(rW, dp + 256 * (wave + NW * i), poff[i], pb);
 #pragma unroll
     for (int i = 0; i < NHI; ++i) {
       const int dw0 = 64 * (wave + NW * i);
-      dma_dword(rW, dh + 4 * ((dw0 / (HC * DPE)) * HS * DPE + dw0 % (HC * DPE)), hoff[i], hb);
+      if (in(NPI + i))
+        dma_dword(rW, dh + 4 * ((dw0 / (HC * DPE)) * HS * DPE + dw0 % (HC * DPE)), hoff[i], hb);
     }
 #pragma unroll
     for (int i = 0; i < NKI; ++i) {
       const int dw0 = 64 * (wave + NW * i);
-      dma_dword(rK, dk + 4 * ((dw0 / (64 * DPE)) * KST * DPE + dw0 % (64 * DPE)), koff[i], hb);
+      if (in(NPI + NHI + i))
+        dma_dword(rK, dk + 4 * ((dw0 / (64 * DPE)) * KST * DPE + dw0 % (64 * DPE)), koff[i],
+                  hb);
     }
 #pragma unroll
     for (int i = 0; i < NSI; ++i) {
       const int idx = wave + NW * i;
+      if (!in(NPI + NHI + NKI + i)) continue;
       if (idx < SPD / 64) dma_dword(rS, dsp + 256 * idx, soff[i], pb);
       else if (idx < NSX) dma_dword(rS, dsh + 256 * (idx - SPD / 64), soff[i], hb);
       else dma_dword(rS, pad, soff[i], 0);
     }
   };
-  // prologue: ring planes z0-2 .. z0+1+AH, y halos / K0 tiles of z0 .. z0+AH-1
-  for (int i = 0; i < AH + 4; ++i) issue(z0 - 2 + i, z0 + min(i, AH - 1));
+  auto issue = [&](int zp, int zh) { issue_part(0, NLOADS, zp, zh); };
+  // prologue: ring planes z0-2 .. z0+AH, y halos / K0 tiles of z0 .. z0+AH-2;
+  // step z loads ring plane z+1+AH and the y halo / K0 tile / s of z+AH-1,
+  // spread over its column blocks
+  for (int i = 0; i < AH + 3; ++i) issue(z0 - 2 + i, z0 + min(i, AH - 2));
   wait_vm<0>();
   __syncthreads();
   T ih[DIM];
@@ -570,6 +582,7 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
 #pragma unroll
     for (int kq = 0; kq < KS; ++kq) {
       if (kq + 1 < KS) read_sten(kq + 1);
+      issue_part(kq * NLOADS / KS, (kq + 1) * NLOADS / KS, z + 1 + AH, z + AH - 1);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
@@ -592,14 +605,12 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
         if (valid && j < r) buf_store(k0 - tcoef * acc[jt][v], rO, xyo + j * ld * TB, zb);
       }
     }
-    // the loads of step z + 1 (issued after the barrier of step z + 1 - AH)
-    // must have landed before the barrier, those of the later AH - 2 steps may
-    // stay in flight; then AH steps ahead: ring plane z+2+AH, y halo / K0
-    // tile / s of z+AH (past the chunk end they are clamped into the grid and
-    // fill buffers no later step reads)
+    // the loads of step z + 1 (issued during step z + 2 - AH) must have
+    // landed before the barrier, those of the later AH - 2 steps may stay in
+    // flight (past the chunk end they are clamped into the grid and fill
+    // buffers no later step reads)
     wait_vm<(AH - 2) * NLOADS>();
     block_barrier();
-    issue(z + 2 + AH, z + AH);
   }
   wait_vm<0>();   // no load into LDS outlives the block
 }
@@ -701,7 +712,8 @@ __global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__res
 template <typename T, typename Tc, int NA>
 __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__restrict__ s,
                                                      const T *__restrict__ X, int ldx, int p,
-                                                     int chunk, double *__restrict__ partial) {
+                                                     int chunk, int nchunk,
+                                                     double *__restrict__ partial) {
   using acc_t = typename Mfma<Tc>::acc_t;
   constexpr int CT = sizeof(Tc) == 8 ? 32 : 64;   // cells per staged tile
   constexpr int CH = CT + 4;                      // with a 2-cell halo on each side
@@ -719,7 +731,12 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int c = lane & 15, qq = lane >> 4;
-  const int d = blockIdx.y;
+  // block -> (direction, chunk): the hardware deals blocks round-robin over
+  // the 8 XCDs; each XCD gets one contiguous range of chunks of a direction,
+  // so the y / z neighbours a chunk reads are mostly its L2's own lines
+  const int nblk = gridDim.x, xcd = blockIdx.x & 7;
+  const int L = xcd * (nblk >> 3) + min(xcd, nblk & 7) + (blockIdx.x >> 3);
+  const int d = L / nchunk, bx = L % nchunk;
   const int st = d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny);
   const int size = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
   const T ih = T(g.inv2h[d]);
@@ -728,7 +745,7 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
   for (int bt = 0; bt < NBT; ++bt)
 #pragma unroll
     for (int at = 0; at < NA; ++at) ab[bt][at] = af[bt][at] = acc_t{0, 0, 0, 0};
-  const int x_begin = blockIdx.x * chunk;
+  const int x_begin = bx * chunk;
   const int x_end = min(g.n, x_begin + chunk);
   for (int x0 = x_begin; x0 < x_end; x0 += CT) {
     __syncthreads();
@@ -812,7 +829,7 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
     }
   }
   const size_t pq = size_t(p) * p;
-  double *outb = partial + (size_t(blockIdx.x) * 2 * gridDim.y + 2 * d) * pq;
+  double *outb = partial + (size_t(bx) * 2 * g.dim + 2 * d) * pq;
   double *outf = outb + pq;
 #pragma unroll
   for (int bt = 0; bt < NBT; ++bt) {
@@ -1340,7 +1357,7 @@ static void stencil_proj_launch(const GridDev &g, const T *s, const T *X, int ld
   if (shm > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
-  kern<<<dim3(nb, g.dim), 256, shm, st>>>(g, s, X, ld, p, chunk, partial);
+  kern<<<nb * g.dim, 256, shm, st>>>(g, s, X, ld, p, chunk, nb, partial);
 }
 
 template <typename T, typename Acc>
