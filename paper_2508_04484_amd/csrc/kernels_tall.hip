@@ -517,6 +517,7 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     my[t] = gy + o >= 0 && gy + o < ny;
   }
   const int base = row * RW + c + 2;
+  T pend[NJW][4];   // outputs of the previous step, stored during this one
   for (int z = z0; z < z1; ++z) {
     const int sc = slot(z), hb = z % NB;
     const T *Wc = ringW + sc * RB * PC, *Sc = ringS + sc * SP;
@@ -552,6 +553,17 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
       cf[d][2] = -ih[d] * sv[d][3];
     }
     acc_t acc[NJW];
+    // stores of the previous step's outputs, spread over this step's column
+    // blocks like the loads
+    auto store_part = [&](int lo, int hi) {
+#pragma unroll
+      for (int u = 0; u < NJW * 4; ++u) {
+        const int jt = u / 4, v = u % 4;
+        const int j = 16 * (jh * NJW + jt) + Mfma<T>::row(q, v);
+        if (u >= lo && u < hi && z > z0 && valid && j < r)
+          buf_store(pend[jt][v], rO, xyo + j * ld * TB, (z - 1) * plane * TB);
+      }
+    };
 #pragma unroll
     for (int jt = 0; jt < NJW; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
     // software pipeline over the column blocks kq: the LDS reads of block
@@ -583,6 +595,7 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     for (int kq = 0; kq < KS; ++kq) {
       if (kq + 1 < KS) read_sten(kq + 1);
       issue_part(kq * NLOADS / KS, (kq + 1) * NLOADS / KS, z + 1 + AH, z + AH - 1);
+      store_part(kq * NJW * 4 / KS, (kq + 1) * NJW * 4 / KS);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
@@ -595,14 +608,12 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
       if (kq + 1 < KS) diffs();
     }
     const T *Kt = K0t + hb * RB * KST + row * 16 + c;
-    const int zb = z * plane * TB;
 #pragma unroll
     for (int jt = 0; jt < NJW; ++jt) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int j = 16 * (jh * NJW + jt) + Mfma<T>::row(q, v);
-        const T k0 = Kt[j * KST];
-        if (valid && j < r) buf_store(k0 - tcoef * acc[jt][v], rO, xyo + j * ld * TB, zb);
+        pend[jt][v] = Kt[j * KST] - tcoef * acc[jt][v];
       }
     }
     // the loads of step z + 1 (issued during step z + 2 - AH) must have
@@ -611,6 +622,14 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     // buffers no later step reads)
     wait_vm<(AH - 2) * NLOADS>();
     block_barrier();
+  }
+#pragma unroll
+  for (int jt = 0; jt < NJW; ++jt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = 16 * (jh * NJW + jt) + Mfma<T>::row(q, v);
+      if (valid && j < r) buf_store(pend[jt][v], rO, xyo + j * ld * TB, (z1 - 1) * plane * TB);
+    }
   }
   wait_vm<0>();   // no load into LDS outlives the block
 }
