@@ -766,7 +766,27 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
     for (int at = 0; at < NA; ++at) ab[bt][at] = af[bt][at] = acc_t{0, 0, 0, 0};
   const int x_begin = bx * chunk;
   const int x_end = min(g.n, x_begin + chunk);
+  // for d != 0 and small NA the y / z neighbours are loaded together with the
+  // staging loads (one memory round trip per tile)
+  constexpr bool EARLY = NA <= 2;
+  T nbv[EARLY ? PER : 1][4];
   for (int x0 = x_begin; x0 < x_end; x0 += CT) {
+    if constexpr (EARLY) {
+      if (d != 0) {
+        const int cc = tid % CT, xc = min(x0 + cc, x_end - 1);
+        const int im1 = max(xc - st, 0), im2 = max(xc - 2 * st, 0);
+        const int ip1 = min(xc + st, g.n - 1), ip2 = min(xc + 2 * st, g.n - 1);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+          const int b = tid / CT + (256 / CT) * i;
+          const T *col = X + size_t(min(b, p - 1)) * ldx;
+          nbv[i][0] = col[im1];
+          nbv[i][1] = col[im2];
+          nbv[i][2] = col[ip1];
+          nbv[i][3] = col[ip2];
+        }
+      }
+    }
     __syncthreads();
     // X on cells x0-2 .. x0+CT+1 (clamped into the grid; only in-tile cells
     // and, for d = 0, in-grid x neighbours of in-tile cells are used)
@@ -816,6 +836,12 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
           const int b = tid / CT + (256 / CT) * i;
           put(b, Xh[(cc + 2) * PA + b], Xh[(cc + 1) * PA + b], Xh[cc * PA + b],
               Xh[(cc + 3) * PA + b], Xh[(cc + 4) * PA + b]);
+        }
+      } else if constexpr (EARLY) {   // y or z neighbours loaded above
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+          const int b = tid / CT + (256 / CT) * i;
+          put(b, Xh[(cc + 2) * PA + b], nbv[i][0], nbv[i][1], nbv[i][2], nbv[i][3]);
         }
       } else {        // y or z neighbours from memory (clamped; masked by s = 0)
         const int im1 = max(xc - st, 0), im2 = max(xc - 2 * st, 0);
@@ -905,26 +931,36 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int n, const T *__restrict__ 
   const int x_begin = blockIdx.x * chunk;
   const int x_end = min(n, x_begin + chunk);
   const int cc = tid % CT, col0 = tid / CT;
+  // the loads of the next tile are issued before the MFMAs of this one
+  T xr[PERA], yr[PERB], wr;
+  auto fetch = [&](int x0) {
+    const int xc = min(x0 + cc, x_end - 1);   // clamped: loads stay unconditional
+    wr = wf(xc);
+#pragma unroll
+    for (int i = 0; i < PERA; ++i) xr[i] = X[size_t(min(col0 + 4 * i, p - 1)) * ldx + xc];
+#pragma unroll
+    for (int i = 0; i < PERB; ++i) yr[i] = yf(xc, min(col0 + 4 * i, q - 1));
+  };
+  fetch(x_begin);
   for (int x0 = x_begin; x0 < x_end; x0 += CT) {
     __syncthreads();
     {
-      const int x = x0 + cc, xc = min(x, x_end - 1);
-      const bool xin = x < x_end;
-      const Tc wt = Tc(wf(xc));
+      const bool xin = x0 + cc < x_end;
+      const Tc wt = Tc(wr);
 #pragma unroll
       for (int i = 0; i < PERA; ++i) {
         const int a = col0 + 4 * i;
-        const Tc v = Tc(X[size_t(min(a, p - 1)) * ldx + xc]) * wt;
+        const Tc v = Tc(xr[i]) * wt;
         Xs[cc * PA + a] = (xin && a < p) ? v : Tc(0);
       }
 #pragma unroll
       for (int i = 0; i < PERB; ++i) {
         const int b = col0 + 4 * i;
-        const Tc v = Tc(yf(xc, min(b, q - 1)));
-        Ys[cc * PB + b] = (xin && b < q) ? v : Tc(0);
+        Ys[cc * PB + b] = (xin && b < q) ? Tc(yr[i]) : Tc(0);
       }
     }
     __syncthreads();
+    fetch(x0 + CT);
 #pragma unroll 2
     for (int k4 = 0; k4 < CT / 4; ++k4) {
       const int cell = 4 * k4 + qq;
@@ -1073,15 +1109,15 @@ __global__ void k_sumsq(int n, const T *__restrict__ X, int ld, int q, double *p
 // src_i(x) = sdt w_i(x) psi(x) (only when sw != nullptr), and optionally
 // dose(x) += dscale sum_j Z(x, j) dc(j).  The coefficient matrix (beta G with
 // the rows sC^T appended, as T, rows padded to a multiple of 4) is staged in
-// LDS once per block; the waves then take 16-cell tiles and compute the
-// transposed tile Z^T = Gs^T X^T: A(j, kk) = Gs(4t + kk, 16 jt + j) from LDS,
+// LDS once per block; the waves then take 32-cell tiles (two 16-cell halves)
+// and compute per half the transposed tile Z^T = Gs^T X^T: A(j, kk) = Gs(4t + kk, 16 jt + j) from LDS,
 // B(kk, i) = X(x0 + i, 4t + kk) from lane i + 16 kk, so the stores of 16
 // consecutive lanes are 16 consecutive cells of one column.  Y may alias Z
 // (each element is read and written by the same lane); X must not.
 constexpr int kUpdBlocks = 2048;
 constexpr int kUpdChunk = 8;      // MFMA k-steps whose loads are issued together
 
-template <typename T, int NQ>
+template <typename T, int NQ, bool HY>
 __global__ __launch_bounds__(256) void k_update_mfma(
     int n, const T *__restrict__ X, int ldx, int p, const double *__restrict__ G, int ldg,
     double beta, const T *Y, int ldy, double alpha, T *Z, int ldz, int q,
@@ -1110,63 +1146,87 @@ __global__ __launch_bounds__(256) void k_update_mfma(
   const int lane = threadIdx.x & 63;
   const int c = lane & 15, qd = lane >> 4;
   const int waves = gridDim.x * (blockDim.x >> 6);
-  const int ntiles = (n + 15) >> 4;
+  // 32-cell tiles: a wave takes two 16-cell halves at once, so that the loads
+  // of both (and the Y loads, issued first) are in flight together
+  const int ntiles = (n + 31) >> 5;
   for (int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < ntiles;
        tile += waves) {
-    const int x = 16 * tile + c;
-    const bool valid = x < n;
-    const int xc = valid ? x : n - 1;   // clamped: loads stay unconditional
-    const double srcs = sw != nullptr ? sdt * double(spsi[xc]) : 0.0;
-    acc_t acc[NQ];
+    int x[2], xc[2];
+    bool valid[2];
 #pragma unroll
-    for (int jt = 0; jt < NQ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+    for (int h = 0; h < 2; ++h) {
+      x[h] = 32 * tile + 16 * h + c;
+      valid[h] = x[h] < n;
+      xc[h] = valid[h] ? x[h] : n - 1;   // clamped: loads stay unconditional
+    }
+    T yraw[2][NQ][4];
+    if constexpr (HY) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int jt = 0; jt < NQ; ++jt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            yraw[h][jt][v] = Y[size_t(min(16 * jt + Mfma<T>::row(qd, v), q - 1)) * ldy + xc[h]];
+    }
+    double srcs[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) srcs[h] = sw != nullptr ? sdt * double(spsi[xc[h]]) : 0.0;
+    acc_t acc[2][NQ];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int jt = 0; jt < NQ; ++jt) acc[h][jt] = acc_t{0, 0, 0, 0};
     for (int k0 = 0; k0 < nk; k0 += 4 * kUpdChunk) {
-      T b[kUpdChunk];
+      T b[2][kUpdChunk];
 #pragma unroll
-      for (int u = 0; u < kUpdChunk; ++u) {
-        const int k = k0 + 4 * u + qd;
-        T v = X[size_t(min(k, p - 1)) * ldx + xc];
-        if (sw != nullptr) {
-          const T sv = T(double(sw[size_t(min(max(k - p, 0), n_mat - 1)) * n + xc]) * srcs);
-          v = k < p ? v : sv;
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int u = 0; u < kUpdChunk; ++u) {
+          const int k = k0 + 4 * u + qd;
+          T v = X[size_t(min(k, p - 1)) * ldx + xc[h]];
+          if (sw != nullptr) {
+            const T sv =
+                T(double(sw[size_t(min(max(k - p, 0), n_mat - 1)) * n + xc[h]]) * srcs[h]);
+            v = k < p ? v : sv;
+          }
+          b[h][u] = (valid[h] && k < ne) ? v : T(0);
         }
-        b[u] = (valid && k < ne) ? v : T(0);
-      }
 #pragma unroll
       for (int u = 0; u < kUpdChunk; ++u) {
         if (k0 + 4 * u < nk) {
           const T *ga = Gs + (k0 + 4 * u + qd) * QS + c;
 #pragma unroll
-          for (int jt = 0; jt < NQ; ++jt) acc[jt] = Mfma<T>::op(ga[16 * jt], b[u], acc[jt]);
+          for (int jt = 0; jt < NQ; ++jt) {
+            const T gv = ga[16 * jt];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc[h][jt] = Mfma<T>::op(gv, b[h][u], acc[h][jt]);
+          }
         }
       }
     }
-    double yv[NQ][4];
 #pragma unroll
-    for (int jt = 0; jt < NQ; ++jt)
+    for (int h = 0; h < 2; ++h) {
+      double dsum = 0.0;
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        yv[jt][v] = (Y != nullptr && alpha != 0.0)
-                        ? alpha * double(Y[size_t(min(16 * jt + Mfma<T>::row(qd, v), q - 1)) *
-                                               ldy + xc])
-                        : 0.0;
-    double dsum = 0.0;
+      for (int jt = 0; jt < NQ; ++jt) {
 #pragma unroll
-    for (int jt = 0; jt < NQ; ++jt) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = 16 * jt + Mfma<T>::row(qd, v);
-        if (valid && j < q) {
-          const T zv = T(double(acc[jt][v]) + yv[jt][v]);
-          Z[size_t(j) * ldz + x] = zv;
-          if (dose != nullptr) dsum += double(zv) * dcs[j];
+        for (int v = 0; v < 4; ++v) {
+          const int j = 16 * jt + Mfma<T>::row(qd, v);
+          double yv = 0.0;
+          if constexpr (HY) yv = alpha * double(yraw[h][jt][v]);
+          if (valid[h] && j < q) {
+            const T zv = T(double(acc[h][jt][v]) + yv);
+            Z[size_t(j) * ldz + x[h]] = zv;
+            if (dose != nullptr) dsum += double(zv) * dcs[j];
+          }
         }
       }
-    }
-    if (dose != nullptr) {
-      dsum += __shfl_xor(dsum, 16);
-      dsum += __shfl_xor(dsum, 32);
-      if (qd == 0 && valid) dose[x] += dscale * dsum;
+      if (dose != nullptr) {
+        dsum += __shfl_xor(dsum, 16);
+        dsum += __shfl_xor(dsum, 32);
+        if (qd == 0 && valid[h]) dose[x[h]] += dscale * dsum;
+      }
     }
   }
 }
@@ -1474,10 +1534,11 @@ static void update(int n, const T *X, int ldx, int p, const double *G, int ldg, 
   const int ne = p + (sw != nullptr ? n_mat : 0);
   const int nk = (ne + 3) & ~3;
   const size_t shm = size_t(nk) * 16 * nq * sizeof(T) + size_t(16) * nq * sizeof(double);
-  const int blocks = std::max(1, std::min(kUpdBlocks, (n + 63) / 64));
+  const int blocks = std::max(1, std::min(kUpdBlocks, (n + 127) / 128));
+  const bool HY = Y != nullptr && alpha != 0.0;
 #define DLRA_UPDATE(NQ)                                                                     \
   do {                                                                                      \
-    auto kern = k_update_mfma<T, NQ>;                                                       \
+    auto kern = HY ? k_update_mfma<T, NQ, true> : k_update_mfma<T, NQ, false>;              \
     if (shm > 65536)                                                                        \
       (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                        \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));     \
