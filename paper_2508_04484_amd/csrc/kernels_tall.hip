@@ -299,12 +299,13 @@ __host__ __device__ constexpr int brick_s_dwords(int dpe) {
   return (kBrickPC * dpe + 63) / 64 * 64;
 }
 
-__host__ __device__ constexpr size_t brick_lds_bytes(int rb, int tsize) {
+__host__ __device__ constexpr size_t brick_lds_bytes(int rb, int tsize, int js) {
   return size_t(4) * (size_t(brick_slots(tsize)) * rb * kBrickPC * (tsize / 4) +
                       size_t(brick_bufs(tsize)) * rb * kBrickHS * (tsize / 4) +
                       size_t(brick_slots(tsize)) * brick_s_dwords(tsize / 4) +
                       size_t(brick_bufs(tsize)) * kBrickHC * (tsize / 4) +
-                      size_t(brick_bufs(tsize)) * rb * kBrickKS * (tsize / 4) + 64);
+                      size_t(brick_bufs(tsize)) * rb * kBrickKS * (tsize / 4) + 64) +
+         (js == 2 ? size_t(2) * kBrickBY * 2 * 256 * tsize : 0);   // partial-sum exchange
 }
 
 // s_waitcnt vmcnt(N) (expcnt and lgkmcnt not waited for): at most N of this
@@ -357,10 +358,16 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     int zchunk) {
   constexpr int RB = 16 * NJ, KS = 4 * NJ, DPE = int(sizeof(T)) / 4, TB = int(sizeof(T));
   constexpr int BY = kBrickBY, RW = kBrickRW, PC = kBrickPC, HC = kBrickHC, HS = kBrickHS;
-  constexpr int KST = kBrickKS, NW = BY * JS, NJW = NJ / JS;
-  static_assert(NJ % JS == 0, "whole output tiles per wave");
+  constexpr int KST = kBrickKS, NW = BY * JS;
+  // JS = 2: the two waves of a brick row split the column blocks kq (the
+  // contraction) and swap their partial sums of each other's output tile
+  // through LDS once per plane; each stores one output tile
+  constexpr bool KSPLIT = JS == 2;
+  constexpr int KSW = KS / JS;                       // column blocks per wave
+  constexpr int NOUT = KSPLIT ? 1 : NJ;              // output tiles stored per wave
+  static_assert(JS == 1 || (JS == 2 && NJ == 2), "column split for two output tiles");
   constexpr int AH = brick_ahead(TB), NS = brick_slots(TB), NB = brick_bufs(TB);
-  static_assert(brick_lds_bytes(RB, TB) <= 160 * 1024, "fits the LDS");
+  static_assert(brick_lds_bytes(RB, TB, JS) <= 160 * 1024, "fits the LDS");
   constexpr int SPD = brick_s_dwords(DPE);           // dwords of one s ring plane
   constexpr int SP = SPD / DPE;                      // ... in elements
   constexpr int NPI = RB * PC * DPE / (64 * NW);     // W-plane loads per wave and step
@@ -381,20 +388,26 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
   T *haloS = ringS + NS * SP;                        // [NB][HC]
   T *K0t = haloS + NB * HC;                          // [NB][RB][KST]
   unsigned char *pad = reinterpret_cast<unsigned char *>(K0t + NB * RB * KST);   // 64 dwords
+  T *xbuf = reinterpret_cast<T *>(pad + 256);        // [2][BY][2][256] (KSPLIT)
   // block -> (brick column, z chunk); the hardware's round-robin of blocks
   // over the 8 XCDs gets one contiguous range of this order per XCD
   const int nblk = gridDim.x, b = blockIdx.x;
   const int xcd = b & 7, per = nblk >> 3, rem = nblk & 7;
   const int L = xcd * per + min(xcd, rem) + (b >> 3);
+  // columns in x-fastest order: an XCD's range covers whole rows of bricks,
+  // so the 128-byte lines shared by x neighbours (x halos, K0 and output
+  // rows) are fetched from HBM once into that XCD's L2
   const int zc = L % nzc, col = L / nzc;
-  const int by = col % nby, bx = col / nby;
+  const int nbx = (g.nx + 15) >> 4;
+  const int bx = col % nbx, by = col / nbx;
   const int gx0 = 16 * bx, gy0 = BY * by;
   const int z0 = zc * zchunk, z1 = min(g.nz, z0 + zchunk);
   if (z0 >= z1) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int row = wave % BY;                    // brick row of this wave
-  const int jh = wave / BY;                     // its output tiles jh NJW ..
+  const int jh = wave / BY;                     // KSPLIT: its half of the kq, its tile
+  const int kq0 = jh * KSW;                     // first column block of this wave
   const int c = lane & 15, q = lane >> 4;
   const int nx = g.nx, ny = g.ny, nz = g.nz, plane = nx * ny;
   const size_t tall_bytes = size_t(ld) * r * TB;
@@ -406,17 +419,17 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
   auto clampz = [&](int z) { return min(max(z, 0), nz - 1); };
   auto halo_y = [&](int hr) { return gy0 + (hr < 2 ? hr - 2 : BY + hr - 2); };
   // couplings: the A operands of all MFMAs of this lane
-  T bq[DIM][KS][NJW][2];
+  T bq[DIM][KSW][NJ][2];
 #pragma unroll
   for (int d = 0; d < DIM; ++d)
 #pragma unroll
-    for (int kq = 0; kq < KS; ++kq)
+    for (int kq = 0; kq < KSW; ++kq)
 #pragma unroll
-      for (int jt = 0; jt < NJW; ++jt)
+      for (int jt = 0; jt < NJ; ++jt)
 #pragma unroll
         for (int f = 0; f < 2; ++f)
-          bq[d][kq][jt][f] = Bp[size_t(2 * d + f) * RB * RB + (4 * kq + q) * RB +
-                                16 * (jh * NJW + jt) + c];
+          bq[d][kq][jt][f] =
+              Bp[size_t(2 * d + f) * RB * RB + (4 * (kq0 + kq) + q) * RB + 16 * jt + c];
   // per-lane byte offsets (within one z plane) of every load of the march
   int poff[NPI], hoff[NHI], koff[NKI], soff[NSI];
 #pragma unroll
@@ -517,7 +530,19 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     my[t] = gy + o >= 0 && gy + o < ny;
   }
   const int base = row * RW + c + 2;
-  T pend[NJW][4];   // outputs of the previous step, stored during this one
+  // outputs of the previous step, stored during this one (KSPLIT: own partial
+  // sums and K0, combined with the partner's partial sums at the store)
+  T pend[NOUT][4], pk0[NOUT][4];
+  auto xslot = [&](int zz, int writer) {
+    return xbuf + (((zz & 1) * BY + row) * 2 + writer) * 256 + lane;
+  };
+  auto out_value = [&](int jt, int v, int zz) {
+    if constexpr (KSPLIT) return pk0[jt][v] - tcoef * (pend[jt][v] + xslot(zz, 1 - jh)[64 * v]);
+    else return pend[jt][v];
+  };
+  auto out_col = [&](int jt, int v) {
+    return 16 * (KSPLIT ? jh : jt) + Mfma<T>::row(q, v);
+  };
   for (int z = z0; z < z1; ++z) {
     const int sc = slot(z), hb = z % NB;
     const T *Wc = ringW + sc * RB * PC, *Sc = ringS + sc * SP;
@@ -552,26 +577,26 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
       cf[d][1] = T(4) * ih[d] * sv[d][2];
       cf[d][2] = -ih[d] * sv[d][3];
     }
-    acc_t acc[NJW];
+    acc_t acc[NJ];
     // stores of the previous step's outputs, spread over this step's column
     // blocks like the loads
     auto store_part = [&](int lo, int hi) {
 #pragma unroll
-      for (int u = 0; u < NJW * 4; ++u) {
+      for (int u = 0; u < NOUT * 4; ++u) {
         const int jt = u / 4, v = u % 4;
-        const int j = 16 * (jh * NJW + jt) + Mfma<T>::row(q, v);
+        const int j = out_col(jt, v);
         if (u >= lo && u < hi && z > z0 && valid && j < r)
-          buf_store(pend[jt][v], rO, xyo + j * ld * TB, (z - 1) * plane * TB);
+          buf_store(out_value(jt, v, z - 1), rO, xyo + j * ld * TB, (z - 1) * plane * TB);
       }
     };
 #pragma unroll
-    for (int jt = 0; jt < NJW; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+    for (int jt = 0; jt < NJ; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
     // software pipeline over the column blocks kq: the LDS reads of block
     // kq + 1 are issued before the MFMAs of block kq and its differences are
     // formed after them, so the reads complete under the matrix work
     T sten[1 + 4 * DIM];
     auto read_sten = [&](int kq) {
-      const int ok = (4 * kq + q) * PC;   // column offset (PC == HS)
+      const int ok = (4 * (kq0 + kq) + q) * PC;   // column offset (PC == HS)
       sten[0] = Wc[ok + base];
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
@@ -592,28 +617,40 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     read_sten(0);
     diffs();
 #pragma unroll
-    for (int kq = 0; kq < KS; ++kq) {
-      if (kq + 1 < KS) read_sten(kq + 1);
-      issue_part(kq * NLOADS / KS, (kq + 1) * NLOADS / KS, z + 1 + AH, z + AH - 1);
-      store_part(kq * NJW * 4 / KS, (kq + 1) * NJW * 4 / KS);
+    for (int kq = 0; kq < KSW; ++kq) {
+      if (kq + 1 < KSW) read_sten(kq + 1);
+      issue_part(kq * NLOADS / KSW, (kq + 1) * NLOADS / KSW, z + 1 + AH, z + AH - 1);
+      store_part(kq * NOUT * 4 / KSW, (kq + 1) * NOUT * 4 / KSW);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
 #pragma unroll
-        for (int jt = 0; jt < NJW; ++jt) {
+        for (int jt = 0; jt < NJ; ++jt) {
           acc[jt] = Mfma<T>::op(bq[d][kq][jt][0], db[d], acc[jt]);
           acc[jt] = Mfma<T>::op(bq[d][kq][jt][1], df[d], acc[jt]);
         }
       __builtin_amdgcn_sched_barrier(0);
-      if (kq + 1 < KS) diffs();
+      if (kq + 1 < KSW) diffs();
     }
     const T *Kt = K0t + hb * RB * KST + row * 16 + c;
-#pragma unroll
-    for (int jt = 0; jt < NJW; ++jt) {
+    if constexpr (KSPLIT) {
+      // partial sums of the partner's tile to LDS (read after the barrier);
+      // own partial sums and K0 of the own tile kept for the next step
+      T *xs = xslot(z, jh);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * (jh * NJW + jt) + Mfma<T>::row(q, v);
-        pend[jt][v] = Kt[j * KST] - tcoef * acc[jt][v];
+        xs[64 * v] = jh ? acc[0][v] : acc[1][v];
+        pend[0][v] = jh ? acc[1][v] : acc[0][v];
+        pk0[0][v] = Kt[out_col(0, v) * KST];
+      }
+      // the LDS writes complete before the barrier
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+    } else {
+#pragma unroll
+      for (int jt = 0; jt < NJ; ++jt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          pend[jt][v] = Kt[out_col(jt, v) * KST] - tcoef * acc[jt][v];
       }
     }
     // the loads of step z + 1 (issued during step z + 2 - AH) must have
@@ -624,11 +661,12 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     block_barrier();
   }
 #pragma unroll
-  for (int jt = 0; jt < NJW; ++jt) {
+  for (int jt = 0; jt < NOUT; ++jt) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int j = 16 * (jh * NJW + jt) + Mfma<T>::row(q, v);
-      if (valid && j < r) buf_store(pend[jt][v], rO, xyo + j * ld * TB, (z1 - 1) * plane * TB);
+      const int j = out_col(jt, v);
+      if (valid && j < r)
+        buf_store(out_value(jt, v, z1 - 1), rO, xyo + j * ld * TB, (z1 - 1) * plane * TB);
     }
   }
   wait_vm<0>();   // no load into LDS outlives the block
@@ -1292,7 +1330,7 @@ template <typename T, int NJ, int DIM, int JS = 1>
 static void kstage_brick_launch(const GridDev &g, const T *s, const T *W, const T *K0, T *out,
                                 int ld, int r, const T *Bp, double coef, hipStream_t st) {
   constexpr int NT = 64 * kBrickBY * JS;
-  const size_t shm = brick_lds_bytes(16 * NJ, int(sizeof(T)));
+  const size_t shm = brick_lds_bytes(16 * NJ, int(sizeof(T)), JS);
   auto kern = k_kstage_brick<T, NJ, DIM, JS>;
   static std::atomic<int> blocks_cache{0};
   int cap = blocks_cache.load(std::memory_order_relaxed);
