@@ -533,6 +533,9 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
   // outputs of the previous step, stored during this one (KSPLIT: own partial
   // sums and K0, combined with the partner's partial sums at the store)
   T pend[NOUT][4], pk0[NOUT][4];
+  // this lane's column offset in a ring plane or halo (PC == HS): column
+  // 4 kq0 + q; the column blocks kq then add compile-time offsets
+  const int qoff = (4 * kq0 + q) * PC;
   auto xslot = [&](int zz, int writer) {
     return xbuf + (((zz & 1) * BY + row) * 2 + writer) * 256 + lane;
   };
@@ -551,16 +554,16 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int o = t < 2 ? t - 2 : t - 1;
-      wp[0][t] = Wc + base + o;
+      wp[0][t] = Wc + base + o + qoff;
       sv[0][t] = mx[t] ? Sc[base + o] : T(0);
       const int yr = row + o;
       const bool inb = yr >= 0 && yr < BY;
       const int hr = yr < 0 ? yr + 2 : yr - BY + 2;
-      wp[1][t] = inb ? Wc + yr * RW + c + 2 : haloW + hb * RB * HS + hr * 16 + c;
+      wp[1][t] = (inb ? Wc + yr * RW + c + 2 : haloW + hb * RB * HS + hr * 16 + c) + qoff;
       const T syv = inb ? Sc[yr * RW + c + 2] : haloS[hb * HC + hr * 16 + c];
       sv[1][t] = my[t] ? syv : T(0);
       if constexpr (DIM == 3) {
-        wp[2][t] = ringW + slot(z + o) * RB * PC + base;
+        wp[2][t] = ringW + slot(z + o) * RB * PC + base + qoff;
         const bool mz = z + o >= 0 && z + o < nz;
         sv[2][t] = mz ? ringS[slot(z + o) * SP + base] : T(0);
       }
@@ -595,9 +598,10 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     // kq + 1 are issued before the MFMAs of block kq and its differences are
     // formed after them, so the reads complete under the matrix work
     T sten[1 + 4 * DIM];
+    const T *wc0 = Wc + base + qoff;
     auto read_sten = [&](int kq) {
-      const int ok = (4 * (kq0 + kq) + q) * PC;   // column offset (PC == HS)
-      sten[0] = Wc[ok + base];
+      const int ok = 4 * kq * PC;   // column block offset (PC == HS)
+      sten[0] = wc0[ok];
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
 #pragma unroll
