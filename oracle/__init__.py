@@ -16,4 +16,5 @@ Modules
   dlra        the dynamical low-rank step (Sec. 2.2 and Sec. 3.3.3)
   raytrace    the uncollided ray tracer (Sec. 3.2)
   solver      drivers that run whole problems
+  adjoint     plan objective over beam weights and its closed-form gradient
 """
