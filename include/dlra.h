@@ -199,6 +199,29 @@ int dlra_sync(dlra_ctx *ctx);
  *             from dlra_last_error() in the calling thread). */
 int dlra_run_batch(dlra_ctx *const *ctxs, int n_ctx, int n_steps, int n_threads);
 
+/* Treatment-plan objective over beam weights and its exact gradient.  The
+ * transport equations are linear in the incoming flux (Sec. 3.2, Sec. 3.3),
+ * so the dose of a plan is D = sum_b w_b D_b with D_b the dose of beam b at
+ * unit weight.  For
+ *   J(w) = sum_{x in T} (D(x) - dhat)^2 + lam sum_{x not in T} D(x)^2
+ * the gradient is dJ/dw_b = sum_x g(x) D_b(x), g = dJ/dD: the adjoint of the
+ * linear dose map, which needs no reverse sweep through the integrator.
+ * (Gradients with respect to voxel densities are not provided.)
+ *   doses    device, [n_beams][n_cells] FP64, cells x-fastest (dose_deposit)
+ *   weights  host, [n_beams]; target: device, [n_cells], nonzero = in T
+ *   dhat     prescription level; lam >= 0 weight of the dose outside T
+ *   work     device, >= dlra_plan_objective_work(n_cells, n_beams) doubles,
+ *            owned by the caller
+ *   stream   HIP stream (NULL: the default stream); the call synchronises it
+ *   J, grad  host outputs: the objective and [n_beams] gradient entries
+ * Sums are taken in a fixed order (identical results on every call).
+ * DLRA_E_INVALID for n_cells <= 0, n_beams outside [1, 64], null pointers,
+ * a too small work space, lam < 0 or non-finite inputs. */
+size_t dlra_plan_objective_work(int n_cells, int n_beams);
+int dlra_plan_objective(int n_cells, int n_beams, const double *doses, const double *weights,
+                        const unsigned char *target, double dhat, double lam, double *work,
+                        size_t work_doubles, void *stream, double *J, double *grad);
+
 /* Timing of the library's own work with HIP events recorded on the context's
  * stream (measurement support; adds one event pair per timed launch).
  *   dlra_profile(ctx, on): on = 1 starts recording, 0 stops; counters are

@@ -24,7 +24,7 @@ DOSE_UNCOLLIDED, DOSE_COLLIDED, DOSE_PER_MASS = 1, 2, 4
 EXPORTS = ["dlra_workspace_size", "dlra_init", "uncollided_raytrace", "dlra_step",
            "dose_deposit", "dlra_get_state", "dlra_set_state", "dlra_get_uncollided",
            "dlra_substeps", "dlra_sync", "dlra_profile", "dlra_profile_read", "dlra_run_batch",
-           "dlra_destroy", "dlra_last_error"]
+           "dlra_plan_objective", "dlra_plan_objective_work", "dlra_destroy", "dlra_last_error"]
 PHASES = ["kstage", "projection", "lstep", "augment", "sstep", "truncate", "collided", "source",
           "step", "raytrace"]
 
@@ -91,11 +91,15 @@ def load(path: str = LIB_PATH):
     lib.dlra_profile.argtypes = [P, I]
     lib.dlra_profile_read.argtypes = [P, I, D, C.POINTER(C.c_longlong)]
     lib.dlra_run_batch.argtypes = [C.POINTER(P), I, I, I]
+    lib.dlra_plan_objective.argtypes = [I, I, V, D, V, C.c_double, C.c_double, V, C.c_size_t, V,
+                                        D, D]
+    lib.dlra_plan_objective_work.argtypes = [I, I]
     lib.dlra_destroy.argtypes = [P]
     lib.dlra_destroy.restype = None
     lib.dlra_last_error.restype = C.c_char_p
     for name in EXPORTS[:-2]:
         getattr(lib, name).restype = C.c_int
+    lib.dlra_plan_objective_work.restype = C.c_size_t
     _lib = lib
     return lib
 
@@ -263,6 +267,36 @@ def batch_solvers(problem, beam_indices=None):
     import torch
     idx = range(len(problem.beams)) if beam_indices is None else beam_indices
     return [BeamSolver(problem, b, stream=torch.cuda.Stream()) for b in idx]
+
+
+def plan_objective(doses, weights, target, dhat, lam, stream=None):
+    """Plan objective J and its gradient over the beam weights (the library's
+    dlra_plan_objective).  doses: torch float64 CUDA tensor [n_beams, n_cells];
+    target: torch uint8 CUDA tensor [n_cells]; weights: host sequence.
+    Returns (J, grad as a numpy array)."""
+    import torch
+    lib = load()
+    nb, n = int(doses.shape[0]), int(doses.shape[1])
+    if doses.dtype != torch.float64 or not doses.is_cuda or not doses.is_contiguous():
+        raise ValueError("doses must be a contiguous float64 CUDA tensor")
+    if target.dtype != torch.uint8 or not target.is_cuda or target.numel() != n:
+        raise ValueError("target must be a uint8 CUDA tensor of n_cells entries")
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    if w.shape != (nb,):
+        raise ValueError("one weight per beam")
+    nwork = lib.dlra_plan_objective_work(n, nb)
+    if nwork == 0:
+        check(lib.dlra_plan_objective(n, nb, None, None, None, 0.0, 0.0, None, 0, None,
+                                      None, None))
+    work = torch.empty(nwork, dtype=torch.float64, device=doses.device)
+    st = torch.cuda.current_stream(doses.device) if stream is None else stream
+    J = C.c_double(0.0)
+    grad = np.zeros(nb)
+    check(lib.dlra_plan_objective(n, nb, C.c_void_p(doses.data_ptr()), _dptr(w),
+                                  C.c_void_p(target.data_ptr()), float(dhat), float(lam),
+                                  C.c_void_p(work.data_ptr()), nwork, C.c_void_p(st.cuda_stream),
+                                  C.byref(J), _dptr(grad)))
+    return J.value, grad
 
 
 def solve(problem, n_steps=None):

@@ -1095,6 +1095,43 @@ int dlra_profile_read(dlra_ctx *c, int phase, double *total_ms, long long *count
 
 void dlra_destroy(dlra_ctx *c) { delete c; }
 
+size_t dlra_plan_objective_work(int n_cells, int n_beams) {
+  if (n_cells <= 0 || n_beams < 1 || n_beams > kPlanMaxBeams) return 0;
+  return plan_objective_work(n_cells, n_beams);
+}
+
+int dlra_plan_objective(int n_cells, int n_beams, const double *doses, const double *weights,
+                        const unsigned char *target, double dhat, double lam, double *work,
+                        size_t work_doubles, void *stream, double *J, double *grad) {
+  if (n_cells <= 0 || n_beams < 1 || n_beams > kPlanMaxBeams)
+    return fail(DLRA_E_INVALID, "n_cells must be positive and n_beams in [1, 64]");
+  if (!doses || !weights || !target || !work || !J || !grad)
+    return fail(DLRA_E_INVALID, "null argument");
+  if (!(lam >= 0.0) || !std::isfinite(lam) || !std::isfinite(dhat))
+    return fail(DLRA_E_INVALID, "lam must be finite and >= 0, dhat finite");
+  if (work_doubles < plan_objective_work(n_cells, n_beams))
+    return fail(DLRA_E_INVALID, "work space smaller than dlra_plan_objective_work()");
+  PlanWeights pw{};
+  for (int b = 0; b < n_beams; ++b) {
+    if (!std::isfinite(weights[b])) return fail(DLRA_E_INVALID, "non-finite weight");
+    pw.w[b] = weights[b];
+  }
+  try {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *out = work + plan_objective_work(n_cells, n_beams) - size_t(n_beams + 1);
+    launch_plan_objective(n_cells, n_beams, doses, pw, target, dhat, lam, work, out, st);
+    HIPCHK(hipGetLastError());
+    std::vector<double> h(size_t(n_beams) + 1);
+    HIPCHK(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *J = h[0];
+    for (int b = 0; b < n_beams; ++b) grad[b] = h[1 + b];
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  return DLRA_OK;
+}
+
 int dlra_run_batch(dlra_ctx *const *ctxs, int n_ctx, int n_steps, int n_threads) {
   if (!ctxs || n_ctx < 0 || n_steps < 0) return fail(DLRA_E_INVALID, "bad batch arguments");
   for (int i = 0; i < n_ctx; ++i) {

@@ -147,6 +147,17 @@ void launch_qr_complete(int m, int r, const double *L1, const double *V, double 
                         double *work, hipStream_t st);
 
 // reduction of per-block partial sums: out[e] = sum_b partial[b*elems + e]
+// plan objective over beam weights and its gradient (out[0] = J, out[1 + b] =
+// dJ/dw_b); work holds plan_objective_work(n, nb) doubles
+constexpr int kPlanMaxBeams = 64;
+constexpr int kPlanBlocks = 512;
+struct PlanWeights {
+  double w[kPlanMaxBeams];
+};
+size_t plan_objective_work(int n, int nb);
+void launch_plan_objective(int n, int nb, const double *doses, const PlanWeights &pw,
+                           const unsigned char *target, double dhat, double lam, double *work,
+                           double *out, hipStream_t st);
 void launch_reduce_partials(const double *partial, int nblocks, int elems, double *out,
                             hipStream_t st);
 

@@ -1618,6 +1618,69 @@ void launch_zero_cols(int n, T *X, int ld, int c0, int c1, hipStream_t st) {
   k_zero_cols<T><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(n, X, ld, c0, c1);
 }
 
+// ------------------------------------------------------------------ plan objective
+// D(x) = sum_b w_b D_b(x); J = sum_{x in T} (D - dhat)^2 + lam sum_{x not in T} D^2;
+// dJ/dw_b = sum_x g(x) D_b(x) with g = dJ/dD (2 (D - dhat) on T, 2 lam D off it).
+// Block k of both kernels covers the cells [k chunk, (k + 1) chunk); partial
+// row k holds its J share (element 0) and its share of every dJ/dw_b.
+__global__ __launch_bounds__(256) void k_plan_residual(int n, int nb, const double *__restrict__ doses,
+                                                       PlanWeights pw,
+                                                       const unsigned char *__restrict__ target,
+                                                       double dhat, double lam, int chunk,
+                                                       double *__restrict__ g,
+                                                       double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int x0 = blockIdx.x * chunk, x1 = min(n, x0 + chunk);
+  double acc = 0.0;
+  for (int x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
+    double D = 0.0;
+    for (int b = 0; b < nb; ++b) D += pw.w[b] * doses[size_t(b) * n + x];
+    const bool in = target[x] != 0;
+    const double e = in ? D - dhat : D;
+    acc += in ? e * e : lam * e * e;
+    g[x] = in ? 2.0 * e : 2.0 * lam * e;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    partial[size_t(blockIdx.x) * (nb + 1)] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_plan_dots(int n, int nb, const double *__restrict__ doses,
+                                                   const double *__restrict__ g, int chunk,
+                                                   double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int b = blockIdx.y;
+  const int x0 = blockIdx.x * chunk, x1 = min(n, x0 + chunk);
+  const double *Db = doses + size_t(b) * n;
+  double acc = 0.0;
+  for (int x = x0 + threadIdx.x; x < x1; x += blockDim.x) acc += g[x] * Db[x];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    partial[size_t(blockIdx.x) * (nb + 1) + 1 + b] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+static int plan_blocks(int n) { return std::max(1, std::min(kPlanBlocks, (n + 255) / 256)); }
+
+size_t plan_objective_work(int n, int nb) {
+  return size_t(n) + size_t(plan_blocks(n) + 1 + 64) * size_t(nb + 1);
+}
+
+void launch_plan_objective(int n, int nb, const double *doses, const PlanWeights &pw,
+                           const unsigned char *target, double dhat, double lam, double *work,
+                           double *out, hipStream_t st) {
+  const int nblk = plan_blocks(n);
+  const int chunk = (n + nblk - 1) / nblk;
+  double *g = work, *partial = work + n;
+  double *scratch = partial + size_t(nblk) * (nb + 1);
+  k_plan_residual<<<nblk, 256, 0, st>>>(n, nb, doses, pw, target, dhat, lam, chunk, g, partial);
+  k_plan_dots<<<dim3(nblk, nb), 256, 0, st>>>(n, nb, doses, g, chunk, partial);
+  reduce_partials(partial, nblk, nb + 1, out, st, scratch, size_t(64) * (nb + 1));
+}
+
 void launch_reduce_partials(const double *partial, int nblocks, int elems, double *out,
                             hipStream_t st) {
   reduce_partials(partial, nblocks, elems, out, st);

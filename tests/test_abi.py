@@ -16,7 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "dlra.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*([a-z_]+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:int|void|size_t|const char \*)\s*\**\s*([a-z_]+)\s*\(", src,
+                       flags=re.M)
     return sorted(set(names))
 
 
@@ -69,3 +70,25 @@ def test_init_rejects_null_workspace_without_touching_the_gpu():
     rc = lib.dlra_init(C.byref(B.make_grid(p.grid)), None, None,
                        C.byref(B.make_options(p.options)), None, 0, None, C.byref(ctx))
     assert rc == -1 and not ctx.value
+
+
+def test_plan_objective_rejects_bad_arguments_without_touching_the_gpu():
+    lib = B.load()
+    assert lib.dlra_plan_objective_work(0, 2) == 0
+    assert lib.dlra_plan_objective_work(100, 65) == 0
+    assert lib.dlra_plan_objective_work(100, 2) >= 100 + 3
+    J = C.c_double()
+    g = (C.c_double * 2)()
+    w = (C.c_double * 2)(1.0, 1.0)
+    gp = C.cast(g, C.POINTER(C.c_double))
+    wp = C.cast(w, C.POINTER(C.c_double))
+    # null device pointers, too small a work space, negative penalty, bad counts
+    assert lib.dlra_plan_objective(100, 2, None, wp, None, 1.0, 0.1, None, 10 ** 6, None,
+                                   C.byref(J), gp) == -1
+    fake = C.c_void_p(16)   # never dereferenced: validation fails first
+    assert lib.dlra_plan_objective(100, 2, fake, wp, fake, 1.0, 0.1, fake, 3, None,
+                                   C.byref(J), gp) == -1
+    assert lib.dlra_plan_objective(100, 2, fake, wp, fake, 1.0, -0.1, fake, 10 ** 6, None,
+                                   C.byref(J), gp) == -1
+    assert lib.dlra_plan_objective(100, 0, fake, wp, fake, 1.0, 0.1, fake, 10 ** 6, None,
+                                   C.byref(J), gp) == -1
