@@ -277,6 +277,7 @@ __device__ int blk_fill(double *Q, int ldq, int p, int cnt, int need, int ncand,
       blk_coefs(Q, ldq, p, cnt, v, coef);
       for (int t = threadIdx.x; t < p; t += blockDim.x) {
         double s = v[t];
+#pragma unroll 8
         for (int j = 0; j < cnt; ++j) s -= Q[t + size_t(j) * ldq] * coef[j];
         v[t] = s;
       }
@@ -342,6 +343,7 @@ __global__ __launch_bounds__(256) void k_sstep_stage(int P, int ld, int ndk,
       if (c_in_lds)
         for (int k = 0; k < P; ++k) acc += Cs[i + k * P] * Ts[k + jj * P];
       else
+#pragma unroll 8
         for (int k = 0; k < P; ++k) acc += C[i + size_t(k) * ld] * Ts[k + jj * P];
       F[u] -= acc;
     }
@@ -440,6 +442,7 @@ __global__ void k_lstep_combine(int m, int r, int ndk, const double *__restrict_
   for (int dk = 0; dk < ndk; ++dk) {
     const double *Td = T + dk * ts;
     const double *Cd = C + size_t(dk) * ldc * ldc;
+#pragma unroll 8
     for (int k = 0; k < r; ++k) acc += Td[i + size_t(k) * m] * Cd[j + size_t(k) * ldc];
   }
   out[i + size_t(j) * m] = L0[i + size_t(j) * m] - coef * acc;
@@ -517,6 +520,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
     for (int e = threadIdx.x; e < m * r; e += blockDim.x) {              // R -= V G
       int i = e % m, j = e / m;
       double s = 0.0;
+#pragma unroll 8
       for (int k = 0; k < r; ++k) s += Vh[i + size_t(k) * ldv] * G[k + j * r];
       R[e] -= s;
     }
@@ -535,6 +539,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
     int i = e % m, c = e / m;
     int j = order[c];
     double s = 0.0;
+#pragma unroll 8
     for (int k = 0; k < r; ++k) s += R[i + size_t(k) * m] * Q[k + j * r];
     X[i + size_t(c) * m] = s / sqrt(sig[j]);
   }
@@ -545,6 +550,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
     for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
       int i = e % m, j = e / m;
       double s = 0.0;
+#pragma unroll 8
       for (int k = 0; k < r; ++k) s += Vh[i + size_t(k) * ldv] * G[k + j * r];
       X[e] -= s;
     }
@@ -556,6 +562,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
       for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
         int i = e % m, c = e / m;
         double s = 0.0;
+#pragma unroll 8
         for (int k = 0; k <= c; ++k) s += X[i + size_t(k) * m] * Q[k + c * kept];
         Vh[i + size_t(r + c) * ldv] = s;
       }
@@ -568,6 +575,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
         int i = e % m, c = e / m;
         int j = order[c];
         double s = 0.0;
+#pragma unroll 8
         for (int k = 0; k < kept; ++k) s += X[i + size_t(k) * m] * Q[k + j * kept];
         Vh[i + size_t(r + c) * ldv] = s / sqrt(sig[j]);
       }
@@ -736,6 +744,7 @@ __global__ __launch_bounds__(kWG) void k_qr_complete(int m, int r, const double 
         blk_coefs(Vt, m, m, cnt, v, coef);
         for (int t = threadIdx.x; t < m; t += blockDim.x) {
           double s = v[t];
+#pragma unroll 8
           for (int j = 0; j < cnt; ++j) s -= Vt[t + size_t(j) * m] * coef[j];
           v[t] = s;
         }
