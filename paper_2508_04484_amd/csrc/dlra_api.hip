@@ -675,6 +675,11 @@ struct Stepper {
         std::swap(Lk, Lb);
       }
     }
+    {
+      // the V-side augmentation needs only V and L1: on the side stream too
+      PhaseTimer t(c, DLRA_PH_AUGMENT, c->st2);
+      launch_vaug(m, r, c->V, m, Lk, c->opt.aug_tol, &ctl->kV, D(p.work), c->st2);
+    }
     HIPCHK(hipEventRecord(c->ev_join, c->st2));
     // K-step: K0 = U S, Horner RK4
     launch_pack_couplings<T>(dd.ndk, r, D(p.Bm), P, c->at<T>(p.Bpk), st);
@@ -697,7 +702,6 @@ struct Stepper {
     {
       PhaseTimer t(c, DLRA_PH_AUGMENT);
       augment_u(r, tall(1));
-      launch_vaug(m, r, c->V, m, Lk, c->opt.aug_tol, &ctl->kV, D(p.work), st);
     }
     // S-step on the augmented bases
     {
@@ -741,11 +745,19 @@ struct Stepper {
       launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, D(p.Lm), m, 0, 1, st);
       launch_small_gemm(0, 1, m, r, nm, dt, gk, m, 0, D(p.H), P, 0, 1.0, D(p.Lm), m, 0, 1, st);
     }
+    // V-side augmentation on the side stream beside the U-side one
+    HIPCHK(hipEventRecord(c->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(c->st2, c->ev_fork, 0));
+    {
+      PhaseTimer t(c, DLRA_PH_AUGMENT, c->st2);
+      launch_vaug(m, r, c->V, m, D(p.Lm), c->opt.aug_tol, &ctl->kV, D(p.work), c->st2);
+    }
+    HIPCHK(hipEventRecord(c->ev_join, c->st2));
     {
       PhaseTimer t(c, DLRA_PH_AUGMENT);
       augment_u(r, tall(1));
-      launch_vaug(m, r, c->V, m, D(p.Lm), c->opt.aug_tol, &ctl->kV, D(p.work), st);
     }
+    HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
     {
       PhaseTimer t(c, DLRA_PH_SOURCE);
       launch_xt_source<T, Acc>(n, tall(0), ld, 2 * r, c->at<T>(p.w_t), nm, psi, D(p.H), P,
