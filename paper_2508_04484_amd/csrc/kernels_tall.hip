@@ -808,48 +808,69 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
     for (int at = 0; at < NA; ++at) ab[bt][at] = af[bt][at] = acc_t{0, 0, 0, 0};
   const int x_begin = bx * chunk;
   const int x_end = min(g.n, x_begin + chunk);
-  // for d != 0 and small NA the y / z neighbours are loaded together with the
-  // staging loads (one memory round trip per tile)
+  // The loads of tile x0 + CT (X with halo, s at the stencil points and, for
+  // d != 0 and small NA, the y / z neighbours) are issued into registers
+  // before the MFMAs of tile x0; all loads are clamped and unconditional.
   constexpr bool EARLY = NA <= 2;
+  constexpr int NSW = (5 * CT + 255) / 256;        // s values per thread
+  T xr[PERH], sr[NSW];
   T nbv[EARLY ? PER : 1][4];
-  for (int x0 = x_begin; x0 < x_end; x0 += CT) {
-    if constexpr (EARLY) {
-      if (d != 0) {
-        const int cc = tid % CT, xc = min(x0 + cc, x_end - 1);
-        const int im1 = max(xc - st, 0), im2 = max(xc - 2 * st, 0);
-        const int ip1 = min(xc + st, g.n - 1), ip2 = min(xc + 2 * st, g.n - 1);
+  // cell offset of stencil point t (0, -1, -2, +1, +2) of tile cell cc; in grid?
+  auto s_point = [&](int x0, int e, int &src) {
+    const int t = e / CT, cc = e % CT;
+    const int xc = min(x0 + cc, x_end - 1);
+    const int cd = d == 0 ? xc % g.nx : (d == 1 ? (xc / g.nx) % g.ny : xc / (g.nx * g.ny));
+    const int o = t == 0 ? 0 : (t < 3 ? -t : t - 2);
+    const bool in = cd + o >= 0 && cd + o < size;
+    src = in ? xc + o * st : xc;
+    return in;
+  };
+  auto fetch = [&](int x0) {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-          const int b = tid / CT + (256 / CT) * i;
-          const T *col = X + size_t(min(b, p - 1)) * ldx;
-          nbv[i][0] = col[im1];
-          nbv[i][1] = col[im2];
-          nbv[i][2] = col[ip1];
-          nbv[i][3] = col[ip2];
-        }
+    for (int i = 0; i < PERH; ++i) {
+      const int e = min(tid + 256 * i, CH * 16 * NA - 1);
+      const int hc = e % CH, a = e / CH;
+      const int xc = min(max(x0 - 2 + hc, 0), g.n - 1);
+      xr[i] = X[size_t(min(a, p - 1)) * ldx + xc];
+    }
+#pragma unroll
+    for (int u = 0; u < NSW; ++u) {
+      int src;
+      (void)s_point(x0, min(tid + 256 * u, 5 * CT - 1), src);
+      sr[u] = s[src];
+    }
+    if constexpr (EARLY) {
+      const int cc = tid % CT, xc = min(x0 + cc, x_end - 1);
+      const int im1 = max(xc - st, 0), im2 = max(xc - 2 * st, 0);
+      const int ip1 = min(xc + st, g.n - 1), ip2 = min(xc + 2 * st, g.n - 1);
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int b = tid / CT + (256 / CT) * i;
+        const T *col = X + size_t(min(b, p - 1)) * ldx;
+        nbv[i][0] = col[im1];
+        nbv[i][1] = col[im2];
+        nbv[i][2] = col[ip1];
+        nbv[i][3] = col[ip2];
       }
     }
+  };
+  fetch(x_begin);
+  for (int x0 = x_begin; x0 < x_end; x0 += CT) {
     __syncthreads();
     // X on cells x0-2 .. x0+CT+1 (clamped into the grid; only in-tile cells
     // and, for d = 0, in-grid x neighbours of in-tile cells are used)
 #pragma unroll
     for (int i = 0; i < PERH; ++i) {
       const int e = tid + 256 * i;
-      if (e < CH * 16 * NA) {
-        const int hc = e % CH, a = e / CH;
-        const int xc = min(max(x0 - 2 + hc, 0), g.n - 1);
-        Xh[hc * PA + a] = X[size_t(min(a, p - 1)) * ldx + xc];
-      }
+      if (e < CH * 16 * NA) Xh[(e % CH) * PA + e / CH] = xr[i];
     }
     // s at the stencil points of every tile cell, zero outside the grid
-    for (int e = tid; e < 5 * CT; e += 256) {
-      const int t = e / CT, cc = e % CT;
-      const int xc = min(x0 + cc, x_end - 1);
-      const int cd = d == 0 ? xc % g.nx : (d == 1 ? (xc / g.nx) % g.ny : xc / (g.nx * g.ny));
-      const int o = t == 0 ? 0 : (t < 3 ? -t : t - 2);   // 0, -1, -2, +1, +2
-      const bool in = cd + o >= 0 && cd + o < size;
-      const T v = s[in ? xc + o * st : xc];
-      Sw[t * CT + cc] = in ? v : T(0);
+#pragma unroll
+    for (int u = 0; u < NSW; ++u) {
+      const int e = tid + 256 * u;
+      int src;
+      const bool in = s_point(x0, min(e, 5 * CT - 1), src);
+      if (e < 5 * CT) Sw[e] = in ? sr[u] : T(0);
     }
     __syncthreads();
 #pragma unroll
@@ -896,6 +917,7 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
         }
       }
     }
+    fetch(x0 + CT);   // past the chunk end: clamped, unused
     __syncthreads();
 #pragma unroll 2
     for (int k4 = 0; k4 < CT / 4; ++k4) {
