@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdint>
 
 #include "kernels.hpp"
 
@@ -1295,6 +1296,147 @@ __global__ __launch_bounds__(256) void k_update_mfma(
   }
 }
 
+// FP32 form with 16-byte accesses: a wave takes 64 cells and lane (c, qd)
+// loads the four consecutive cells 64 t + 4 c .. 64 t + 4 c + 3 of a column at
+// once; MFMA i (i = 0..3) takes the cells 64 t + 4 c + i, so the four
+// accumulators of one output row are again four consecutive cells (one
+// 16-byte store).  Each output is formed by the same MFMA sequence as in
+// k_update_mfma.  A tile that ends past n takes clamped scalar accesses.
+template <int NQ, bool HY>
+__global__ __launch_bounds__(256) void k_update_vec(
+    int n, const float *__restrict__ X, int ldx, int p, const double *__restrict__ G, int ldg,
+    double beta, const float *Y, int ldy, double alpha, float *Z, int ldz, int q,
+    double *__restrict__ dose, const double *__restrict__ dc, double dscale,
+    const float *__restrict__ sw, int n_mat, const float *__restrict__ spsi,
+    const double *__restrict__ sC, int ldsc, double sdt) {
+  using acc_t = typename Mfma<float>::acc_t;
+  constexpr int QS = 16 * NQ;
+  extern __shared__ unsigned char smem_raw[];
+  const int ne = p + (sw != nullptr ? n_mat : 0);
+  const int nk = (ne + 3) & ~3;
+  float *Gs = reinterpret_cast<float *>(smem_raw);             // [nk][QS]
+  double *dcs = reinterpret_cast<double *>(Gs + nk * QS);      // [QS]
+  for (int e = threadIdx.x; e < nk * QS; e += blockDim.x) {
+    const int a = e / QS, j = e % QS;
+    double v = 0.0;
+    if (j < q) {
+      if (a < p) v = beta * G[size_t(j) * ldg + a];
+      else if (a < ne) v = sC[j + size_t(a - p) * ldsc];
+    }
+    Gs[e] = float(v);
+  }
+  if (dose != nullptr)
+    for (int j = threadIdx.x; j < QS; j += blockDim.x) dcs[j] = j < q ? dc[j] : 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 15, qd = lane >> 4;
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  const int ntiles = (n + 63) >> 6;
+  for (int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < ntiles;
+       tile += waves) {
+    const int xb = 64 * tile + 4 * c;
+    const bool full = 64 * tile + 64 <= n;   // wave-uniform
+    bool valid[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) valid[i] = xb + i < n;
+    // four consecutive cells of one column
+    auto ld4 = [&](const float *col) {
+      if (full) return *reinterpret_cast<const float4 *>(col + xb);
+      float4 v;
+      v.x = col[min(xb, n - 1)];
+      v.y = col[min(xb + 1, n - 1)];
+      v.z = col[min(xb + 2, n - 1)];
+      v.w = col[min(xb + 3, n - 1)];
+      return v;
+    };
+    float4 yraw[NQ][4];
+    if constexpr (HY) {
+#pragma unroll
+      for (int jt = 0; jt < NQ; ++jt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          yraw[jt][v] = ld4(Y + size_t(min(16 * jt + Mfma<float>::row(qd, v), q - 1)) * ldy);
+    }
+    double srcs[4];
+    if (sw != nullptr) {
+      const float4 ps = ld4(spsi);
+      srcs[0] = sdt * double(ps.x);
+      srcs[1] = sdt * double(ps.y);
+      srcs[2] = sdt * double(ps.z);
+      srcs[3] = sdt * double(ps.w);
+    }
+    acc_t acc[4][NQ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int jt = 0; jt < NQ; ++jt) acc[i][jt] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < nk; k0 += 4 * kUpdChunk) {
+      float b[kUpdChunk][4];
+#pragma unroll
+      for (int u = 0; u < kUpdChunk; ++u) {
+        const int k = k0 + 4 * u + qd;
+        const float4 xv = ld4(X + size_t(min(k, p - 1)) * ldx);
+        float v[4] = {xv.x, xv.y, xv.z, xv.w};
+        if (sw != nullptr) {
+          const float4 wv = ld4(sw + size_t(min(max(k - p, 0), n_mat - 1)) * n);
+          const float wa[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = k < p ? v[i] : float(double(wa[i]) * srcs[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[u][i] = (valid[i] && k < ne) ? v[i] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kUpdChunk; ++u) {
+        if (k0 + 4 * u < nk) {
+          const float *ga = Gs + (k0 + 4 * u + qd) * QS + c;
+#pragma unroll
+          for (int jt = 0; jt < NQ; ++jt) {
+            const float gv = ga[16 * jt];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i][jt] = Mfma<float>::op(gv, b[u][i], acc[i][jt]);
+          }
+        }
+      }
+    }
+    double dsum[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int jt = 0; jt < NQ; ++jt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * jt + Mfma<float>::row(qd, v);
+        if (j < q) {
+          float zv[4];
+          const float yr[4] = {HY ? yraw[jt][v].x : 0.0f, HY ? yraw[jt][v].y : 0.0f,
+                               HY ? yraw[jt][v].z : 0.0f, HY ? yraw[jt][v].w : 0.0f};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double yv = HY ? alpha * double(yr[i]) : 0.0;
+            zv[i] = float(double(acc[i][jt][v]) + yv);
+            if (dose != nullptr) dsum[i] += double(zv[i]) * dcs[j];
+          }
+          float *zc = Z + size_t(j) * ldz;
+          if (full) {
+            *reinterpret_cast<float4 *>(zc + xb) = make_float4(zv[0], zv[1], zv[2], zv[3]);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (valid[i]) zc[xb + i] = zv[i];
+          }
+        }
+      }
+    }
+    if (dose != nullptr) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        dsum[i] += __shfl_xor(dsum[i], 16);
+        dsum[i] += __shfl_xor(dsum[i], 32);
+        if (qd == 0 && valid[i]) dose[xb + i] += dscale * dsum[i];
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ void k_zero_cols(int n, T *X, int ld, int c0, int c1) {
   int x = blockIdx.x * kBlock + threadIdx.x;
@@ -1609,6 +1751,33 @@ static void update(int n, const T *X, int ldx, int p, const double *G, int ldg, 
     kern<<<blocks, 256, shm, st>>>(n, X, ldx, p, G, ldg, beta, Y, ldy, alpha, Z, ldz, q,    \
                                    dose, dc, dscale, sw, n_mat, spsi, sC, ldsc, sdt);       \
   } while (0)
+  auto a16 = [](const void *ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; };
+  if constexpr (sizeof(T) == 4) {
+    // 16-byte form where every column start is 16-byte aligned
+    const bool vec = ldx % 4 == 0 && ldz % 4 == 0 && a16(X) && a16(Z) &&
+                     (!HY || (ldy % 4 == 0 && a16(Y))) &&
+                     (sw == nullptr || (n % 4 == 0 && a16(sw) && a16(spsi)));
+    if (vec) {
+      const int vblocks = std::max(1, std::min(kUpdBlocks, (n + 255) / 256));
+#define DLRA_UPDATE_VEC(NQ)                                                                 \
+  do {                                                                                      \
+    auto kern = HY ? k_update_vec<NQ, true> : k_update_vec<NQ, false>;                      \
+    if (shm > 65536)                                                                        \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                        \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));     \
+    kern<<<vblocks, 256, shm, st>>>(n, X, ldx, p, G, ldg, beta, Y, ldy, alpha, Z, ldz, q,   \
+                                    dose, dc, dscale, sw, n_mat, spsi, sC, ldsc, sdt);      \
+  } while (0)
+      switch (nq) {
+        case 1: DLRA_UPDATE_VEC(1); break;
+        case 2: DLRA_UPDATE_VEC(2); break;
+        case 3: DLRA_UPDATE_VEC(3); break;
+        default: DLRA_UPDATE_VEC(4); break;
+      }
+#undef DLRA_UPDATE_VEC
+      return;
+    }
+  }
   switch (nq) {
     case 1: DLRA_UPDATE(1); break;
     case 2: DLRA_UPDATE(2); break;
