@@ -39,6 +39,15 @@ CASES = {
     # rank 20: two 16-column output tiles in the K-step (ragged 11^3 grid)
     "rank20_3d": lambda **k: configs.small_3d(n=11, N=7, r=20, n_steps=6, **k),
 }
+# rank edges of the K-step kernels (mixed precision: the z-march kernel takes
+# r <= 32 in FP32, one output tile up to 16, two above; r = 33 goes to the
+# general kernel)
+RANK_EDGES = {
+    "rank16_3d": lambda **k: configs.small_3d(n=10, N=7, r=16, n_steps=5, **k),
+    "rank17_3d": lambda **k: configs.small_3d(n=10, N=7, r=17, n_steps=5, **k),
+    "rank32_3d": lambda **k: configs.small_3d(n=10, N=7, r=32, n_steps=5, **k),
+    "rank33_3d": lambda **k: configs.small_3d(n=9, N=8, r=33, n_steps=4, **k),
+}
 
 
 def rel(a, b):
@@ -189,3 +198,17 @@ def test_batched_beams_match_single_runs(n_threads):
         d = s.dose()
         assert torch.equal(d, alone[b]), f"beam {b}"
         s.close()
+
+
+@pytest.mark.parametrize("name", list(RANK_EDGES))
+def test_mixed_precision_rank_edges(name):
+    dl = _gpu()
+    p = RANK_EDGES[name](precision="mixed", aug_tol=1e-4, floor_tol=1e-5)
+    say(f"mixed precision {name}")
+    s = dl.BeamSolver(p, 0)
+    s.raytrace()
+    s.run()
+    dose = s.dose().cpu().numpy()
+    want = ref.run_beam_dlra(p.with_options(precision="fp64"), p.beams[0])
+    assert rel(dose, want["dose"]) <= 1e-4
+    s.close()
