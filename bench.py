@@ -178,6 +178,7 @@ def bench_batch(problem, args):
     (each beam on its own stream, one host thread per beam).  Per beam: ray
     trace + all energy steps; inputs resident before timing; doses checked
     bitwise equal between the two runs."""
+    import numpy as np
     import torch
 
     import paper_2508_04484_amd as dl
@@ -221,6 +222,22 @@ def bench_batch(problem, args):
     t_batch = time.perf_counter() - t0
     print(f"batched: {B} beams, {t_batch:.2f} s", file=sys.stderr, flush=True)
     same = all(torch.equal(s.dose().cpu(), plain_dose[b]) for b, s in enumerate(solvers))
+    # plan objective over the beam weights and its exact gradient (the adjoint
+    # of the linear dose map) on the batched doses: target = the central 2 cm
+    # cube, prescription = mean target dose at unit weights, lam = 0.1
+    from workloads.plan import centre_target
+    doses = torch.stack([s.dose() for s in solvers]).contiguous()
+    target = torch.from_numpy(centre_target(problem.grid, 1.0)).cuda()
+    tmask = target.bool()
+    dhat = float(doses.sum(0)[tmask].mean()) if bool(tmask.any()) else 1.0
+    w = np.ones(B)
+    dl.binding.plan_objective(doses, w, target, dhat, 0.1)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_rep = 20
+    for _ in range(n_rep):
+        J, grad = dl.binding.plan_objective(doses, w, target, dhat, 0.1)
+    t_grad = (time.perf_counter() - t0) / n_rep
     for s in solvers:
         s.close()
     o = problem.options
@@ -248,6 +265,11 @@ def bench_batch(problem, args):
         "batched_over_plain": round(t_plain / t_batch, 4),
         "plain_s": round(t_plain, 3), "batched_s": round(t_batch, 3),
         "doses_bitwise_equal": bool(same),
+        "weight_gradient": {"ms": round(1000.0 * t_grad, 4),
+                            "over_batched_forward": t_grad / t_batch,
+                            "J": J, "dJ_dw": [round(float(x), 6) for x in grad],
+                            "note": "exact gradient over beam weights only; the voxel-density "
+                                    "adjoint (reverse sweep) is not built"},
     }
     print(json.dumps(out), flush=True)
 
