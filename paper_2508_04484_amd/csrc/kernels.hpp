@@ -95,9 +95,6 @@ void launch_source_k(int n, const T *U, int ld, int r, const double *St, int lds
                      const T *w, int n_mat, const T *psi, const double *Cg, int ldcg, double dt,
                      T *K, hipStream_t st);
 
-template <typename T>
-void launch_zero_cols(int n, T *X, int ld, int c0, int c1, hipStream_t st);
-
 // ----------------------------------------------------------------- small kernels (double)
 // C[z] = alpha op(A[z]) op(B[z]) + beta C[z], batched over blockIdx.z with
 // strides; op = transpose when ta/tb.
@@ -158,8 +155,6 @@ size_t plan_objective_work(int n, int nb);
 void launch_plan_objective(int n, int nb, const double *doses, const PlanWeights &pw,
                            const unsigned char *target, double dhat, double lam, double *work,
                            double *out, hipStream_t st);
-void launch_reduce_partials(const double *partial, int nblocks, int elems, double *out,
-                            hipStream_t st);
 
 // ----------------------------------------------------------------- ray tracer
 struct RayParams {

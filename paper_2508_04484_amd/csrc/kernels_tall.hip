@@ -24,29 +24,6 @@ __device__ __forceinline__ void cell_coords(const GridDev &g, int x, int c[3]) {
   c[2] = t / g.ny;
 }
 
-// second-order one-sided difference of v(x) = s(x) W(x, col) along d
-// (zero ghost cells); kind 0: backward (3v_i - 4v_{i-1} + v_{i-2}),
-// kind 1: forward (-3v_i + 4v_{i+1} - v_{i+2}), times 1/(2 Delta_d).  The
-// neighbour loads use clamped indices and are unconditional (a load inside
-// a divergent branch would be followed by a full wait); terms outside the
-// grid are zeroed by a select.
-template <typename T>
-__device__ __forceinline__ T stencil_diff(const GridDev &g, const T *__restrict__ s,
-                                          const T *__restrict__ col, int x, const int c[3],
-                                          int d, int kind) {
-  const int size[3] = {g.nx, g.ny, g.nz};
-  const int stride = d == 0 ? 1 : (d == 1 ? g.nx : g.nx * g.ny);
-  const bool ok1 = kind == 0 ? c[d] >= 1 : c[d] + 1 < size[d];
-  const bool ok2 = kind == 0 ? c[d] >= 2 : c[d] + 2 < size[d];
-  const int sg = kind == 0 ? -stride : stride;
-  const int i1 = ok1 ? x + sg : x, i2 = ok2 ? x + 2 * sg : x;
-  const T v0 = s[x] * col[x];
-  const T a1 = s[i1] * col[i1], a2 = s[i2] * col[i2];
-  const T v1 = ok1 ? a1 : T(0), v2 = ok2 ? a2 : T(0);
-  const T diff = T(3) * v0 - T(4) * v1 + v2;
-  return (kind == 0 ? diff : -diff) * T(g.inv2h[d]);
-}
-
 // ------------------------------------------------------------------ 1/S
 template <typename T>
 __global__ void k_inverse_stop(GridDev g, const T *__restrict__ w, int n_mat,
@@ -87,7 +64,6 @@ struct WMatS {
 };
 
 // ------------------------------------------------------------------ K-step stage
-constexpr int kTC = 32;   // cells per tile of the reductions
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -355,7 +331,7 @@ __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, int vo,
 template <typename T, int NJ, int DIM, int JS>
 __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     GridDev g, const T *__restrict__ s, const T *__restrict__ W, const T *__restrict__ K0,
-    T *__restrict__ out, int ld, int r, const T *__restrict__ Bp, double coef, int nby, int nzc,
+    T *__restrict__ out, int ld, int r, const T *__restrict__ Bp, double coef, int nzc,
     int zchunk) {
   constexpr int RB = 16 * NJ, KS = 4 * NJ, DPE = int(sizeof(T)) / 4, TB = int(sizeof(T));
   constexpr int BY = kBrickBY, RW = kBrickRW, PC = kBrickPC, HC = kBrickHC, HS = kBrickHS;
@@ -628,12 +604,14 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
       store_part(kq * NOUT * 4 / KSW, (kq + 1) * NOUT * 4 / KSW);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int d = 0; d < DIM; ++d)
+      for (int d = 0; d < DIM; ++d) {
+        // the output tiles alternate, so consecutive MFMAs never depend on
+        // each other (same accumulation order per tile)
 #pragma unroll
-        for (int jt = 0; jt < NJ; ++jt) {
-          acc[jt] = Mfma<T>::op(bq[d][kq][jt][0], db[d], acc[jt]);
-          acc[jt] = Mfma<T>::op(bq[d][kq][jt][1], df[d], acc[jt]);
-        }
+        for (int jt = 0; jt < NJ; ++jt) acc[jt] = Mfma<T>::op(bq[d][kq][jt][0], db[d], acc[jt]);
+#pragma unroll
+        for (int jt = 0; jt < NJ; ++jt) acc[jt] = Mfma<T>::op(bq[d][kq][jt][1], df[d], acc[jt]);
+      }
       __builtin_amdgcn_sched_barrier(0);
       if (kq + 1 < KSW) diffs();
     }
@@ -677,21 +655,18 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
   wait_vm<0>();   // no load into LDS outlives the block
 }
 
-// Tall-skinny contractions on the matrix cores.  Per block a chunk of cells,
-// processed in tiles of 64 cells: the tile of the left factor X (64 x p) and
-// of the right factor (64 x q: differences of s o X in stencil mode, Y times
-// the weights otherwise) are staged in LDS with coalesced loads (consecutive
-// threads read consecutive cells of one column), then each wave (one 16-column
-// tile b of the right factor) runs the 16x16x4 MFMAs over the 16 groups of 4
-// cells for all 16-row tiles a of the left factor.
-//   stencil mode (blockIdx.y = dk):  P_dk(a, b) = sum_x X(x, a) d_dk(s o X)(x, b)
-//   gram mode:                       P(a, b) = sum_x X(x, a) wt(x) Y(x, b)
-// Partial sums of block (bx, by) go to partial[(bx * gridDim.y + by) * pq].
+// General weighted Gram P(a, b) = sum_x X(x, a) wt(x) Y(x, b) on the matrix
+// cores (any p, q <= 112; k_gram_mfma covers the common shapes).  Per block a
+// chunk of cells in tiles of 64: the tiles of X (64 x p) and of Y (64 x q)
+// are staged in LDS with coalesced loads (consecutive threads read
+// consecutive cells of one column), then each wave (one 16-column tile b of
+// Y) runs the 16x16x4 MFMAs over the 16 groups of 4 cells for all 16-row
+// tiles a of X.  Partial sums of block bx go to partial[bx * pq].
 constexpr int kCT = 64;   // cells per staged tile
 
-template <typename T, typename Tc, int NA, bool STENCIL, typename YF, typename WF>
-__global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__restrict__ s,
-                                                      const T *__restrict__ X, int ldx, int p,
+template <typename T, typename Tc, int NA, typename YF, typename WF>
+__global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__restrict__ X,
+                                                      int ldx, int p,
                                                       YF yf, int q, WF wf, int chunk,
                                                       double *__restrict__ partial) {
   using acc_t = typename Mfma<Tc>::acc_t;
@@ -704,7 +679,6 @@ __global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__res
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int w = tid >> 6, lane = tid & 63;
   const int c = lane & 15, qq = lane >> 4;
-  const int dk = blockIdx.y;
   acc_t acc[NA];
 #pragma unroll
   for (int at = 0; at < NA; ++at) acc[at] = acc_t{0, 0, 0, 0};
@@ -712,14 +686,13 @@ __global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__res
   const int x_end = min(g.n, x_begin + chunk);
   for (int x0 = x_begin; x0 < x_end; x0 += kCT) {
     __syncthreads();
-    // staging: clamped, unconditional loads (see stencil_diff), zeroed by a select
+    // staging: clamped, unconditional loads, zeroed by a select
 #pragma unroll 4
     for (int e = tid; e < kCT * 16 * NA; e += nthr) {
       const int cc_ = e % kCT, a = e / kCT;
       const int x = x0 + cc_;
       const int xc = min(x, x_end - 1);
-      Tc v = Tc(X[size_t(min(a, p - 1)) * ldx + xc]);
-      if constexpr (!STENCIL) v *= Tc(wf(xc));
+      const Tc v = Tc(X[size_t(min(a, p - 1)) * ldx + xc]) * Tc(wf(xc));
       Xs[cc_ * pa + a] = (x < x_end && a < p) ? v : Tc(0);
     }
 #pragma unroll 4
@@ -727,14 +700,7 @@ __global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__res
       const int cc_ = e % kCT, b = e / kCT;
       const int x = x0 + cc_;
       const int xc = min(x, x_end - 1), bc = min(b, q - 1);
-      Tc v;
-      if constexpr (STENCIL) {
-        int cd[3];
-        cell_coords(g, xc, cd);
-        v = Tc(stencil_diff(g, s, X + size_t(bc) * ldx, xc, cd, dk >> 1, dk & 1));
-      } else {
-        v = Tc(yf(xc, bc));
-      }
+      const Tc v = Tc(yf(xc, bc));
       Ys[cc_ * pb + b] = (x < x_end && b < q) ? v : Tc(0);
     }
     __syncthreads();
@@ -748,7 +714,7 @@ __global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__res
     }
   }
   const size_t pq = size_t(p) * q;
-  double *out = partial + (size_t(blockIdx.x) * gridDim.y + blockIdx.y) * pq;
+  double *out = partial + size_t(blockIdx.x) * pq;
   const int b = w * 16 + c;
 #pragma unroll
   for (int at = 0; at < NA; ++at) {
@@ -1437,13 +1403,6 @@ __global__ __launch_bounds__(256) void k_update_vec(
   }
 }
 
-template <typename T>
-__global__ void k_zero_cols(int n, T *X, int ld, int c0, int c1) {
-  int x = blockIdx.x * kBlock + threadIdx.x;
-  if (x >= n) return;
-  for (int c = c0; c < c1; ++c) X[size_t(c) * ld + x] = T(0);
-}
-
 
 }  // namespace
 
@@ -1523,7 +1482,7 @@ static void kstage_brick_launch(const GridDev &g, const T *s, const T *W, const 
   int nzc = std::max(1, std::min(g.nz, (cap + ncol - 1) / ncol));
   const int zchunk = (g.nz + nzc - 1) / nzc;
   nzc = (g.nz + zchunk - 1) / zchunk;
-  kern<<<ncol * nzc, NT, shm, st>>>(g, s, W, K0, out, ld, r, Bp, coef, nby, nzc, zchunk);
+  kern<<<ncol * nzc, NT, shm, st>>>(g, s, W, K0, out, ld, r, Bp, coef, nzc, zchunk);
 }
 
 template <typename T>
@@ -1560,28 +1519,27 @@ void launch_kstep_stage(const GridDev &g, const T *s, const T *W, const T *K0, T
   }
 }
 
-template <typename T, typename Tc, bool STENCIL, typename YF, typename WF>
-static void contract(const GridDev &g, const T *s, const T *X, int ldx, int p, YF yf, int q,
-                     WF wf, int ny, double *partial, size_t partial_elems, hipStream_t st,
-                     int &nb_out) {
+template <typename T, typename Tc, typename YF, typename WF>
+static void contract(const GridDev &g, const T *X, int ldx, int p, YF yf, int q, WF wf,
+                     double *partial, size_t partial_elems, hipStream_t st, int &nb_out) {
   const size_t pq = size_t(p) * q;
   const int na = (p + 15) / 16, nbw = (q + 15) / 16;
-  int nb = (kContractWaves + ny * nbw - 1) / (ny * nbw);
+  int nb = (kContractWaves + nbw - 1) / nbw;
   nb = std::max(1, std::min({nb, kMaxPartialBlocks, (g.n + kCT - 1) / kCT}));
-  // partial sums of nb * ny blocks plus the reduced ny blocks behind them
-  while (nb > 1 && size_t(nb + 1) * ny * pq > partial_elems) nb /= 2;
+  // partial sums of nb blocks plus their sum behind them
+  while (nb > 1 && size_t(nb + 1) * pq > partial_elems) nb /= 2;
   int chunk = (g.n + nb - 1) / nb;
   chunk = (chunk + 3) / 4 * 4;
   nb = (g.n + chunk - 1) / chunk;
-  dim3 grid(nb, ny), block(64 * nbw);
+  dim3 grid(nb), block(64 * nbw);
   const size_t shm = size_t(kCT) * (16 * na + 1 + 16 * nbw + 1) * sizeof(Tc);
 #define DLRA_CONTRACT(NA)                                                                  \
   do {                                                                                     \
-    auto kern = k_contract_mfma<T, Tc, NA, STENCIL, YF, WF>;                               \
+    auto kern = k_contract_mfma<T, Tc, NA, YF, WF>;                                        \
     if (shm > 65536)                                                                       \
       (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                       \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));    \
-    kern<<<grid, block, shm, st>>>(g, s, X, ldx, p, yf, q, wf, chunk, partial);            \
+    kern<<<grid, block, shm, st>>>(g, X, ldx, p, yf, q, wf, chunk, partial);               \
   } while (0)
   switch (na) {
     case 1: DLRA_CONTRACT(1); break;
@@ -1689,11 +1647,11 @@ void launch_gram(int n, const T *X, int ldx, int p, const T *Y, int ldy, int q, 
       gram<T, Acc, true>(n, X, ldx, p, YMat<T>{Y, ldy}, q, WOne<T>{}, partial, partial_elems,
                          st, nb);
   } else if (wmat != nullptr) {
-    contract<T, Acc, false>(g, s, X, ldx, p, YMat<T>{Y, ldy}, q, WMatS<T>{wmat, s}, 1, partial,
-                            partial_elems, st, nb);
+    contract<T, Acc>(g, X, ldx, p, YMat<T>{Y, ldy}, q, WMatS<T>{wmat, s}, partial,
+                     partial_elems, st, nb);
   } else {
-    contract<T, Acc, false>(g, s, X, ldx, p, YMat<T>{Y, ldy}, q, WOne<T>{}, 1, partial,
-                            partial_elems, st, nb);
+    contract<T, Acc>(g, X, ldx, p, YMat<T>{Y, ldy}, q, WOne<T>{}, partial, partial_elems,
+                     st, nb);
   }
   const size_t per = size_t(p) * q;
   double *red = partial + size_t(nb) * per;
@@ -1712,8 +1670,8 @@ void launch_xt_source(int n, const T *X, int ld, int p, const T *w, int n_mat, c
   } else {
     GridDev g{};
     g.n = n;
-    contract<T, Acc, false>(g, nullptr, X, ld, p, YSrc<T>{w, psi, n}, n_mat, WOne<T>{}, 1,
-                            partial, partial_elems, st, nb);
+    contract<T, Acc>(g, X, ld, p, YSrc<T>{w, psi, n}, n_mat, WOne<T>{}, partial, partial_elems,
+                     st, nb);
   }
   const size_t per = size_t(p) * n_mat;
   double *red = partial + size_t(nb) * per;
@@ -1803,12 +1761,6 @@ void launch_source_k(int n, const T *U, int ld, int r, const double *St, int lds
             n_mat, psi, Cg, ldcg, dt, st);
 }
 
-template <typename T>
-void launch_zero_cols(int n, T *X, int ld, int c0, int c1, hipStream_t st) {
-  if (c1 <= c0) return;
-  k_zero_cols<T><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(n, X, ld, c0, c1);
-}
-
 // ------------------------------------------------------------------ plan objective
 // D(x) = sum_b w_b D_b(x); J = sum_{x in T} (D - dhat)^2 + lam sum_{x not in T} D^2;
 // dJ/dw_b = sum_x g(x) D_b(x) with g = dJ/dD (2 (D - dhat) on T, 2 lam D off it).
@@ -1872,11 +1824,6 @@ void launch_plan_objective(int n, int nb, const double *doses, const PlanWeights
   reduce_partials(partial, nblk, nb + 1, out, st, scratch, size_t(64) * (nb + 1));
 }
 
-void launch_reduce_partials(const double *partial, int nblocks, int elems, double *out,
-                            hipStream_t st) {
-  reduce_partials(partial, nblocks, elems, out, st);
-}
-
 #define DLRA_INSTANTIATE(T, Acc)                                                              \
   template void launch_inverse_stop<T>(const GridDev &, const T *, int, const double *, T *,  \
                                        Ctl *, hipStream_t);                                   \
@@ -1897,8 +1844,7 @@ void launch_reduce_partials(const double *partial, int nblocks, int elems, doubl
                                  const double *, double, hipStream_t);                        \
   template void launch_source_k<T>(int, const T *, int, int, const double *, int, const T *,  \
                                    int, const T *, const double *, int, double, T *,          \
-                                   hipStream_t);                                              \
-  template void launch_zero_cols<T>(int, T *, int, int, int, hipStream_t);
+                                   hipStream_t);
 
 DLRA_INSTANTIATE(double, double)
 DLRA_INSTANTIATE(float, float)
