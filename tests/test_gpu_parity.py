@@ -94,7 +94,7 @@ def test_single_step_from_injected_state(name):
     k = 3
     s = dl.BeamSolver(p, 0)
     s.raytrace()
-    ps, Du = s.uncollided()
+    ps, Du = raytrace.Tracer(p, p.beams[0]).trace()   # the reference's own tables
     res = ref.run_beam_dlra(p, p.beams[0], n_steps=k, psibar=ps, Du=Du)
     st = res["state"]
     s.set_state(st.U, st.S, st.V, k)
@@ -212,3 +212,48 @@ def test_mixed_precision_rank_edges(name):
     want = ref.run_beam_dlra(p.with_options(precision="fp64"), p.beams[0])
     assert rel(dose, want["dose"]) <= 1e-4
     s.close()
+
+
+def _fro_diff(U1, S1, V1, U2, S2, V2):
+    """||U1 S1 V1^T - U2 S2 V2^T||_F and ||U2 S2 V2^T||_F from r x r traces."""
+    a2 = np.trace((U1.T @ U1) @ S1 @ (V1.T @ V1) @ S1.T)
+    b2 = np.trace((U2.T @ U2) @ S2 @ (V2.T @ V2) @ S2.T)
+    ab = np.trace((U1.T @ U2) @ S2 @ (V2.T @ V1) @ S1.T)
+    return float(np.sqrt(max(a2 + b2 - 2.0 * ab, 0.0))), float(np.sqrt(b2))
+
+
+def test_full_size_bench_configuration_one_step():
+    # the benchmark's workload (128^3 cells, P_15, rank 30, mixed precision,
+    # same launch configuration): one step from a seeded random rank-30 state
+    # late in the energy range, where the beam has left the phantom and the
+    # uncollided source vanishes (the reference step takes a zero source; a
+    # non-negligible source on the library side would show as a mismatch).
+    # Compared: the low-rank product (Frobenius norm from r x r traces), 64
+    # sampled rows of it, and the collided dose of the step.
+    dl = _gpu()
+    from workloads.states import random_low_rank_state
+    p = configs.c3()
+    b = p.beams[0]
+    k = p.options.n_steps - 5
+    say(f"full-size c3 step {k}")
+    U0, S0, V0 = random_low_rank_state(p.grid.n, (p.options.pn_degree + 1) ** 2, p.options.r)
+    s = dl.BeamSolver(p, 0)
+    s.raytrace()
+    s.set_state(U0, S0, V0, k)
+    s.step(sync=True)
+    U, S, V, kk = s.state()
+    dose_c = s.dose(flags=2).cpu().numpy()
+    s.close()
+    assert kk == k + 1
+    p64 = p.with_options(precision="fp64")
+    c = coeffs.step_coeffs(p64, b, k)
+    st = dlra.State(U0, S0, V0, np.zeros(p.grid.n), k)
+    nxt = dlra.step(st, c, ref.streaming_split(p64), p64, np.zeros(p.grid.n))
+    err, nrm = _fro_diff(U, S, V, nxt.U, nxt.S, nxt.V)
+    say(f"full-size step: rel Frobenius error {err / nrm:.3e}")
+    assert err <= 1e-4 * nrm
+    rows = np.random.default_rng(11).choice(p.grid.n, 64, replace=False)
+    a = U[rows] @ S @ V.T
+    want = nxt.U[rows] @ nxt.S @ nxt.V.T
+    assert rel(a, want) <= 1e-4
+    assert rel(dose_c, nxt.dose_c) <= 1e-4
