@@ -447,17 +447,18 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     }
     soff[i] = ((gy * nx + gx) * DPE + half) * 4;
   }
-  auto slot = [](int z) { return (z + 2 * NS) % NS; };
+  static_assert(NB == AH, "one y-halo / K0 buffer per step in flight");
+  auto slot = [](int z) { return (z % NS + NS) % NS; };   // prologue only
   // W of ring plane zp, W y halo of plane zh, K0 tile of plane zh, s of both
   // loads lo .. hi-1 of the NLOADS of one step (W plane, W y halo, K0 tile,
   // s), so that a step's loads can be spread over the column blocks
-  auto issue_part = [&](int lo, int hi, int zp, int zh) {
+  auto issue_part = [&](int lo, int hi, int zp, int zh, int hbuf, int sl) {
     const int pb = clampz(zp) * plane * TB, hb = clampz(zh) * plane * TB;
-    unsigned char *dp = reinterpret_cast<unsigned char *>(ringW + slot(zp) * RB * PC);
-    unsigned char *dh = reinterpret_cast<unsigned char *>(haloW + (zh % NB) * RB * HS);
-    unsigned char *dk = reinterpret_cast<unsigned char *>(K0t + (zh % NB) * RB * KST);
-    unsigned char *dsp = reinterpret_cast<unsigned char *>(ringS + slot(zp) * SP);
-    unsigned char *dsh = reinterpret_cast<unsigned char *>(haloS + (zh % NB) * HC);
+    unsigned char *dp = reinterpret_cast<unsigned char *>(ringW + sl * RB * PC);
+    unsigned char *dh = reinterpret_cast<unsigned char *>(haloW + hbuf * RB * HS);
+    unsigned char *dk = reinterpret_cast<unsigned char *>(K0t + hbuf * RB * KST);
+    unsigned char *dsp = reinterpret_cast<unsigned char *>(ringS + sl * SP);
+    unsigned char *dsh = reinterpret_cast<unsigned char *>(haloS + hbuf * HC);
     auto in = [&](int i) { return i >= lo && i < hi; };
 #pragma unroll
     for (int i = 0; i < NPI; ++i)
@@ -484,7 +485,7 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
       else dma_dword(rS, pad, soff[i], 0);
     }
   };
-  auto issue = [&](int zp, int zh) { issue_part(0, NLOADS, zp, zh); };
+  auto issue = [&](int zp, int zh) { issue_part(0, NLOADS, zp, zh, zh % NB, slot(zp)); };
   // prologue: ring planes z0-2 .. z0+AH, y halos / K0 tiles of z0 .. z0+AH-2;
   // step z loads ring plane z+1+AH and the y halo / K0 tile / s of z+AH-1,
   // spread over its column blocks
@@ -523,8 +524,12 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
   auto out_col = [&](int jt, int v) {
     return 16 * (KSPLIT ? jh : jt) + Mfma<T>::row(q, v);
   };
+  // ring slots of the planes z - 2 .. z + 2 and z + 1 + AH, and the y-halo /
+  // K0 buffer of step z, all stepped below (no division)
+  int hb = z0 % NB, sc = slot(z0), sdma = slot(z0 + 1 + AH);
+  int zsl[4] = {slot(z0 - 2), slot(z0 - 1), slot(z0 + 1), slot(z0 + 2)};
   for (int z = z0; z < z1; ++z) {
-    const int sc = slot(z), hb = z % NB;
+    const int hbl = hb == 0 ? NB - 1 : hb - 1;   // buffer of step z + AH - 1 (NB == AH)
     const T *Wc = ringW + sc * RB * PC, *Sc = ringS + sc * SP;
     const T *wp[DIM][4];
     T sv[DIM][4];
@@ -532,17 +537,20 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     for (int t = 0; t < 4; ++t) {
       const int o = t < 2 ? t - 2 : t - 1;
       wp[0][t] = Wc + base + o + qoff;
-      sv[0][t] = mx[t] ? Sc[base + o] : T(0);
+      const T sx = Sc[base + o];   // loads unconditional, masked by selects
+      sv[0][t] = mx[t] ? sx : T(0);
       const int yr = row + o;
       const bool inb = yr >= 0 && yr < BY;
       const int hr = yr < 0 ? yr + 2 : yr - BY + 2;
       wp[1][t] = (inb ? Wc + yr * RW + c + 2 : haloW + hb * RB * HS + hr * 16 + c) + qoff;
-      const T syv = inb ? Sc[yr * RW + c + 2] : haloS[hb * HC + hr * 16 + c];
-      sv[1][t] = my[t] ? syv : T(0);
+      const T sy_in = Sc[min(max(yr, 0), BY - 1) * RW + c + 2];
+      const T sy_h = haloS[hb * HC + min(max(hr, 0), 3) * 16 + c];
+      sv[1][t] = my[t] ? (inb ? sy_in : sy_h) : T(0);
       if constexpr (DIM == 3) {
-        wp[2][t] = ringW + slot(z + o) * RB * PC + base + qoff;
+        wp[2][t] = ringW + zsl[t] * RB * PC + base + qoff;
         const bool mz = z + o >= 0 && z + o < nz;
-        sv[2][t] = mz ? ringS[slot(z + o) * SP + base] : T(0);
+        const T sz = ringS[zsl[t] * SP + base];
+        sv[2][t] = mz ? sz : T(0);
       }
     }
     // s-weights of the one-sided differences (ih folded in)
@@ -600,7 +608,8 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
 #pragma unroll
     for (int kq = 0; kq < KSW; ++kq) {
       if (kq + 1 < KSW) read_sten(kq + 1);
-      issue_part(kq * NLOADS / KSW, (kq + 1) * NLOADS / KSW, z + 1 + AH, z + AH - 1);
+      issue_part(kq * NLOADS / KSW, (kq + 1) * NLOADS / KSW, z + 1 + AH, z + AH - 1, hbl,
+                 sdma);
       store_part(kq * NOUT * 4 / KSW, (kq + 1) * NOUT * 4 / KSW);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -642,6 +651,13 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     // buffers no later step reads)
     wait_vm<(AH - 2) * NLOADS>();
     block_barrier();
+    hb = hb + 1 == NB ? 0 : hb + 1;
+    zsl[0] = zsl[1];
+    zsl[1] = sc;
+    sc = zsl[2];
+    zsl[2] = zsl[3];
+    zsl[3] = zsl[3] + 1 == NS ? 0 : zsl[3] + 1;
+    sdma = sdma + 1 == NS ? 0 : sdma + 1;
   }
 #pragma unroll
   for (int jt = 0; jt < NOUT; ++jt) {
