@@ -113,14 +113,118 @@ __device__ void blk_gemm_tn(int M, int N, int K, double alpha, const double *A, 
   __syncthreads();
 }
 
+// Pair (i, j) with i < j that group k of a round-robin round plays, for qe
+// (even) columns: one column stays put, the others rotate.
+__device__ inline void rr_pair(int qe, int round, int k, int &i, int &j) {
+  if (k == 0) {
+    i = round;
+    j = qe - 1;
+  } else {
+    i = (round + k) % (qe - 1);
+    j = (round - k + qe - 1) % (qe - 1);
+  }
+  if (i > j) {
+    const int t = i;
+    i = j;
+    j = t;
+  }
+}
+
+// x of the lane that the DPP row permutation CTRL names, both 32-bit halves
+template <int CTRL>
+__device__ inline double dpp_mov(double x) {
+  const unsigned long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(
+      (long long)((unsigned long long)unsigned(hi) << 32 | (unsigned long long)unsigned(lo)));
+}
+
+// Sum over each aligned group of 16 lanes (all lanes active): four pairwise
+// exchanges (swap neighbours, swap pairs of a quad, mirror each half row,
+// mirror the row).  Every step pairs lanes symmetrically, so all 16 lanes end
+// with the same bits.
+__device__ inline double row16_sum(double x) {
+  x += dpp_mov<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += dpp_mov<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += dpp_mov<0x141>(x);   // row_half_mirror
+  x += dpp_mov<0x140>(x);   // row_mirror
+  return x;
+}
+
+// Rounds of the one-sided Jacobi below for p, q <= 64 when the workgroup has
+// 16 lanes for every pair of a round: the lanes of a pair hold its two
+// columns of A and of V in registers (rows lane, lane + 16, ...), so each
+// round issues all its LDS reads at once and sums the three inner products
+// across the 16 lanes of a DPP row.  Same ordering, rotation rule and
+// stopping test as the general rounds.
+__device__ void jacobi_rounds_reg(double *A, int lda, int p, int q, double *V, int ldv,
+                                  int *flag, double tiny) {
+  constexpr int LP = 16, RPL = 4;   // lanes per pair, rows per lane
+  const int tid = threadIdx.x;
+  const int qe = q + (q & 1);
+  const int lane = tid % LP, k = tid / LP;
+  const bool active = k < qe / 2;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int round = 0; round < qe - 1; ++round) {
+      int i = 0, j = 0;
+      if (active) rr_pair(qe, round, k, i, j);
+      const bool valid = active && j < q;
+      double a[RPL], b[RPL], va[RPL], vb[RPL];
+      double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        const int t = lane + LP * u;
+        const bool inA = valid && t < p, inV = valid && t < q;
+        a[u] = inA ? A[t + size_t(i) * lda] : 0.0;
+        b[u] = inA ? A[t + size_t(j) * lda] : 0.0;
+        va[u] = inV ? V[t + size_t(i) * ldv] : 0.0;
+        vb[u] = inV ? V[t + size_t(j) * ldv] : 0.0;
+        al += a[u] * a[u];
+        be += b[u] * b[u];
+        ga += a[u] * b[u];
+      }
+      al = row16_sum(al);
+      be = row16_sum(be);
+      ga = row16_sum(ga);
+      if (valid && al > 0.0 && be > 0.0 && fabs(ga) > 1e-15 * sqrt(al * be) &&
+          fabs(ga) > tiny) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          const int r = lane + LP * u;
+          if (r < p) {
+            A[r + size_t(i) * lda] = c * a[u] - s * b[u];
+            A[r + size_t(j) * lda] = s * a[u] + c * b[u];
+          }
+          if (r < q) {
+            V[r + size_t(i) * ldv] = c * va[u] - s * vb[u];
+            V[r + size_t(j) * ldv] = s * va[u] + c * vb[u];
+          }
+        }
+        if (lane == 0) *flag = 1;
+      }
+      __syncthreads();
+    }
+    const int f = *flag;
+    __syncthreads();
+    if (!f) break;
+  }
+}
+
 // One-sided Jacobi: orthogonalise the q columns (length p) of A, accumulating
 // the rotations in V (q x q, initialised here).  Parallel round-robin
-// ordering, 8 lanes per column pair.  A pair is rotated when its inner
+// ordering; 8 lanes per column pair, or the register rounds above when the
+// matrix is at most 64 x 64.  A pair is rotated when its inner
 // product is above 1e-15 of the columns' norms and above 1e-30 ||A||_F^2:
 // pairs of columns that are both negligible against the matrix (singular
 // values below ~1e-15 of the largest) carry only rounding noise, and
 // rotating them would keep the sweeps from terminating.
-__device__ void blk_jacobi(double *A, int lda, int p, int q, double *V, int ldv, int *flag,
+__device__ __attribute__((always_inline)) void blk_jacobi(double *A, int lda, int p, int q, double *V, int ldv, int *flag,
                            double *red) {
   const int tid = threadIdx.x;
   for (int e = tid; e < q * q; e += blockDim.x) V[(e % q) + size_t(e / q) * ldv] = (e % q == e / q) ? 1.0 : 0.0;
@@ -133,6 +237,10 @@ __device__ void blk_jacobi(double *A, int lda, int p, int q, double *V, int ldv,
   __syncthreads();
   const int qe = q + (q & 1);
   if (qe < 2) return;
+  if (p <= 64 && q <= 64 && (qe / 2) * 16 <= int(blockDim.x) && blockDim.x % 64 == 0) {
+    jacobi_rounds_reg(A, lda, p, q, V, ldv, flag, tiny);
+    return;
+  }
   const int lane8 = tid & 7;
   const int grp = tid >> 3;
   const int ngrp = blockDim.x >> 3;
@@ -142,18 +250,7 @@ __device__ void blk_jacobi(double *A, int lda, int p, int q, double *V, int ldv,
     for (int round = 0; round < qe - 1; ++round) {
       for (int k = grp; k < qe / 2; k += ngrp) {
         int i, j;
-        if (k == 0) {
-          i = round;
-          j = qe - 1;
-        } else {
-          i = (round + k) % (qe - 1);
-          j = (round - k + qe - 1) % (qe - 1);
-        }
-        if (i > j) {
-          int t = i;
-          i = j;
-          j = t;
-        }
+        rr_pair(qe, round, k, i, j);
         bool valid = j < q;
         double al = 0.0, be = 0.0, ga = 0.0;
         if (valid) {
@@ -612,7 +709,9 @@ __global__ __launch_bounds__(kWG) void k_truncate(const double *__restrict__ Sh,
     A[i + j * p] = cols ? Sh[i + j * P] : Sh[j + i * P];
   }
   __syncthreads();
-  blk_jacobi(A, p, p, q, V, q, &flag, red);
+  // the branch lets the LDS case address the matrices as LDS
+  if (in_lds) blk_jacobi(dyn, p, p, q, dyn + P * P, q, &flag, red);
+  else blk_jacobi(work, p, p, q, work + P * P, q, &flag, red);
   __syncthreads();
   blk_colnorms_sorted(A, p, p, q, sig, order);
   // rank
