@@ -751,7 +751,9 @@ __global__ __launch_bounds__(512) void k_contract_mfma(GridDev g, const T *__res
 // each tile cell is staged once per tile, and only the y or z neighbours of
 // W = X are loaded per element (clamped, unconditional, masked by a select).
 // Four waves; wave w owns the 16-column tiles w, w + 4 of the right factor
-// for all 16-row tiles of the left one.  Partial sums of block bx go to
+// for all 16-row tiles of the left one.  With one or two such tiles the 4 / NA
+// waves of a tile split the cells of each staged tile instead, and their sums
+// are added in wave order at the end.  Partial sums of block bx go to
 // partial[(bx * 2 dim + dk) * p * p].
 template <typename T, typename Tc, int NA>
 __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__restrict__ s,
@@ -763,6 +765,9 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
   constexpr int CH = CT + 4;                      // with a 2-cell halo on each side
   constexpr int PA = 16 * NA + 1;                 // row length (odd: no bank conflicts)
   constexpr int NBT = (NA + 3) / 4;               // right-factor tiles per wave
+  constexpr int KSP = NA <= 2 ? 4 / NA : 1;       // waves splitting the cells of a tile
+  static_assert(KSP == 1 || (CH * PA + 5 * CT) * sizeof(T) % (4 * sizeof(Tc)) == 0,
+                "wave-sum exchange aligned");
   constexpr int PER = CT * 16 * NA / 256;         // staged elements per thread
   constexpr int PERH = (CH * 16 * NA + 255) / 256;
   static_assert((CT * 16 * NA) % 256 == 0, "whole staging rounds");
@@ -903,13 +908,13 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
     fetch(x0 + CT);   // past the chunk end: clamped, unused
     __syncthreads();
 #pragma unroll 2
-    for (int k4 = 0; k4 < CT / 4; ++k4) {
+    for (int k4 = KSP > 1 ? w / NA : 0; k4 < CT / 4; k4 += KSP) {
       const int cell = 4 * k4 + qq;
 #pragma unroll
       for (int bt = 0; bt < NBT; ++bt) {
         // a wave without a tile of its own repeats the last one (no branch
         // around the MFMAs; its sums are not written out)
-        const int btile = min(w + 4 * bt, NA - 1);
+        const int btile = KSP > 1 ? w % NA : min(w + 4 * bt, NA - 1);
         const Tc yb = Yb[cell * PA + btile * 16 + c], yf = Yf[cell * PA + btile * 16 + c];
 #pragma unroll
         for (int at = 0; at < NA; ++at) {
@@ -920,12 +925,42 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
       }
     }
   }
+  if constexpr (KSP > 1) {
+    // sums of the waves w >= NA through LDS (the staging buffers are free
+    // once every wave is past its last MFMA), added in wave order
+    acc_t *xb = reinterpret_cast<acc_t *>(Yb);
+    __syncthreads();
+    if (w >= NA) {
+#pragma unroll
+      for (int at = 0; at < NA; ++at) {
+        xb[((w - NA) * NA + at) * 2 * 64 + lane] = ab[0][at];
+        xb[(((w - NA) * NA + at) * 2 + 1) * 64 + lane] = af[0][at];
+      }
+    }
+    __syncthreads();
+    if (w < NA) {
+      for (int kp = 1; kp < KSP; ++kp) {
+        const int o = kp * NA + w - NA;
+#pragma unroll
+        for (int at = 0; at < NA; ++at) {
+          const acc_t vb = xb[(o * NA + at) * 2 * 64 + lane];
+          const acc_t vf = xb[((o * NA + at) * 2 + 1) * 64 + lane];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            ab[0][at][v] += vb[v];
+            af[0][at][v] += vf[v];
+          }
+        }
+      }
+    }
+  }
   const size_t pq = size_t(p) * p;
   double *outb = partial + (size_t(bx) * 2 * g.dim + 2 * d) * pq;
   double *outf = outb + pq;
 #pragma unroll
   for (int bt = 0; bt < NBT; ++bt) {
-    const int b = (w + 4 * bt) * 16 + c;   // >= p for a repeated tile
+    // >= p for a repeated tile or a wave whose sums went to another
+    const int b = (KSP > 1 && w >= NA) ? p : (w + 4 * bt) * 16 + c;
 #pragma unroll
     for (int at = 0; at < NA; ++at) {
 #pragma unroll
@@ -944,6 +979,10 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
 template <typename T, typename Tc, int NA>
 constexpr size_t stencil_proj_lds() {
   constexpr int CT = sizeof(Tc) == 8 ? 32 : 64;
+  // the wave-sum exchange of NA <= 2 reuses the three CT x (16 NA + 1) buffers
+  static_assert(NA > 2 || size_t(4 - NA) * NA * 2 * 64 * 4 * sizeof(Tc) <=
+                              size_t(3) * CT * (16 * NA + 1) * sizeof(Tc),
+                "wave sums fit in the staging buffers");
   return size_t(CT + 4) * (16 * NA + 1) * sizeof(T) + size_t(5) * CT * sizeof(T) +
          size_t(3) * CT * (16 * NA + 1) * sizeof(Tc);
 }
