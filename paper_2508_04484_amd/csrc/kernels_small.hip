@@ -14,6 +14,7 @@ namespace {
 constexpr int kT = 16;
 constexpr int kWG = 512;   // threads of the single-workgroup kernels
 constexpr int kTruncLdsDoubles = 19200;   // LDS room of k_truncate (150 KiB)
+constexpr size_t kSmallMaxLds = 150 * 1024;   // largest dynamic LDS a small kernel asks for
 
 // ------------------------------------------------------------------ small GEMM
 __global__ void k_small_gemm(int ta, int tb, int M, int N, int K, double alpha,
@@ -85,29 +86,55 @@ __device__ void blk_gemm(int ta, int tb, int M, int N, int K, double alpha, cons
   __syncthreads();
 }
 
-// coef[j] = sum_t Q(t, j) v(t) for j < cnt: one wave per column, the lanes
-// stride over t and a fixed shuffle tree reduces (deterministic).
+// x of the lane that the DPP row permutation CTRL names, both 32-bit halves
+template <int CTRL>
+__device__ inline double dpp_mov(double x) {
+  const unsigned long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(
+      (long long)((unsigned long long)unsigned(hi) << 32 | (unsigned long long)unsigned(lo)));
+}
+
+// Sum over each aligned group of 16 lanes (all lanes of the row active): four pairwise
+// exchanges (swap neighbours, swap pairs of a quad, mirror each half row,
+// mirror the row).  Every step pairs lanes symmetrically, so all 16 lanes end
+// with the same bits.
+__device__ inline double row16_sum(double x) {
+  x += dpp_mov<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += dpp_mov<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += dpp_mov<0x141>(x);   // row_half_mirror
+  x += dpp_mov<0x140>(x);   // row_mirror
+  return x;
+}
+
+// coef[j] = sum_t Q(t, j) v(t) for j < cnt: 16 lanes (one DPP row) per
+// column stride over t and sum across the row (deterministic).  The
+// workgroup size is a multiple of 64.
 __device__ void blk_coefs(const double *Q, int ldq, int p, int cnt, const double *v,
                           double *coef) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int j = wv; j < cnt; j += nw) {
+  const int lane = threadIdx.x & 15, grp = threadIdx.x >> 4, ng = blockDim.x >> 4;
+  for (int j = grp; j < cnt; j += ng) {   // uniform within a DPP row
     double s = 0.0;
-    for (int t = lane; t < p; t += 64) s += Q[t + size_t(j) * ldq] * v[t];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+#pragma unroll 4
+    for (int t = lane; t < p; t += 16) s += Q[t + size_t(j) * ldq] * v[t];
+    s = row16_sum(s);
     if (lane == 0) coef[j] = s;
   }
   __syncthreads();
 }
 
-// C(M x N) = alpha A^T B (A: K x M, B: K x N, long K) with one wave per output.
+// C(M x N) = alpha A^T B (A: K x M, B: K x N, long K), one DPP row of 16
+// lanes per output.
 __device__ void blk_gemm_tn(int M, int N, int K, double alpha, const double *A, int lda,
                             const double *B, int ldb, double *C, int ldc) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int e = wv; e < M * N; e += nw) {
+  const int lane = threadIdx.x & 15, grp = threadIdx.x >> 4, ng = blockDim.x >> 4;
+  for (int e = grp; e < M * N; e += ng) {   // uniform within a DPP row
     const int i = e % M, j = e / M;
     double s = 0.0;
-    for (int t = lane; t < K; t += 64) s += A[t + size_t(i) * lda] * B[t + size_t(j) * ldb];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+#pragma unroll 4
+    for (int t = lane; t < K; t += 16) s += A[t + size_t(i) * lda] * B[t + size_t(j) * ldb];
+    s = row16_sum(s);
     if (lane == 0) C[i + size_t(j) * ldc] = alpha * s;
   }
   __syncthreads();
@@ -128,28 +155,6 @@ __device__ inline void rr_pair(int qe, int round, int k, int &i, int &j) {
     i = j;
     j = t;
   }
-}
-
-// x of the lane that the DPP row permutation CTRL names, both 32-bit halves
-template <int CTRL>
-__device__ inline double dpp_mov(double x) {
-  const unsigned long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(
-      (long long)((unsigned long long)unsigned(hi) << 32 | (unsigned long long)unsigned(lo)));
-}
-
-// Sum over each aligned group of 16 lanes (all lanes active): four pairwise
-// exchanges (swap neighbours, swap pairs of a quad, mirror each half row,
-// mirror the row).  Every step pairs lanes symmetrically, so all 16 lanes end
-// with the same bits.
-__device__ inline double row16_sum(double x) {
-  x += dpp_mov<0xB1>(x);    // quad_perm [1, 0, 3, 2]
-  x += dpp_mov<0x4E>(x);    // quad_perm [2, 3, 0, 1]
-  x += dpp_mov<0x141>(x);   // row_half_mirror
-  x += dpp_mov<0x140>(x);   // row_mirror
-  return x;
 }
 
 // Rounds of the one-sided Jacobi below for p, q <= 64 when the workgroup has
@@ -820,6 +825,7 @@ __global__ __launch_bounds__(256) void k_collided_solve(int N, int m, int r, int
 }
 
 // ------------------------------------------------------------------ QR with completion
+template <bool QL>
 __global__ __launch_bounds__(kWG) void k_qr_complete(int m, int r, const double *__restrict__ L1,
                                                     const double *__restrict__ V, double tol,
                                                     double fill_tol, double *Vt, double *St,
@@ -828,6 +834,10 @@ __global__ __launch_bounds__(kWG) void k_qr_complete(int m, int r, const double 
   extern __shared__ double dyn[];
   double *v = dyn;                  // m (LDS)
   double *coef = dyn + m;           // r (LDS)
+  // the basis being built: in LDS when it fits (copied to Vt at the end)
+  double *Q;
+  if constexpr (QL) Q = dyn + m + r;
+  else Q = Vt;
   (void)work;
   double nl = 0.0;
   for (int e = threadIdx.x; e < m * r; e += blockDim.x) nl += L1[e] * L1[e];
@@ -840,11 +850,11 @@ __global__ __launch_bounds__(kWG) void k_qr_complete(int m, int r, const double 
       for (int t = threadIdx.x; t < m; t += blockDim.x) v[t] = cand[t + size_t(c) * m];
       __syncthreads();
       for (int pass = 0; pass < 2; ++pass) {
-        blk_coefs(Vt, m, m, cnt, v, coef);
+        blk_coefs(Q, m, m, cnt, v, coef);
         for (int t = threadIdx.x; t < m; t += blockDim.x) {
           double s = v[t];
 #pragma unroll 8
-          for (int j = 0; j < cnt; ++j) s -= Vt[t + size_t(j) * m] * coef[j];
+          for (int j = 0; j < cnt; ++j) s -= Q[t + size_t(j) * m] * coef[j];
           v[t] = s;
         }
         __syncthreads();
@@ -853,15 +863,17 @@ __global__ __launch_bounds__(kWG) void k_qr_complete(int m, int r, const double 
       for (int t = threadIdx.x; t < m; t += blockDim.x) nv += v[t] * v[t];
       nv = sqrt(blk_sum(nv, red));
       if (nv > accept) {
-        for (int t = threadIdx.x; t < m; t += blockDim.x) Vt[t + size_t(cnt) * m] = v[t] / nv;
+        for (int t = threadIdx.x; t < m; t += blockDim.x) Q[t + size_t(cnt) * m] = v[t] / nv;
         ++cnt;
       }
       __syncthreads();
     }
   }
   if (cnt != r && threadIdx.x == 0) atomicOr(&ctl->flags, kFlagCompletion);
+  if constexpr (QL)
+    for (int e = threadIdx.x; e < m * cnt; e += blockDim.x) Vt[e] = Q[e];
   // S~ = L1^T V~
-  blk_gemm_tn(r, r, m, 1.0, L1, m, Vt, m, St, lds);
+  blk_gemm_tn(r, r, m, 1.0, L1, m, Q, m, St, lds);
 }
 
 __global__ void k_check_finite(const double *__restrict__ x, int count, Ctl *ctl) {
@@ -1002,7 +1014,17 @@ void launch_qr_complete(int m, int r, const double *L1, const double *V, double 
                         double fill_tol, double *Vt, double *St, int lds, Ctl *ctl,
                         double *work, hipStream_t st) {
   const size_t shm = size_t(m + r) * sizeof(double);
-  k_qr_complete<<<1, kWG, shm, st>>>(m, r, L1, V, tol, fill_tol, Vt, St, lds, ctl, work);
+  const size_t shm_q = shm + size_t(m) * r * sizeof(double);
+  if (shm_q <= kSmallMaxLds) {
+    if (shm_q > 64 * 1024)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_qr_complete<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(kSmallMaxLds));
+    k_qr_complete<true><<<1, kWG, shm_q, st>>>(m, r, L1, V, tol, fill_tol, Vt, St, lds, ctl,
+                                               work);
+  } else {
+    k_qr_complete<false><<<1, kWG, shm, st>>>(m, r, L1, V, tol, fill_tol, Vt, St, lds, ctl,
+                                              work);
+  }
 }
 
 void launch_check_finite(const double *x, int count, Ctl *ctl, hipStream_t st) {
