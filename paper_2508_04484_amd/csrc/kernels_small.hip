@@ -297,6 +297,96 @@ __device__ __attribute__((always_inline)) void blk_jacobi(double *A, int lda, in
   }
 }
 
+// SVD of A (p x q, q <= p <= 64) by one-sided Jacobi with QR preconditioning
+// (Householder A = H [R; 0], H = H_0 ... H_{q-1}; Jacobi on R^T, whose
+// columns converge in far fewer sweeps than those of a graded A):
+// R^T Z = Y with orthogonal columns, sigma_j = ||Y_j||, and then
+// A V = H [Z; 0] diag(sigma) for V = Y diag(1 / sigma).  Leaves the same
+// outputs as blk_jacobi on A: A <- A V (columns u_j sigma_j), V the right
+// singular vectors (a zero column where sigma_j = 0).  X (q x q), B (p x q)
+// and hb (2 q) are scratch; one DPP row of 16 lanes works on one column.
+__device__ __attribute__((always_inline)) void blk_svd_qr(double *A, int p, int q, double *V,
+                                                          double *X, double *B, double *hb,
+                                                          int *flag, double *red) {
+  const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4, ng = blockDim.x >> 4;
+  double *beta = hb, *rdiag = hb + q;
+  // Householder QR: reflector k in A[k:, k], R above the diagonal of A
+  for (int k = 0; k < q; ++k) {
+    double *x = A + k + size_t(k) * p;
+    const int len = p - k;
+    if (grp == 0) {
+      double s2 = 0.0;
+#pragma unroll 4
+      for (int t = lane; t < len; t += 16) s2 += x[t] * x[t];
+      s2 = row16_sum(s2);
+      if (lane == 0) {
+        const double nrm = sqrt(s2), x0 = x[0];
+        if (nrm > 0.0) {
+          const double sg = x0 >= 0.0 ? 1.0 : -1.0;
+          rdiag[k] = -sg * nrm;
+          beta[k] = 1.0 / (nrm * (nrm + fabs(x0)));
+          x[0] = x0 + sg * nrm;
+        } else {
+          rdiag[k] = 0.0;
+          beta[k] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    const double bk = beta[k];
+    for (int j = k + 1 + grp; j < q; j += ng) {   // uniform within a DPP row
+      double *y = A + k + size_t(j) * p;
+      double w = 0.0;
+#pragma unroll 4
+      for (int t = lane; t < len; t += 16) w += x[t] * y[t];
+      w = row16_sum(w) * bk;
+#pragma unroll 4
+      for (int t = lane; t < len; t += 16) y[t] -= w * x[t];
+    }
+    __syncthreads();
+  }
+  // X = R^T
+  for (int e = tid; e < q * q; e += blockDim.x) {
+    const int a = e % q, b = e / q;
+    X[e] = b < a ? A[b + size_t(a) * p] : (b == a ? rdiag[a] : 0.0);
+  }
+  __syncthreads();
+  blk_jacobi(X, q, q, q, V, q, flag, red);   // X <- Y, V <- Z
+  __syncthreads();
+  // B = H [Z; 0], reflectors applied last to first; a row owns its columns
+  for (int e = tid; e < p * q; e += blockDim.x) {
+    const int i = e % p, j = e / p;
+    B[e] = i < q ? V[i + size_t(j) * q] : 0.0;
+  }
+  __syncthreads();
+  for (int j = grp; j < q; j += ng) {
+    for (int k = q - 1; k >= 0; --k) {
+      const double *x = A + k + size_t(k) * p;
+      double *y = B + k + size_t(j) * p;
+      const int len = p - k;
+      double w = 0.0;
+#pragma unroll 4
+      for (int t = lane; t < len; t += 16) w += x[t] * y[t];
+      w = row16_sum(w) * beta[k];
+#pragma unroll 4
+      for (int t = lane; t < len; t += 16) y[t] -= w * x[t];
+    }
+  }
+  __syncthreads();
+  for (int j = grp; j < q; j += ng) {
+    double s2 = 0.0;
+#pragma unroll 4
+    for (int t = lane; t < q; t += 16) s2 += X[t + size_t(j) * q] * X[t + size_t(j) * q];
+    const double sg = sqrt(row16_sum(s2));
+#pragma unroll 4
+    for (int t = lane; t < p; t += 16) A[t + size_t(j) * p] = B[t + size_t(j) * p] * sg;
+#pragma unroll 4
+    for (int t = lane; t < q; t += 16)
+      V[t + size_t(j) * q] = sg > 0.0 ? X[t + size_t(j) * q] / sg : 0.0;
+  }
+  __syncthreads();
+}
+
 // Cholesky-based orthonormalisation of a well-conditioned Gram matrix:
 // A = L L^T in place (A: q x q SPD, lower part used and overwritten), then
 // T = L^{-T} (q x q upper triangular, leading dimension ldt) so that X T has
@@ -707,6 +797,8 @@ __global__ __launch_bounds__(kWG) void k_truncate(const double *__restrict__ Sh,
   const int p = cols ? pU : pV, q = cols ? pV : pU;
   // p x q matrix and q x q rotations in LDS when the launch provided room
   const bool in_lds = size_t(P) * P * 2 <= size_t(kTruncLdsDoubles);
+  // room for the QR-preconditioned SVD (two more P x P blocks and 2P)
+  const bool pre = P <= 64 && size_t(P) * P * 4 + 2 * P <= size_t(kTruncLdsDoubles);
   double *A = in_lds ? dyn : work;
   double *V = A + P * P;
   for (int e = threadIdx.x; e < p * q; e += blockDim.x) {
@@ -715,7 +807,10 @@ __global__ __launch_bounds__(kWG) void k_truncate(const double *__restrict__ Sh,
   }
   __syncthreads();
   // the branch lets the LDS case address the matrices as LDS
-  if (in_lds) blk_jacobi(dyn, p, p, q, dyn + P * P, q, &flag, red);
+  if (pre)
+    blk_svd_qr(dyn, p, q, dyn + P * P, dyn + 2 * P * P, dyn + 3 * P * P, dyn + 4 * P * P,
+               &flag, red);
+  else if (in_lds) blk_jacobi(dyn, p, p, q, dyn + P * P, q, &flag, red);
   else blk_jacobi(work, p, p, q, work + P * P, q, &flag, red);
   __syncthreads();
   blk_colnorms_sorted(A, p, p, q, sig, order);
@@ -995,7 +1090,9 @@ void launch_vaug(int m, int r, double *Vh, int ldv, const double *L, double tol,
 void launch_truncate(const double *Sh, int P, const int *kU, const int *kV, int r_base,
                      TruncOpt opt, double *Pp, double *Qp, double *Sp, int lds, Ctl *ctl,
                      double *work, hipStream_t st) {
-  const size_t shm = size_t(P) * P * 2 <= size_t(kTruncLdsDoubles)
+  const bool pre = P <= 64 && size_t(P) * P * 4 + 2 * P <= size_t(kTruncLdsDoubles);
+  const size_t shm = pre ? (size_t(P) * P * 4 + 2 * P) * sizeof(double)
+                     : size_t(P) * P * 2 <= size_t(kTruncLdsDoubles)
                          ? size_t(P) * P * 2 * sizeof(double)
                          : 0;
   if (shm > 60 * 1024)
