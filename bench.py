@@ -318,26 +318,36 @@ def main():
         return bench_batch(problem, args)
     K = min(args.steps, o.n_steps)
 
-    # warm-up: a separate solver runs W steps (code objects, allocator, caches)
+    # warm-up: a separate solver runs W steps (code objects, allocator,
+    # caches); every phase of its steps is timed, for the phase breakdown
+    # (the events themselves add a few microseconds per phase)
+    warm_prof, warm_steps = None, 0
     if args.warmup > 0:
         s = dl.BeamSolver(problem, 0)
         s.raytrace()
-        for _ in range(min(args.warmup, o.n_steps)):
+        s.sync()
+        s.profile(True)
+        warm_steps = min(args.warmup, o.n_steps)
+        for _ in range(warm_steps):
             s.step()
         s.sync()
+        warm_prof = s.profile_read()
+        s.profile(False)
         s.close()
         del s
         torch.cuda.synchronize()
 
+    # the timed solver records only the light events: the step, the ray
+    # tracer and one pair around each step's K-step RK4 loop
     s = dl.BeamSolver(problem, 0)
-    s.profile(True)
+    s.profile(True, light=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.raytrace()
     s.sync()
     t_ray = time.perf_counter() - t0
     prof_ray = s.profile_read()["raytrace"]
-    s.profile(True)          # reset counters for the timed region
+    s.profile(True, light=True)   # reset counters for the timed region
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -399,8 +409,12 @@ def main():
         "event_ms_per_step": round(ev0.elapsed_time(ev1) / K, 3),
         "raytrace_ms": round(1000.0 * t_ray, 2),
         "raytrace_kernel_ms": round(prof_ray[0], 2),
-        "phase_ms_per_step": {k: round(v[0] / K, 3) for k, v in prof.items()
-                              if k not in ("raytrace",) and v[1] > 0},
+        "phase_ms_per_step": None if warm_prof is None else {
+            k: round(v[0] / warm_steps, 3) for k, v in warm_prof.items()
+            if k not in ("raytrace",) and v[1] > 0},
+        "phase_steps": (f"0..{warm_steps - 1} of the warm-up solver, every phase timed"
+                        if warm_prof is not None else None),
+        "kstage_timing": "one event pair per step around its RK4 loop (launch gaps included)",
         "roofline": roof,
     }
     if not args.no_cpu_baseline and args.config == "c3":

@@ -223,9 +223,16 @@ int dlra_plan_objective(int n_cells, int n_beams, const double *doses, const dou
                         size_t work_doubles, void *stream, double *J, double *grad);
 
 /* Timing of the library's own work with HIP events recorded on the context's
- * stream (measurement support; adds one event pair per timed launch).
- *   dlra_profile(ctx, on): on = 1 starts recording, 0 stops; counters are
- *                          reset when recording starts.
+ * stream (measurement support).  Every event record between two kernels
+ * leaves the device idle for a few microseconds.
+ *   dlra_profile(ctx, on): on = 1 records every phase (one event pair per
+ *                          timed launch or phase); on = 2 records only the
+ *                          whole step (DLRA_PH_STEP), the ray tracer and, once
+ *                          per step, the K-step RK4 loop, whose duration goes
+ *                          to DLRA_PH_KSTAGE counted as its 4 n_sub stage
+ *                          launches (the launch gaps inside the loop
+ *                          included); 0 stops.  Counters are reset when
+ *                          recording starts.  DLRA_E_INVALID for another on.
  *   dlra_profile_read(ctx, phase, total_ms, count): synchronises and returns
  *                          the summed duration and number of recorded launches
  *                          of one phase (DLRA_PH_*). */

@@ -210,8 +210,10 @@ class BeamSolver:
         self.sync()
         return out
 
-    def profile(self, on=True):
-        check(self.lib.dlra_profile(self.ctx, 1 if on else 0))
+    def profile(self, on=True, light=False):
+        """Event timing: every phase, or (light) only the step, the ray tracer
+        and the K-step RK4 loop once per step."""
+        check(self.lib.dlra_profile(self.ctx, (2 if light else 1) if on else 0))
 
     def profile_read(self):
         """{phase: (total_ms, launches)} of the event timings recorded so far."""

@@ -229,8 +229,9 @@ struct dlra_ctx {
   struct Rec {
     hipEvent_t a, b;
     int ph;
+    long long n;   // launches the pair brackets
   };
-  bool prof = false;
+  int prof = 0;   // 0 off, 1 every phase, 2 light (step and K-step loop only)
   std::vector<hipEvent_t> pool;
   std::vector<Rec> pending;
   double prof_ms[DLRA_PH_COUNT] = {};
@@ -258,7 +259,7 @@ struct dlra_ctx {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
         prof_ms[r.ph] += ms;
-        prof_n[r.ph] += 1;
+        prof_n[r.ph] += r.n;
       }
       pool.push_back(r.a);
       pool.push_back(r.b);
@@ -285,15 +286,22 @@ struct dlra_ctx {
 
 namespace {
 
-// records an event pair around a phase when timing is on
+// Records an event pair around a phase when timing is on.  An event record
+// between two kernels on a stream costs several microseconds of idle device
+// time, so the light level (2) records only the pairs marked kLight: the
+// whole step and, once per step, the K-step RK4 loop counted as its stage
+// launches; the full level (1) records the others.
+enum TimerLevel { kFull = 1, kLight = 2, kBoth = 3 };
 struct PhaseTimer {
   dlra_ctx *c;
   int ph;
   hipStream_t s;
+  long long n;
   hipEvent_t a = nullptr;
-  PhaseTimer(dlra_ctx *c_, int ph_, hipStream_t s_ = nullptr)
-      : c(c_), ph(ph_), s(s_ ? s_ : c_->st) {
-    if (c->prof) {
+  PhaseTimer(dlra_ctx *c_, int ph_, hipStream_t s_ = nullptr, int when = kFull,
+             long long n_ = 1)
+      : c(c_), ph(ph_), s(s_ ? s_ : c_->st), n(n_) {
+    if (c->prof & when) {
       a = c->event();
       (void)hipEventRecord(a, s);
     }
@@ -302,7 +310,7 @@ struct PhaseTimer {
     if (a) {
       hipEvent_t b = c->event();
       (void)hipEventRecord(b, s);
-      c->pending.push_back({a, b, ph});
+      c->pending.push_back({a, b, ph, n});
     }
   }
 };
@@ -643,7 +651,7 @@ struct Stepper {
     Ctl *ctl = c->ctl();
     int r = c->r;
     T *s = c->at<T>(p.s);
-    PhaseTimer t_step(c, DLRA_PH_STEP);
+    PhaseTimer t_step(c, DLRA_PH_STEP, nullptr, kBoth);
     // coefficients
     launch_inverse_stop<T>(c->gdev, c->at<T>(p.w_t), nm, D(p.stepS) + size_t(k) * nm, s, ctl, st);
     // ---------------- streaming (augmented BUG, RK4)
@@ -685,17 +693,21 @@ struct Stepper {
     launch_pack_couplings<T>(dd.ndk, r, D(p.Bm), P, c->at<T>(p.Bpk), st);
     launch_update<T>(n, tall(0), ld, r, D(p.S), R, 1.0, nullptr, 0, 0.0, tall(1), ld, r, nullptr,
                      nullptr, 0, st);
-    for (int sub = 0; sub < ns; ++sub) {
-      T *K0 = tall(1);
-      T *in = K0;
-      T *outs[2] = {tall(2), tall(3)};
-      for (int stg = 0; stg < 4; ++stg) {
-        T *out = outs[stg & 1];
-        PhaseTimer t(c, DLRA_PH_KSTAGE);
-        launch_kstep_stage<T>(c->gdev, s, in, K0, out, ld, r, c->at<T>(p.Bpk), cf[stg] * h, st);
-        in = out;
+    {
+      PhaseTimer t_kloop(c, DLRA_PH_KSTAGE, nullptr, kLight, 4LL * ns);
+      for (int sub = 0; sub < ns; ++sub) {
+        T *K0 = tall(1);
+        T *in = K0;
+        T *outs[2] = {tall(2), tall(3)};
+        for (int stg = 0; stg < 4; ++stg) {
+          T *out = outs[stg & 1];
+          PhaseTimer t(c, DLRA_PH_KSTAGE);
+          launch_kstep_stage<T>(c->gdev, s, in, K0, out, ld, r, c->at<T>(p.Bpk), cf[stg] * h,
+                                st);
+          in = out;
+        }
+        std::swap(c->tall[1], c->tall[3]);
       }
-      std::swap(c->tall[1], c->tall[3]);
     }
     HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
     // augmentation
@@ -966,7 +978,7 @@ int uncollided_raytrace(dlra_ctx *c) {
                               c->at<double>(p.rt_stopw), c->at<double>(p.rt_scratch), psib,
                               c->at<double>(p.dose_u), c->st);
     };
-    PhaseTimer t(c, DLRA_PH_RAYTRACE);
+    PhaseTimer t(c, DLRA_PH_RAYTRACE, nullptr, kBoth);
     if (d.tsize == 8) go(c->at<double>(p.psibar));
     else go(c->at<float>(p.psibar));
     HIPCHK(hipGetLastError());
@@ -1077,6 +1089,7 @@ int dlra_sync(dlra_ctx *c) {
 
 int dlra_profile(dlra_ctx *c, int on) {
   if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
+  if (on < 0 || on > 2) return fail(DLRA_E_INVALID, "profile level must be 0, 1 or 2");
   try {
     c->drain();
   } catch (const std::exception &e) {
@@ -1088,7 +1101,7 @@ int dlra_profile(dlra_ctx *c, int on) {
       c->prof_n[i] = 0;
     }
   }
-  c->prof = on != 0;
+  c->prof = on;
   return DLRA_OK;
 }
 

@@ -257,3 +257,29 @@ def test_full_size_bench_configuration_one_step():
     want = nxt.U[rows] @ nxt.S @ nxt.V.T
     assert rel(a, want) <= 1e-4
     assert rel(dose_c, nxt.dose_c) <= 1e-4
+
+
+def test_profile_levels():
+    # light timing records the step and one pair per K-step RK4 loop, counted
+    # as its 4 n_sub stage launches; full timing records every stage launch
+    dl = _gpu()
+    say("profile levels")
+    p = configs.small_3d(n=8, r=6)
+    s = dl.BeamSolver(p, 0)
+    s.raytrace()
+    s.profile(True, light=True)
+    s.step()
+    s.step()
+    light = s.profile_read()
+    s.profile(True)
+    s.step()
+    full = s.profile_read()
+    s.profile(False)
+    want = 4 * (s.substeps(0) + s.substeps(1))
+    assert light["kstage"][1] == want and light["step"][1] == 2
+    assert all(v[1] == 0 for k, v in light.items() if k not in ("kstage", "step"))
+    assert full["kstage"][1] == 4 * s.substeps(2) and full["projection"][1] == 2
+    assert full["step"][1] == 1
+    with pytest.raises(RuntimeError):
+        dl.binding.check(s.lib.dlra_profile(s.ctx, 3))
+    s.close()
