@@ -776,7 +776,9 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
   T *Sw = Xh + CH * PA;                           // [5][CT] s at the stencil points (0 outside)
   Tc *Yb = reinterpret_cast<Tc *>(Sw + 5 * CT);   // [CT][PA]
   Tc *Yf = Yb + CT * PA;                          // [CT][PA]
-  Tc *Xs = Yf + CT * PA;                          // [CT][PA] left factor in the MFMA type
+  // the left factor is read from the tile's own rows of Xh: beyond the chunk
+  // end the differences are zero, and rows a >= p are never written out
+  static_assert(sizeof(T) == sizeof(Tc), "left factor read in the storage type");
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int c = lane & 15, qq = lane >> 4;
@@ -861,12 +863,6 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
       if (e < 5 * CT) Sw[e] = in ? sr[u] : T(0);
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = tid + 256 * i, cc = e % CT, a = e / CT;
-      const bool ok = x0 + cc < x_end && a < p;
-      Xs[cc * PA + a] = ok ? Tc(Xh[(cc + 2) * PA + a]) : Tc(0);
-    }
     // each thread keeps one cell (cc = tid % CT) and walks the columns b
     {
       const int cc = tid % CT, x = x0 + cc, xc = min(x, x_end - 1);
@@ -918,7 +914,7 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
         const Tc yb = Yb[cell * PA + btile * 16 + c], yf = Yf[cell * PA + btile * 16 + c];
 #pragma unroll
         for (int at = 0; at < NA; ++at) {
-          const Tc xa = Xs[cell * PA + at * 16 + c];
+          const Tc xa = Xh[(cell + 2) * PA + at * 16 + c];
           ab[bt][at] = Mfma<Tc>::op(xa, yb, ab[bt][at]);
           af[bt][at] = Mfma<Tc>::op(xa, yf, af[bt][at]);
         }
@@ -979,12 +975,12 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
 template <typename T, typename Tc, int NA>
 constexpr size_t stencil_proj_lds() {
   constexpr int CT = sizeof(Tc) == 8 ? 32 : 64;
-  // the wave-sum exchange of NA <= 2 reuses the three CT x (16 NA + 1) buffers
-  static_assert(NA > 2 || size_t(4 - NA) * NA * 2 * 64 * 4 * sizeof(Tc) <=
-                              size_t(3) * CT * (16 * NA + 1) * sizeof(Tc),
-                "wave sums fit in the staging buffers");
+  // the two difference tiles; the wave-sum exchange of NA <= 2 reuses them
+  // (extended where it needs more room)
+  constexpr size_t diff = size_t(2) * CT * (16 * NA + 1) * sizeof(Tc);
+  constexpr size_t xchg = NA <= 2 ? size_t(4 - NA) * NA * 2 * 64 * 4 * sizeof(Tc) : 0;
   return size_t(CT + 4) * (16 * NA + 1) * sizeof(T) + size_t(5) * CT * sizeof(T) +
-         size_t(3) * CT * (16 * NA + 1) * sizeof(Tc);
+         (diff > xchg ? diff : xchg);
 }
 
 // Weighted Grams G(a, b) = sum_x X(x, a) wt(x) Y(x, b) on the matrix cores
