@@ -11,7 +11,8 @@ Follows Sec. 3.3.3 with the augmented BUG integrator of Sec. 2.2 (eq. KLS):
      (I - dt sum_i a_{il} M_i) L1[p, :]^T = L0[p, :]^T for every p of degree l,
      M_i = U^T diag(w_i s) U, L0 = V S^T; QR with completion -> (V~, S~)
 3. uncollided in-scattering source, explicit Euler (items 2-4), starting from
-   (U^1/2, S~, V~), source term sum_i (w_i psi_u) g_i^T with
+   (U^1/2, S~, V~), source term sum_i (w_i psi_u) g_i^T (summed over the beams
+   of a joint source) with
    g_i = (G_l - G_{N+1}) T_M (no 1/S factor: the collided equation of
    eq. final_collided_multmat sources the untransformed psi_u):
      K = U S~ + dt sum_i q_i (V~^T g_i)^T,  L = V~ S~^T + dt sum_i g_i (U^T q_i)^T,
@@ -94,28 +95,40 @@ def collided(U, S, V, c, w, N, opts):
     return U, St, Vt
 
 
-def uncollided(U, St, Vt, c, w, psibar_k, opts):
+def source_factors(w, psibars, gs):
+    """Q (n x n_src) and G (m x n_src) with Q G^T = sum_b sum_i (w_i o psi_b) g_{i,b}^T:
+    the in-scattering source of one or several beams (a joint source, the
+    two-beam case of Sec. 4.3), columns beam-major."""
+    Q = np.concatenate([(w * ps[None, :]).T for ps in psibars], axis=1)
+    G = np.concatenate(gs, axis=1)
+    return Q, G
+
+
+def uncollided(U, St, Vt, dt, Q, G, opts):
+    """Explicit-Euler K, L and S steps of the source Q G^T (Sec. 3.3.3 items 2-4)."""
     r = U.shape[1]
-    Q = (w * psibar_k[None, :]).T                       # (n, n_mat), q_i = w_i o psi_u
-    Ku = U @ St + c.dt * Q @ (Vt.T @ c.g).T
-    Lu = Vt @ St.T + c.dt * c.g @ (U.T @ Q).T
+    Ku = U @ St + dt * Q @ (Vt.T @ G).T
+    Lu = Vt @ St.T + dt * G @ (U.T @ Q).T
     Uh = linalg.augment(U, Ku, opts.aug_tol)
     Vh = linalg.augment(Vt, Lu, opts.aug_tol)
     Sh = np.zeros((Uh.shape[1], Vh.shape[1]))
     Sh[:r, :r] = St
-    Sh += c.dt * (Uh.T @ Q) @ (Vh.T @ c.g).T
+    Sh += dt * (Uh.T @ Q) @ (Vh.T @ G).T
     P, Sn, Qv = linalg.truncate(Sh, opts, rank_target(opts, r))
     return Uh @ P, Sn, Vh @ Qv, (Uh.shape[1] - r, Vh.shape[1] - r)
 
 
-def step(state, c, Apm, problem, psibar_k):
-    """Advance `state` by energy step c.k in place-free fashion; returns a new State."""
+def step(state, c, Apm, problem, psibar_k, sources=None):
+    """Advance `state` by energy step c.k in place-free fashion; returns a new
+    State.  The source is that of one beam (psibar_k with c.g), or the factor
+    pair `sources` = (Q, G) of source_factors for several beams."""
     g, o = problem.grid, problem.options
     w = problem.materials.w
+    Q, G = source_factors(w, [psibar_k], [c.g]) if sources is None else sources
     U, S, V, aug1 = streaming(state.U, state.S, state.V, c, Apm, g, o)
     r_half = U.shape[1]
     U, St, Vt = collided(U, S, V, c, w, o.pn_degree, o)
-    U, S, V, aug2 = uncollided(U, St, Vt, c, w, psibar_k, o)
+    U, S, V, aug2 = uncollided(U, St, Vt, c.dt, Q, G, o)
     dose_c = state.dose_c + c.dt * math.sqrt(4.0 * math.pi) * (U @ (S @ V[0, :]))
     log = state.log + [dict(k=c.k, n_sub=c.n_sub, r_half=r_half, r=U.shape[1],
                             aug_stream=aug1, aug_source=aug2)]

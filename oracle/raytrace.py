@@ -32,7 +32,7 @@ import math
 
 import numpy as np
 
-from .coeffs import energy_grid
+from .coeffs import energy_edges
 
 
 def _slope_table(e_tab, v_tab, E):
@@ -146,10 +146,19 @@ class EnergyDG:
         return np.array([f(eye[j]) for j in range(3 * self.G)])
 
 
+def removal_table(problem, i):
+    """Tabulated removal rate of the uncollided flux for material i:
+    G_0 - G_{N+1} (Boltzmann with the extended transport correction), or zero
+    (Fokker-Planck: Gamma_out = 0, Sec. 3.1)."""
+    mat = problem.materials
+    if getattr(problem.options, "collision", "boltzmann") == "fokker_planck":
+        return np.zeros_like(mat.e)
+    return mat.dG[i, :, problem.options.pn_degree + 1]
+
+
 def material_operators(problem, dg):
     mat = problem.materials
-    N = problem.options.pn_degree
-    return [dg.operator(mat.e, mat.S[i], mat.T[i], mat.dG[i, :, N + 1])
+    return [dg.operator(mat.e, mat.S[i], mat.T[i], removal_table(problem, i))
             for i in range(mat.n_mat)]
 
 
@@ -226,20 +235,22 @@ def lateral(grid, beam, xc):
 # ------------------------------------------------------------------ tracing
 
 class Tracer:
-    def __init__(self, problem, beam):
+    def __init__(self, problem, beam, edges=None):
+        """edges: the run's energy grid E_0 > ... > E_n (default: the beam's own)."""
         o = problem.options
         self.problem, self.beam = problem, beam
-        self.e_max, self.e_cut, self.dt = energy_grid(beam, o)
+        self.edges = energy_edges(problem, [beam]) if edges is None else np.asarray(edges)
+        self.e_max, self.e_cut = float(self.edges[0]), float(self.edges[-1])
         self.dg = EnergyDG(self.e_cut, self.e_max, o.n_groups)
         self.ops = material_operators(problem, self.dg)
         self._cache = {}
         mat = problem.materials
         # linear functionals of the DG coefficients: step integrals and, per
         # material, int S_i(E) psi dE
+        E = self.edges
         self.step_int = np.stack([
-            self.dg.functional(lambda c, k=k: self.dg.integral(
-                c, self.e_max - (k + 1) * self.dt, self.e_max - k * self.dt))
-            for k in range(o.n_steps)]) / self.dt
+            self.dg.functional(lambda c, k=k: self.dg.integral(c, E[k + 1], E[k]))
+            / (E[k] - E[k + 1]) for k in range(o.n_steps)])
         self.stop_int = np.stack([
             self.dg.functional(lambda c, i=i: self.dg.weighted_integral(
                 c, lambda E: np.interp(E, mat.e, mat.S[i])))

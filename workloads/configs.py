@@ -20,12 +20,17 @@ beams with 1% energy spread, Sec. 4) at the sizes of the benchmark workloads:
   c4_axis  c4 with the beam directions snapped to the nearest axial grid axis
   c5  c2's phantom with 9 beams of 100 + 10 b MeV at 40 b degrees aimed at the
       centre (adjoint workload)
+  c2_elements, c3_elements  c2 / c3 with every voxel decomposed into the
+      paper's twelve elements (12 base materials)
+  two_beams  the paper's two-beam case on c1's grid: two perpendicular 70 MeV
+      beams in water in one joint collided solve
 
 Every random draw uses numpy's PCG64 with the stated seed.  Nothing here
 implements any part of the transport method.
 """
 from __future__ import annotations
 
+import dataclasses
 import functools
 import hashlib
 import math
@@ -189,7 +194,40 @@ def c5(**opt) -> Problem:
     return Problem(p.grid, p.materials, beams, p.options, name="c5")
 
 
-CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c4_axis": c4_axis, "c5": c5}
+def to_elements(problem: Problem) -> Problem:
+    """The same phantom decomposed into the paper's twelve elements (Sec. 2.1):
+    every voxel's compound partial densities become elemental partial densities
+    (mass fractions of the compounds), with per-element tables."""
+    names, w = M.element_weights(problem.materials.names, problem.materials.w)
+    mats = make_materials(names, w, problem.options.pn_degree)
+    return Problem(problem.grid, mats, problem.beams, problem.options,
+                   name=problem.name + "_elements", meta=dict(problem.meta))
+
+
+def c2_elements(**opt) -> Problem:
+    """c2's slab phantom with the twelve-element decomposition."""
+    return to_elements(c2(**opt))
+
+
+def c3_elements(**opt) -> Problem:
+    """c3's random phantom with the twelve-element decomposition."""
+    return to_elements(c3(**opt))
+
+
+def two_beams(**opt) -> Problem:
+    """The paper's two-beam case (Sec. 4.3) on c1's grid: 2D water 64 x 64 cells
+    of 1 mm, two perpendicular 70 MeV beams (sigma 3 mm), one along +x through
+    the centre row and one along +y through the centre column, in one joint
+    collided solve (P_7, fixed rank 10, 100 energy steps, FP64)."""
+    p = c1(**opt)
+    L = p.grid.nx * p.grid.dx
+    b2 = Beam(E0=70.0, sigma_E=0.7, spot_sigma=0.3, pos=(0.5 * L + 0.013, 0.0, 0.0),
+              dir=(0.0, 1.0, 0.0))
+    return Problem(p.grid, p.materials, [p.beams[0], b2], p.options, name="two_beams")
+
+
+CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c4_axis": c4_axis, "c5": c5,
+           "c2_elements": c2_elements, "c3_elements": c3_elements, "two_beams": two_beams}
 
 
 # ---------------------------------------------------------------- small cases
@@ -213,6 +251,17 @@ def small_2d(nx=16, ny=12, N=3, E0=30.0, n_steps=12, spot=0.15, mats="water", r=
         raise ValueError(mats)
     m = make_materials(names, w, o.pn_degree)
     return Problem(grid, m, [beam_along_x(E0, spot, 0.5 * ny * dx + 0.013)], o, name="small_2d")
+
+
+def small_joint_2d(nx=14, ny=14, N=3, n_steps=10, mats="slab", r=8, dx=0.05, E=(25.0, 20.0),
+                   weights=(1.0, 0.7), **opt) -> Problem:
+    """Small 2D case with two perpendicular beams (+x and +y) of different
+    energies and weights, for joint-source tests."""
+    p = small_2d(nx=nx, ny=ny, N=N, n_steps=n_steps, mats=mats, r=r, dx=dx, E0=E[0], **opt)
+    b1 = dataclasses.replace(p.beams[0], weight=weights[0])
+    b2 = Beam(E0=E[1], sigma_E=0.01 * E[1], spot_sigma=0.15, weight=weights[1],
+              pos=(0.5 * nx * dx - 0.021, 0.0, 0.0), dir=(0.0, 1.0, 0.0))
+    return Problem(p.grid, p.materials, [b1, b2], p.options, name="small_joint_2d")
 
 
 def small_3d(n=8, N=3, E0=25.0, n_steps=8, spot=0.15, mats="random", r=6, dx=0.05,

@@ -98,6 +98,24 @@ AIR = BaseMaterial(
 )
 BASE_MATERIALS = {m.name: m for m in (WATER, BONE, LUNG, AIR)}
 
+# The twelve elements themselves as base materials (the paper's decomposition,
+# Sec. 2.1): mass fraction one, the element's own mean excitation energy.
+ELEMENT_MATERIALS = {e: BaseMaterial(e, 0.0, ((e, 1.0),), v[2]) for e, v in ELEMENTS.items()}
+BASE_MATERIALS.update(ELEMENT_MATERIALS)
+
+
+def element_weights(names, w):
+    """Partial densities of the twelve elements (12 x n, g/cm^3, in ELEMENTS
+    order) of voxels given as partial densities w (n_mat x n) of the compound
+    base materials `names`: w_e(x) = sum_c w_c(x) f_{c,e} with f the compound's
+    elemental mass fractions."""
+    els = list(ELEMENTS)
+    out = np.zeros((len(els), np.asarray(w).shape[1]))
+    for c, name in enumerate(names):
+        for el, f in BASE_MATERIALS[name].fractions:
+            out[els.index(el)] += f * np.asarray(w)[c]
+    return tuple(els), out
+
 
 def kinematics(E):
     """Proton kinetic energy E (MeV) -> (beta^2, gamma, p c in MeV)."""

@@ -86,6 +86,9 @@ class Options:
     ray_h_max: float = 0.01        # cm, ray-tracer step bound (Sec. 3.2)
     n_groups: int = 128            # DG energy groups of the ray tracer (Sec. 3.2)
     beam_cut_sigmas: float = 8.0   # rays are traced where d_perp <= cut * spot sigma
+    collision: str = "boltzmann"   # "boltzmann" | "fokker_planck" (Sec. 2.1)
+    egrid: str = "uniform"         # "uniform" | "proportional" | "cfl" | "user"
+    egrid_points: tuple = ()       # n_steps + 1 descending energies (egrid = "user")
 
     def cfl(self, dim: int) -> float:
         if self.nu_max > 0:
