@@ -5,8 +5,10 @@
  * voxel phantom with the rank-adaptive augmented basis-update & Galerkin
  * integrator (paper Sec. 2.2, eq. KLS), energy acting as pseudo-time
  * (Sec. 3.3), and feeds it with the uncollided flux of a ray tracer
- * (Sec. 3.2).  One context holds one beam.  All compute runs in HIP kernels
- * on the stream given at initialisation.
+ * (Sec. 3.2).  A context holds one pencil beam, or several beams whose
+ * uncollided fluxes source one joint collided solve (the two-beam case of
+ * Sec. 4.3).  All compute runs in HIP kernels on the stream given at
+ * initialisation.
  *
  * Conventions
  *   - Cells are ordered x fastest: cell = (k*ny + j)*nx + i (Sec. 3.3.2).
@@ -45,6 +47,25 @@ enum {
 
 enum { DLRA_RANK_FIXED = 0, DLRA_RANK_ADAPTIVE = 1 };
 enum { DLRA_FP64 = 0, DLRA_MIXED = 1 };
+/* Collision operator (Sec. 2.1, Sec. 3.1): Boltzmann with the extended
+ * transport correction, or Fokker-Planck (eigenvalues -xi_1 l (l+1) / 2 of the
+ * scaled Laplace-Beltrami operator, xi_1 = G_0 - G_1; no removal of the
+ * uncollided flux, Gamma_out = 0, which sources the whole operator). */
+enum { DLRA_BOLTZMANN = 0, DLRA_FOKKER_PLANCK = 1 };
+/* Pseudo-time (energy) grid E_0 = E_max > E_1 > ... > E_n = E_cut; step k
+ * spans [E_{k+1}, E_k] and takes its coefficients at the midpoint.
+ *   UNIFORM       equal steps (the paper's experiments)
+ *   PROPORTIONAL  E_k = E_cut (E_max / E_cut)^(1 - k/n): short steps at low
+ *                 energy, where the flux changes fastest (the non-uniform
+ *                 grid proposed in Sec. 6)
+ *   CFL           equal steps of residual range in the least-stopping voxel,
+ *                 R(E_k) = (1 - k/n) R(E_max), R(E) = int_{E_cut}^E dE'/S_min,
+ *                 S_min(E) = min_x S(x, E) (trapezoid rule on 4096 equal
+ *                 intervals, inverted by linear interpolation): every step
+ *                 takes the same number of RK4 substeps
+ *   USER          the n_steps + 1 descending energies of egrid_points */
+enum { DLRA_EGRID_UNIFORM = 0, DLRA_EGRID_PROPORTIONAL = 1, DLRA_EGRID_CFL = 2,
+       DLRA_EGRID_USER = 3 };
 
 /* Structured grid (Sec. 3.3.2).  nz == 1 selects the 2D problem (streaming in
  * x and y only).  Spacings in cm. */
@@ -54,7 +75,8 @@ typedef struct {
 } dlra_grid;
 
 /* Mixture model (Sec. 2.1, eq. mixXS): per-voxel partial densities of n_mat
- * base materials and per-material energy tables, interpolated linearly in E.
+ * base materials (1 <= n_mat <= 16; the paper's decomposition has twelve
+ * elements) and per-material energy tables, interpolated linearly in E.
  *   w   [n_mat][n_cells]     partial density of material i in the cell, g/cm^3
  *   e   [n_e]                ascending table energies, MeV
  *   S   [n_mat][n_e]         mass stopping power, MeV cm^2/g
@@ -77,7 +99,8 @@ typedef struct {
 
 /* Pencil beam (Sec. 4): Gaussian energy spectrum N(E0, sigma_E) and Gaussian
  * lateral profile of standard deviation spot_sigma around the axis through
- * pos along the unit vector dir. */
+ * pos along the unit vector dir.  weight scales the beam's source (protons
+ * per unit of the plan); the deposited energy is linear in it. */
 typedef struct {
   double E0, sigma_E, spot_sigma, weight;
   double pos[3];
@@ -86,7 +109,8 @@ typedef struct {
 
 /* Method options.
  *   pn_degree     N of the real spherical-harmonics expansion, m = (N+1)^2
- *   n_steps       uniform energy steps on [e_cut, E0 + e_max_sigmas*sigma_E]
+ *   n_steps       energy steps on [e_cut, E_max], E_max = the largest
+ *                 E0 + e_max_sigmas*sigma_E of the context's beams
  *   rank_mode     DLRA_RANK_FIXED (rank r) or DLRA_RANK_ADAPTIVE
  *                 (relative L1 singular-value tail <= trunc_tol, rank clamped
  *                 to [r_min, r_max], initial rank r_min) (Sec. 2.2)
@@ -101,7 +125,11 @@ typedef struct {
  *   n_sub_max     upper bound on RK4 substeps per energy step (DLRA_E_CFL)
  *   ray_h_max     maximal Crank-Nicolson step of the ray tracer, cm (Sec. 3.2)
  *   n_groups      DG energy groups of the ray tracer (Sec. 3.2)
- *   beam_cut_sigmas  rays are traced for cells within this many spot sigmas */
+ *   beam_cut_sigmas  rays are traced for cells within this many spot sigmas
+ *   collision     DLRA_BOLTZMANN or DLRA_FOKKER_PLANCK
+ *   egrid         DLRA_EGRID_*; egrid_points: host [n_steps + 1] strictly
+ *                 descending energies > 0 for DLRA_EGRID_USER (then E_max and
+ *                 e_cut are its first and last entries), else ignored */
 typedef struct {
   int pn_degree;
   int n_steps;
@@ -119,32 +147,41 @@ typedef struct {
   double nu_max;
   double ray_h_max;
   double beam_cut_sigmas;
+  int collision;
+  int egrid;
+  const double *egrid_points;
 } dlra_options;
 
 typedef struct dlra_ctx dlra_ctx;
 
-/* Bytes of device workspace dlra_init needs for this grid, material count
- * and options. */
-int dlra_workspace_size(const dlra_grid *grid, int n_mat, const dlra_options *opt,
+/* Bytes of device workspace dlra_init needs for this grid, material count,
+ * beam count and options. */
+int dlra_workspace_size(const dlra_grid *grid, int n_mat, int n_beams, const dlra_options *opt,
                         size_t *bytes);
 
 /* Validates the problem, copies the tables to the device, builds the P_N
  * streaming matrices A_d = int m m^T Omega_d and their eigen-split A_d^{+-}
- * (Sec. 3.3.1-3.3.2), the per-step coefficients at E_{k+1/2}, the RK4
- * substep counts and the initial low-rank state (S = 0).
+ * (Sec. 3.3.1-3.3.2), the energy grid, the per-step coefficients at the step
+ * midpoints, the RK4 substep counts and the initial low-rank state (S = 0).
+ *   n_beams     1 <= n_beams <= 64 beams (host array beams[n_beams]); with
+ *               more than one, their weighted uncollided fluxes source one
+ *               joint collided solve, sum_b sum_i (w_i psi_b) g_{i,b}^T
+ *               (Sec. 4.3), with n_mat * n_beams <= 64
  *   workspace   device memory of at least dlra_workspace_size bytes, 256-byte
  *               aligned, owned by the caller and kept until dlra_destroy
  *   stream      hipStream_t to enqueue on (NULL: the null stream)
- * On success *out receives the context.  Synchronises the stream once. */
-int dlra_init(const dlra_grid *grid, const dlra_materials *mat, const dlra_beam *beam,
-              const dlra_options *opt, void *workspace, size_t workspace_bytes,
-              void *stream, dlra_ctx **out);
+ * On success *out receives the context.  Synchronises the stream once.
+ * DLRA_E_CFL when a step needs more than n_sub_max RK4 substeps. */
+int dlra_init(const dlra_grid *grid, const dlra_materials *mat, int n_beams,
+              const dlra_beam *beams, const dlra_options *opt, void *workspace,
+              size_t workspace_bytes, void *stream, dlra_ctx **out);
 
-/* Ray tracer for the uncollided flux (Sec. 3.2): for every cell within
- * beam_cut_sigmas of the beam axis marches a DG-in-energy / Crank-Nicolson
- * ray from the domain entry to the cell centre and stores the step-averaged
- * uncollided flux of every energy step and the uncollided deposited energy.
- * Must precede the first dlra_step. */
+/* Ray tracer for the uncollided flux (Sec. 3.2): for every beam and every
+ * cell within beam_cut_sigmas of the beam axis marches a DG-in-energy /
+ * Crank-Nicolson ray from the domain entry to the cell centre and stores the
+ * step-averaged uncollided flux of every energy step (times the beam weight)
+ * and the weighted uncollided deposited energy.  Must precede the first
+ * dlra_step (or be replaced by dlra_set_uncollided). */
 int uncollided_raytrace(dlra_ctx *ctx);
 
 /* One energy (pseudo-time) step k -> k+1 of the collided flux (Sec. 3.3.3):
@@ -157,9 +194,18 @@ int uncollided_raytrace(dlra_ctx *ctx);
  *             DLRA_E_NUMERIC / DLRA_E_RANK raised by the step's kernels. */
 int dlra_step(dlra_ctx *ctx, int *rank_out);
 
-/* Deposited energy into the caller's device buffer dose[n_cells] (FP64):
- *   flags bit 0  add the uncollided part, bit 1  add the collided part,
- *   bit 2  divide by the local density (dose per mass).  dose is overwritten. */
+/* Deposited energy of the context's (weighted) beams into the caller's device
+ * buffer dose[n_cells] (FP64).  The paper states the quantity (deposited
+ * energy, Sec. 4) but not its formula; the library takes the energy lost by
+ * the collided flux, int int psi~ dOmega dE over each energy step by the
+ * right-endpoint rule, sqrt(4 pi) sum_k dt_k u_0^{k+1}(x) (m_0^0 = 1/sqrt(4 pi)),
+ * plus that of the uncollided flux, int S(x, E) psi_u(E, x) dE.
+ *   flags bit 0  the uncollided part, bit 1  the collided part,
+ *   bit 2  divide by the local density (dose per mass, 0 where it is 0),
+ *   bit 3  add into dose instead of overwriting it (summing the separately
+ *          solved beams of a plan).
+ * Synchronises the stream first and returns DLRA_E_NUMERIC / DLRA_E_RANK if
+ * a kernel raised an error flag (then nothing is written). */
 int dose_deposit(dlra_ctx *ctx, double *dose, int flags);
 
 /* Test and checkpoint access (host buffers, FP64, synchronous).
@@ -173,13 +219,37 @@ int dlra_set_state(dlra_ctx *ctx, const double *U, const double *S, const double
                    int rank, int step);
 
 /* Uncollided tables after uncollided_raytrace, host FP64:
- *   psibar [n_steps][n_cells] step-averaged uncollided flux, Du [n_cells]. */
+ *   psibar [n_beams][n_steps][n_cells] step-averaged uncollided flux (times
+ *   the beam weight), Du [n_cells] the weighted uncollided deposited energy;
+ *   either may be NULL. */
 int dlra_get_uncollided(dlra_ctx *ctx, double *psibar, double *Du);
+
+/* Test access: overwrite the uncollided table of one beam and energy step
+ * with host FP64 psibar[n_cells] (NULL: leave it), and the uncollided
+ * deposited energy with Du[n_cells] (NULL: leave it).  Marks the context as
+ * traced (tables never set read as zero).  Synchronous. */
+int dlra_set_uncollided(dlra_ctx *ctx, int beam, int step, const double *psibar,
+                        const double *Du);
+
+/* Checkpoint of the collided state (rank, step, U, S, V, collided dose) as a
+ * byte buffer in host memory.  dlra_save with buf == NULL stores the size
+ * needed in *bytes; otherwise *bytes is the buffer's size on input and the
+ * bytes written on output (DLRA_E_INVALID if too small).  dlra_load restores
+ * a buffer written by dlra_save of a context with the same grid, moments,
+ * rank bound, precision, beam count and step count (DLRA_E_INVALID
+ * otherwise); the uncollided tables are not part of it.  A run resumed from a
+ * checkpoint reproduces the uninterrupted run bitwise.  Both synchronise the
+ * stream; dlra_save first reports pending error flags like dlra_sync. */
+int dlra_save(dlra_ctx *ctx, void *buf, size_t *bytes);
+int dlra_load(dlra_ctx *ctx, const void *buf, size_t bytes);
 
 /* Number of RK4 substeps of energy step k (host-side, from dlra_init). */
 int dlra_substeps(dlra_ctx *ctx, int k, int *n_sub);
 
-/* Waits for the context's stream. */
+/* Waits for the context's stream, then reports errors raised by its kernels
+ * since the last report: DLRA_E_NUMERIC (a non-finite value in the low-rank
+ * state, or a non-positive stopping power), DLRA_E_RANK (basis completion
+ * failed).  The flags are cleared once reported. */
 int dlra_sync(dlra_ctx *ctx);
 
 /* Batched beams.  The paper treats one pencil beam per solve; a treatment

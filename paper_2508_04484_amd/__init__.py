@@ -4,5 +4,5 @@ The compute path is the HIP library libdlra.so (C ABI in include/dlra.h);
 `binding` marshals arguments to it, with PyTorch supplying device memory and
 the stream.  Build the library with `python -m paper_2508_04484_amd.build`.
 """
-from .binding import (BeamSolver, DlraError, batch_solvers, load, run_batch, solve,  # noqa: F401
-                      workspace_size)
+from .binding import (BeamSolver, DlraError, Solver, batch_solvers, load, run_batch,  # noqa: F401
+                      solve, workspace_size)

@@ -19,10 +19,13 @@ ERRORS = {-1: "DLRA_E_INVALID", -2: "DLRA_E_NOMEM", -3: "DLRA_E_HIP", -4: "DLRA_
           -5: "DLRA_E_CFL", -6: "DLRA_E_RANK", -7: "DLRA_E_STATE"}
 RANK_FIXED, RANK_ADAPTIVE = 0, 1
 FP64, MIXED = 0, 1
-DOSE_UNCOLLIDED, DOSE_COLLIDED, DOSE_PER_MASS = 1, 2, 4
+COLLISION = {"boltzmann": 0, "fokker_planck": 1}
+EGRID = {"uniform": 0, "proportional": 1, "cfl": 2, "user": 3}
+DOSE_UNCOLLIDED, DOSE_COLLIDED, DOSE_PER_MASS, DOSE_ACCUMULATE = 1, 2, 4, 8
 
 EXPORTS = ["dlra_workspace_size", "dlra_init", "uncollided_raytrace", "dlra_step",
            "dose_deposit", "dlra_get_state", "dlra_set_state", "dlra_get_uncollided",
+           "dlra_set_uncollided", "dlra_save", "dlra_load",
            "dlra_substeps", "dlra_sync", "dlra_profile", "dlra_profile_read", "dlra_run_batch",
            "dlra_plan_objective", "dlra_plan_objective_work", "dlra_destroy", "dlra_last_error"]
 PHASES = ["kstage", "projection", "lstep", "augment", "sstep", "truncate", "collided", "source",
@@ -60,7 +63,8 @@ class Options(C.Structure):
                 ("trunc_tol", C.c_double), ("aug_tol", C.c_double),
                 ("floor_tol", C.c_double), ("fill_tol", C.c_double),
                 ("nu_max", C.c_double), ("ray_h_max", C.c_double),
-                ("beam_cut_sigmas", C.c_double)]
+                ("beam_cut_sigmas", C.c_double), ("collision", C.c_int), ("egrid", C.c_int),
+                ("egrid_points", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -76,9 +80,9 @@ def load(path: str = LIB_PATH):
                            "`python -m paper_2508_04484_amd.build` (no CPU fallback exists)")
     lib = C.CDLL(path)
     P, I, D, V = C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_void_p
-    lib.dlra_workspace_size.argtypes = [C.POINTER(Grid), I, C.POINTER(Options),
+    lib.dlra_workspace_size.argtypes = [C.POINTER(Grid), I, I, C.POINTER(Options),
                                         C.POINTER(C.c_size_t)]
-    lib.dlra_init.argtypes = [C.POINTER(Grid), C.POINTER(Materials), C.POINTER(Beam),
+    lib.dlra_init.argtypes = [C.POINTER(Grid), C.POINTER(Materials), I, C.POINTER(Beam),
                               C.POINTER(Options), V, C.c_size_t, V, C.POINTER(P)]
     lib.uncollided_raytrace.argtypes = [P]
     lib.dlra_step.argtypes = [P, C.POINTER(I)]
@@ -86,6 +90,9 @@ def load(path: str = LIB_PATH):
     lib.dlra_get_state.argtypes = [P, D, D, D, C.POINTER(I), C.POINTER(I)]
     lib.dlra_set_state.argtypes = [P, D, D, D, I, I]
     lib.dlra_get_uncollided.argtypes = [P, D, D]
+    lib.dlra_set_uncollided.argtypes = [P, I, I, D, D]
+    lib.dlra_save.argtypes = [P, V, C.POINTER(C.c_size_t)]
+    lib.dlra_load.argtypes = [P, V, C.c_size_t]
     lib.dlra_substeps.argtypes = [P, I, C.POINTER(I)]
     lib.dlra_sync.argtypes = [P]
     lib.dlra_profile.argtypes = [P, I]
@@ -117,57 +124,73 @@ def make_grid(g) -> Grid:
     return Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz)
 
 
-def make_options(o) -> Options:
-    return Options(o.pn_degree, o.n_steps,
+def make_options(o):
+    """(Options, keep-alive) for a workloads Options; the second item holds the
+    user energy grid the struct points to."""
+    pts = np.ascontiguousarray(getattr(o, "egrid_points", ()) or (), dtype=np.float64)
+    egrid = EGRID[getattr(o, "egrid", "uniform")]
+    opts = Options(o.pn_degree, o.n_steps,
                    RANK_FIXED if o.rank_mode == "fixed" else RANK_ADAPTIVE,
                    o.r, o.r_min, o.r_max, FP64 if o.precision == "fp64" else MIXED,
                    o.n_groups, getattr(o, "n_sub_max", 0), o.e_cut, o.e_max_sigmas,
                    o.trunc_tol, o.aug_tol, o.floor_tol, o.fill_tol, o.nu_max, o.ray_h_max,
-                   o.beam_cut_sigmas)
+                   o.beam_cut_sigmas, COLLISION[getattr(o, "collision", "boltzmann")], egrid,
+                   _dptr(pts) if pts.size else None)
+    return opts, pts
 
 
-def make_beam(b) -> Beam:
-    return Beam(b.E0, b.sigma_E, b.spot_sigma, b.weight, (C.c_double * 3)(*b.pos),
-                (C.c_double * 3)(*b.dir))
+def make_beam(b, weight=None) -> Beam:
+    return Beam(b.E0, b.sigma_E, b.spot_sigma, b.weight if weight is None else weight,
+                (C.c_double * 3)(*b.pos), (C.c_double * 3)(*b.dir))
 
 
-def workspace_size(problem) -> int:
+def workspace_size(problem, n_beams: int = 1) -> int:
     lib = load()
     out = C.c_size_t(0)
+    opts, _keep = make_options(problem.options)
     check(lib.dlra_workspace_size(C.byref(make_grid(problem.grid)), problem.materials.n_mat,
-                                  C.byref(make_options(problem.options)), C.byref(out)))
+                                  int(n_beams), C.byref(opts), C.byref(out)))
     return int(out.value)
 
 
-class BeamSolver:
-    """One pencil beam of a problem on the current CUDA (HIP) device.
+class Solver:
+    """A context of the library on the current CUDA (HIP) device: one beam of a
+    problem, or several beams in one joint collided solve.
 
-    Usage: s = BeamSolver(problem, b); s.raytrace(); s.run(); dose = s.dose()."""
+      beams        indices into problem.beams (default: all of them)
+      unit_weight  solve at unit beam weight (the single-beam dose) instead of
+                   the beams' own weights
 
-    def __init__(self, problem, beam_index: int = 0, stream=None):
+    Usage: s = Solver(problem); s.raytrace(); s.run(); dose = s.dose()."""
+
+    def __init__(self, problem, beams=None, unit_weight=False, stream=None):
         import torch
         if not torch.cuda.is_available():
-            raise RuntimeError("BeamSolver needs a GPU (torch.cuda.is_available() is False)")
+            raise RuntimeError("the DLRA library needs a GPU (torch.cuda.is_available() is False)")
         self.lib = load()
         self.problem = problem
-        self.beam = problem.beams[beam_index]
+        idx = list(range(len(problem.beams))) if beams is None else list(beams)
+        self.beams = [problem.beams[b] for b in idx]
+        self.n_beams = len(self.beams)
         self.torch = torch
-        size = workspace_size(problem)
+        size = workspace_size(problem, self.n_beams)
         self._ws = torch.empty(size + 256, dtype=torch.uint8, device="cuda")
         base = self._ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ws.record_stream(self.stream)
         mat = problem.materials
         self._arrays = [np.ascontiguousarray(a, dtype=np.float64)
                         for a in (mat.w, mat.e, mat.S, mat.T, mat.dG)]
         w, e, S, T, dG = self._arrays
         m = Materials(mat.n_mat, e.size, dG.shape[-1], _dptr(w), _dptr(e), _dptr(S), _dptr(T),
                       _dptr(dG))
+        barr = (Beam * self.n_beams)(*[make_beam(b, 1.0 if unit_weight else None)
+                                       for b in self.beams])
+        opts, _keep = make_options(problem.options)
         ctx = C.c_void_p(0)
-        check(self.lib.dlra_init(C.byref(make_grid(problem.grid)), C.byref(m),
-                                 C.byref(make_beam(self.beam)),
-                                 C.byref(make_options(problem.options)),
-                                 C.c_void_p(self._ws_ptr), C.c_size_t(size),
+        check(self.lib.dlra_init(C.byref(make_grid(problem.grid)), C.byref(m), self.n_beams,
+                                 barr, C.byref(opts), C.c_void_p(self._ws_ptr), C.c_size_t(size),
                                  C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
         self.ctx = ctx
         self.n = problem.grid.n
@@ -175,8 +198,13 @@ class BeamSolver:
 
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
+            # the library syncs its streams before releasing the context; the
+            # workspace goes back to torch only after that
+            rc = self.lib.dlra_sync(self.ctx)
             self.lib.dlra_destroy(self.ctx)
             self.ctx = None
+            self.stream.synchronize()
+            check(rc)
 
     def __del__(self):
         try:
@@ -204,8 +232,11 @@ class BeamSolver:
     def sync(self):
         check(self.lib.dlra_sync(self.ctx))
 
-    def dose(self, flags=DOSE_UNCOLLIDED | DOSE_COLLIDED):
-        out = self.torch.empty(self.n, dtype=self.torch.float64, device="cuda")
+    def dose(self, flags=DOSE_UNCOLLIDED | DOSE_COLLIDED, out=None):
+        """Deposited energy (torch float64 on the GPU); with out given and
+        flags containing DOSE_ACCUMULATE it is added into out."""
+        if out is None:
+            out = self.torch.empty(self.n, dtype=self.torch.float64, device="cuda")
         check(self.lib.dose_deposit(self.ctx, C.c_void_p(out.data_ptr()), flags))
         self.sync()
         return out
@@ -246,14 +277,43 @@ class BeamSolver:
         check(self.lib.dlra_set_state(self.ctx, _dptr(U), _dptr(S), _dptr(V), U.shape[1], step))
 
     def uncollided(self):
-        ps = np.zeros((self.problem.options.n_steps, self.n))
+        """(psibar, Du): psibar [n_steps, n] for one beam, [n_beams, n_steps, n]
+        for several."""
+        ps = np.zeros((self.n_beams, self.problem.options.n_steps, self.n))
         Du = np.zeros(self.n)
         check(self.lib.dlra_get_uncollided(self.ctx, _dptr(ps), _dptr(Du)))
-        return ps, Du
+        return (ps[0] if self.n_beams == 1 else ps), Du
+
+    def set_uncollided(self, beam, step, psibar=None, Du=None):
+        ps = None if psibar is None else np.ascontiguousarray(psibar, dtype=np.float64)
+        du = None if Du is None else np.ascontiguousarray(Du, dtype=np.float64)
+        check(self.lib.dlra_set_uncollided(self.ctx, int(beam), int(step),
+                                           None if ps is None else _dptr(ps),
+                                           None if du is None else _dptr(du)))
+
+    def save(self) -> bytes:
+        """Checkpoint of the collided state as bytes (dlra_save)."""
+        need = C.c_size_t(0)
+        check(self.lib.dlra_save(self.ctx, None, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        check(self.lib.dlra_save(self.ctx, buf, C.byref(need)))
+        return buf.raw[:need.value]
+
+    def load(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        check(self.lib.dlra_load(self.ctx, buf, len(data)))
+
+
+class BeamSolver(Solver):
+    """One pencil beam of a problem at unit weight (the single-beam solve)."""
+
+    def __init__(self, problem, beam_index: int = 0, stream=None):
+        super().__init__(problem, [beam_index], unit_weight=True, stream=stream)
+        self.beam = self.beams[0]
 
 
 def run_batch(solvers, n_steps=None, n_threads=0):
-    """Advance several BeamSolvers (each on its own stream) together through the
+    """Advance several solvers (each on its own stream) together through the
     library's batch scheduler: ray traces first where missing, then n_steps
     energy steps (default: all), concurrently; returns when all are done."""
     if not solvers:
@@ -301,14 +361,24 @@ def plan_objective(doses, weights, target, dhat, lam, stream=None):
     return J.value, grad
 
 
-def solve(problem, n_steps=None):
-    """Deposited energy of all beams (weighted sum), torch float64 on the GPU."""
-    total = None
-    for b in range(len(problem.beams)):
-        s = BeamSolver(problem, b)
+def solve(problem, n_steps=None, joint=False):
+    """Deposited energy of all beams of a problem at their weights (torch
+    float64 on the GPU): one joint collided solve (joint=True), or every beam
+    solved on its own and its weighted dose added into one buffer by the
+    library (dose_deposit with DOSE_ACCUMULATE)."""
+    import torch
+    if joint:
+        s = Solver(problem)
         s.raytrace()
         s.run(n_steps)
-        d = s.dose() * problem.beams[b].weight
-        total = d if total is None else total + d
+        d = s.dose()
+        s.close()
+        return d
+    total = torch.zeros(problem.grid.n, dtype=torch.float64, device="cuda")
+    for b in range(len(problem.beams)):
+        s = Solver(problem, [b])
+        s.raytrace()
+        s.run(n_steps)
+        s.dose(DOSE_UNCOLLIDED | DOSE_COLLIDED | DOSE_ACCUMULATE, out=total)
         s.close()
     return total

@@ -55,20 +55,25 @@ struct Plan {
     return off;
   }
   // offsets
-  size_t w_t, w_d, s, tall[4], psibar, dose_c, dose_u, Apm, AV, stepS, stepA, stepG, minstop;
+  size_t w_t, w_d, s, tall[4], psibar, dose_c, dose_u, Apm, AV, stepS, stepA, stepG, minstop,
+      egrid_s, egrid_min;
   size_t S, V, Vn, Bm, Bpk, Cm, Sh, Pp, Qp, Sp, G1, G2, Wg, T1, T2, Lm, L0, La, Lb, Mi, H, Cg, dc,
       tmp, work, partial, ctl;
-  size_t rt_diag, rt_up, rt_lo, rt_mass, rt_c0, rt_g0, rt_sw, rt_stopw, rt_rows, rt_f,
+  size_t rt_diag, rt_up, rt_lo, rt_mass, rt_c0, rt_g0, rt_sw, rt_stopw, rt_rays, rt_f,
       rt_scratch;
   size_t partial_elems = 0;
 };
 
 struct Dims {
-  int n, dim, ndk, N, m, n_mat, R, P, ld, n_steps, G, ng_step, max_rows;
+  int n, dim, ndk, N, m, n_mat, n_beams, n_src, R, P, ld, n_steps, G, ray_batch;
   size_t tsize;
 };
 
-bool make_dims(const dlra_grid *g, int n_mat, const dlra_options *o, Dims &d, std::string &err) {
+constexpr int kCflIntervals = 4096;   // trapezoid intervals of the CFL energy grid
+constexpr int kRayBatch = 32768;      // rays per ray-tracer launch
+
+bool make_dims(const dlra_grid *g, int n_mat, int n_beams, const dlra_options *o, Dims &d,
+               std::string &err) {
   if (!g || !o) {
     err = "null grid or options";
     return false;
@@ -78,7 +83,19 @@ bool make_dims(const dlra_grid *g, int n_mat, const dlra_options *o, Dims &d, st
     return false;
   }
   if (n_mat < 1 || n_mat > kMaxMat) {
-    err = "n_mat must be in [1, 8]";
+    err = "n_mat must be in [1, 16]";
+    return false;
+  }
+  if (n_beams < 1 || n_beams > kMaxBeams || n_mat * n_beams > kMaxSrc) {
+    err = "n_beams must be in [1, 64] with n_mat * n_beams <= 64";
+    return false;
+  }
+  if (o && (o->collision != DLRA_BOLTZMANN && o->collision != DLRA_FOKKER_PLANCK)) {
+    err = "collision must be DLRA_BOLTZMANN or DLRA_FOKKER_PLANCK";
+    return false;
+  }
+  if (o && (o->egrid < DLRA_EGRID_UNIFORM || o->egrid > DLRA_EGRID_USER)) {
+    err = "egrid must be one of DLRA_EGRID_*";
     return false;
   }
   if (o->pn_degree < 0 || o->pn_degree > 40) {
@@ -122,15 +139,16 @@ bool make_dims(const dlra_grid *g, int n_mat, const dlra_options *o, Dims &d, st
   d.dim = g->nz == 1 ? 2 : 3;
   d.ndk = 2 * d.dim;
   d.n_mat = n_mat;
+  d.n_beams = n_beams;
+  d.n_src = n_mat * n_beams;
   d.P = 2 * d.R;
   d.ld = (d.n + 63) / 64 * 64;
   d.n_steps = o->n_steps;
   d.G = o->n_groups;
   d.tsize = o->precision == DLRA_FP64 ? 8 : 4;
-  // step windows: a step spans at most dt/h_E + 2 groups; dt/h_E = G / n_steps
-  d.ng_step = std::min(d.G, d.G / d.n_steps + 3);
-  int mn = d.dim == 2 ? std::min(g->nx, g->ny) : std::min(g->nx, std::min(g->ny, g->nz));
-  d.max_rows = d.n / mn;
+  // rays traced together: rows of an axis-aligned beam, or target cells of an
+  // oblique one, in batches that bound the per-ray scratch
+  d.ray_batch = std::min(d.n, kRayBatch);
   return true;
 }
 
@@ -141,15 +159,17 @@ Plan make_plan(const Dims &d) {
   p.w_d = p.take(d.n_mat * n * 8);
   p.s = p.take(n * T);
   for (int i = 0; i < 4; ++i) p.tall[i] = p.take(ld * P * T);
-  p.psibar = p.take(size_t(d.n_steps) * n * T);
+  p.psibar = p.take(size_t(d.n_beams) * d.n_steps * n * T);
   p.dose_c = p.take(n * 8);
   p.dose_u = p.take(n * 8);
   p.Apm = p.take(d.ndk * m * m * 8);
   p.AV = p.take(d.ndk * m * P * 8);
   p.stepS = p.take(size_t(d.n_steps) * d.n_mat * 8);
   p.stepA = p.take(size_t(d.n_steps) * d.n_mat * (d.N + 1) * 8);
-  p.stepG = p.take(size_t(d.n_steps) * m * d.n_mat * 8);
+  p.stepG = p.take(size_t(d.n_steps) * m * d.n_src * 8);
   p.minstop = p.take(size_t(d.n_steps) * 8);
+  p.egrid_s = p.take(size_t(kCflIntervals + 1) * d.n_mat * 8);
+  p.egrid_min = p.take(size_t(kCflIntervals + 1) * 8);
   p.S = p.take(R * R * 8);
   p.V = p.take(m * P * 8);
   p.Vn = p.take(m * P * 8);
@@ -170,15 +190,15 @@ Plan make_plan(const Dims &d) {
   p.La = p.take(m * P * 8);
   p.Lb = p.take(m * P * 8);
   p.Mi = p.take(d.n_mat * R * R * 8);
-  p.H = p.take(P * kMaxMat * 8);
-  p.Cg = p.take(P * kMaxMat * 8);
+  p.H = p.take(P * kMaxSrc * 8);
+  p.Cg = p.take(P * kMaxSrc * 8);
   p.dc = p.take(P * 8);
   p.tmp = p.take(P * 8);
   p.work = p.take((4 * P * P + 3 * m * P + 4 * P + 64) * 8);
   size_t ntile = (n + 31) / 32;
   size_t nb = std::min<size_t>(kPartialBlocks, ntile);
   // partial blocks, their sum and up to 64 segment sums of the reduction
-  p.partial_elems = (nb + 1 + 64) * std::max<size_t>(d.ndk * P * P, 64);
+  p.partial_elems = (nb + 1 + 64) * std::max<size_t>({d.ndk * P * P, P * kMaxSrc, 64});
   p.partial = p.take(p.partial_elems * 8);
   p.ctl = p.take(sizeof(Ctl));
   const size_t G = d.G;
@@ -186,13 +206,13 @@ Plan make_plan(const Dims &d) {
   p.rt_up = p.take(d.n_mat * G * 9 * 8);
   p.rt_lo = p.take(d.n_mat * G * 9 * 8);
   p.rt_mass = p.take(3 * 8);
-  p.rt_c0 = p.take(3 * G * 8);
+  p.rt_c0 = p.take(size_t(d.n_beams) * 3 * G * 8);
   p.rt_g0 = p.take(size_t(d.n_steps) * 4);
-  p.rt_sw = p.take(size_t(d.n_steps) * d.ng_step * 3 * 8);
+  p.rt_sw = p.take(size_t(d.n_steps) * G * 3 * 8);
   p.rt_stopw = p.take(d.n_mat * 3 * G * 8);
-  p.rt_rows = p.take(size_t(d.max_rows) * 4);
-  p.rt_f = p.take(size_t(d.max_rows) * 8);
-  p.rt_scratch = p.take(size_t(24) * G * d.max_rows * 8);
+  p.rt_rays = p.take(size_t(d.n_beams) * n * 4);
+  p.rt_f = p.take(size_t(d.n_beams) * n * 8);
+  p.rt_scratch = p.take(size_t(kRayScratchPerGroup) * G * d.ray_batch * 8);
   return p;
 }
 
@@ -204,7 +224,7 @@ struct dlra_ctx {
   Plan plan;
   dlra_grid grid;
   dlra_options opt;
-  dlra_beam beam;
+  std::vector<dlra_beam> beams;
   GridDev gdev;
   hipStream_t st = nullptr;
   hipStream_t st2 = nullptr;            // side stream of the L-step (default priority)
@@ -215,13 +235,14 @@ struct dlra_ctx {
   int r = 0;
   int step = 0;
   bool traced = false;
-  double e_max = 0, dt = 0;
+  double e_max = 0, e_cut = 0;
+  std::vector<double> edges;   // E_0 = E_max > ... > E_n = E_cut
+  std::vector<double> dtk;     // dt_k = E_k - E_{k+1}
   std::vector<int> n_sub;
-  std::vector<double> w_host;
   TruncOpt topt;
-  // ray rows
-  RayParams rp{};
-  int n_rows = 0;
+  // rays of every beam
+  std::vector<RayParams> rps;
+  std::vector<RayGeom> rgeo;
   // rotating tall buffers: 0 = Uhat, 1 = K, 2 = Wa, 3 = Wb
   void *tall[4];
   double *V, *Vn;
@@ -366,11 +387,97 @@ std::vector<double> initial_angular_basis(const std::vector<double> &g0, int m, 
   return Q;
 }
 
+// Energy edges E_0 = E_max > ... > E_n = E_cut of the context's grid mode.
+// The CFL grid needs S_min(E) = min_x sum_i w_i S_i(E) on kCflIntervals + 1
+// energies, taken on the device.
+void energy_edges(dlra_ctx *c, const dlra_materials *mat) {
+  const Dims &d = c->d;
+  const Plan &p = c->plan;
+  const int n = d.n_steps;
+  std::vector<double> &E = c->edges;
+  E.assign(n + 1, 0.0);
+  const double e_max = c->e_max, e_cut = c->e_cut;
+  switch (c->opt.egrid) {
+    case DLRA_EGRID_UNIFORM: {
+      const double dt = (e_max - e_cut) / n;
+      for (int k = 0; k <= n; ++k) E[k] = e_max - k * dt;
+      break;
+    }
+    case DLRA_EGRID_PROPORTIONAL:
+      for (int k = 0; k <= n; ++k) E[k] = e_cut * std::pow(e_max / e_cut, 1.0 - double(k) / n);
+      break;
+    case DLRA_EGRID_CFL: {
+      const int K = kCflIntervals, nm = d.n_mat, ne = mat->n_e;
+      const double h = (e_max - e_cut) / K;
+      std::vector<double> x(K + 1), Sk(size_t(K + 1) * nm), smin(K + 1);
+      for (int j = 0; j <= K; ++j) {
+        x[j] = e_cut + h * j;
+        for (int i = 0; i < nm; ++i)
+          Sk[size_t(j) * nm + i] = interp(mat->e, mat->S + size_t(i) * ne, ne, x[j]);
+      }
+      upload(c, p.egrid_s, Sk.data(), Sk.size() * 8);
+      launch_min_stop(d.n, c->at<double>(p.w_d), nm, c->at<double>(p.egrid_s), K + 1,
+                      c->at<double>(p.egrid_min), c->st);
+      HIPCHK(hipMemcpyAsync(smin.data(), c->base + p.egrid_min, smin.size() * 8,
+                            hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipStreamSynchronize(c->st));
+      std::vector<double> R(K + 1, 0.0);
+      for (int j = 0; j < K; ++j) {
+        if (!(smin[j] > 0) || !(smin[j + 1] > 0))
+          throw std::invalid_argument("stopping power must be positive in every cell");
+        R[j + 1] = R[j] + 0.5 * h * (1.0 / smin[j] + 1.0 / smin[j + 1]);
+      }
+      // invert R by linear interpolation (R ascends)
+      for (int k = 0; k <= n; ++k) {
+        const double t = R[K] * (1.0 - double(k) / n);
+        int j = int(std::upper_bound(R.begin(), R.end(), t) - R.begin()) - 1;
+        if (j >= K) {
+          E[k] = x[K];
+          continue;
+        }
+        j = std::max(j, 0);
+        const double slope = (x[j + 1] - x[j]) / (R[j + 1] - R[j]);
+        E[k] = x[j] + slope * (t - R[j]);
+      }
+      break;
+    }
+    default:
+      for (int k = 0; k <= n; ++k) E[k] = c->opt.egrid_points[k];
+  }
+  if (c->opt.egrid != DLRA_EGRID_USER) {
+    E[0] = e_max;
+    E[n] = e_cut;
+  }
+  c->dtk.resize(n);
+  for (int k = 0; k < n; ++k) c->dtk[k] = E[k] - E[k + 1];
+}
+
+// Per-step collision coefficients from the table differences dg[l] = G_0 - G_l
+// at the step midpoint: self-scattering a_l and in-scattering factors gt_l
+// (l = 0..N) and the removal rate of the uncollided flux.
+//   Boltzmann with the extended transport correction (Sec. 3.3.1):
+//     a_l = G_l - G_0, gt_l = G_l - G_{N+1}, removal G_0 - G_{N+1};
+//   Fokker-Planck (Sec. 2.1, Sec. 3.1): a_l = gt_l = -xi_1 l (l+1) / 2 with
+//     xi_1 = G_0 - G_1, no removal.
+void collision_coeffs(int model, int N, const double *dg, double *a, double *gt) {
+  if (model == DLRA_FOKKER_PLANCK) {
+    for (int l = 0; l <= N; ++l) {
+      a[l] = -0.5 * dg[1] * double(l) * double(l + 1);
+      gt[l] = a[l];
+    }
+    return;
+  }
+  for (int l = 0; l <= N; ++l) {
+    a[l] = -dg[l];
+    gt[l] = dg[N + 1] - dg[l];
+  }
+}
+
 template <typename T>
 int init_impl(dlra_ctx *c, const dlra_materials *mat) {
   const Dims &d = c->d;
   const Plan &p = c->plan;
-  const int n = d.n, m = d.m, N = d.N, nm = d.n_mat;
+  const int n = d.n, m = d.m, N = d.N, nm = d.n_mat, nb = d.n_beams, ns_ = d.n_src;
   HIPCHK(hipMemsetAsync(c->base, 0, p.bytes, c->st));
   // ---- angular algebra
   std::vector<double> A[3];
@@ -384,36 +491,8 @@ int init_impl(dlra_ctx *c, const dlra_materials *mat) {
     std::copy(Am.begin(), Am.end(), Apm.begin() + size_t(2 * dd + 1) * m * m);
   }
   upload(c, p.Apm, Apm.data(), Apm.size() * 8);
-  std::vector<double> TM(m);
-  beam_moments(N, c->beam.dir, TM.data());
-  // ---- energy grid and per-step coefficients at E_{k+1/2}
-  c->e_max = c->beam.E0 + c->opt.e_max_sigmas * c->beam.sigma_E;
-  c->dt = (c->e_max - c->opt.e_cut) / d.n_steps;
-  std::vector<double> stepS(size_t(d.n_steps) * nm), stepA(size_t(d.n_steps) * nm * (N + 1)),
-      stepG(size_t(d.n_steps) * m * nm);
-  const int ne = mat->n_e, nl = mat->n_leg;
-  for (int k = 0; k < d.n_steps; ++k) {
-    const double E = c->e_max - (k + 0.5) * c->dt;
-    for (int i = 0; i < nm; ++i) {
-      stepS[size_t(k) * nm + i] = interp(mat->e, mat->S + size_t(i) * ne, ne, E);
-      std::vector<double> dg(N + 2), col(ne);
-      for (int l = 0; l < N + 2; ++l) {
-        for (int e = 0; e < ne; ++e) col[e] = mat->dG[(size_t(i) * ne + e) * nl + l];
-        dg[l] = interp(mat->e, col.data(), ne, E);
-      }
-      for (int l = 0; l <= N; ++l) stepA[(size_t(k) * nm + i) * (N + 1) + l] = -dg[l];
-      for (int l = 0; l <= N; ++l) {
-        double gt = dg[N + 1] - dg[l];
-        for (int kk = -l; kk <= l; ++kk) {
-          int pidx = l * l + l + kk;
-          stepG[(size_t(k) * nm + i) * m + pidx] = gt * TM[pidx];
-        }
-      }
-    }
-  }
-  upload(c, p.stepS, stepS.data(), stepS.size() * 8);
-  upload(c, p.stepA, stepA.data(), stepA.size() * 8);
-  upload(c, p.stepG, stepG.data(), stepG.size() * 8);
+  std::vector<double> TM(size_t(nb) * m);
+  for (int b = 0; b < nb; ++b) beam_moments(N, c->beams[b].dir, TM.data() + size_t(b) * m);
   // ---- materials
   upload(c, p.w_d, mat->w, size_t(nm) * n * 8);
   if (sizeof(T) == 8) {
@@ -421,6 +500,44 @@ int init_impl(dlra_ctx *c, const dlra_materials *mat) {
   } else {
     upload_cast<T>(c, p.w_t, mat->w, size_t(nm) * n);
   }
+  // ---- energy grid and per-step coefficients at the step midpoints
+  if (c->opt.egrid == DLRA_EGRID_USER) {
+    c->e_max = c->opt.egrid_points[0];
+    c->e_cut = c->opt.egrid_points[d.n_steps];
+  } else {
+    c->e_max = 0.0;
+    for (const dlra_beam &bm : c->beams)
+      c->e_max = std::max(c->e_max, bm.E0 + c->opt.e_max_sigmas * bm.sigma_E);
+    c->e_cut = c->opt.e_cut;
+  }
+  energy_edges(c, mat);
+  std::vector<double> stepS(size_t(d.n_steps) * nm), stepA(size_t(d.n_steps) * nm * (N + 1)),
+      stepG(size_t(d.n_steps) * m * ns_);
+  const int ne = mat->n_e, nl = mat->n_leg;
+  for (int k = 0; k < d.n_steps; ++k) {
+    const double E = 0.5 * (c->edges[k] + c->edges[k + 1]);
+    for (int i = 0; i < nm; ++i) {
+      stepS[size_t(k) * nm + i] = interp(mat->e, mat->S + size_t(i) * ne, ne, E);
+      std::vector<double> dg(N + 2), col(ne), a(N + 1), gt(N + 1);
+      for (int l = 0; l < N + 2; ++l) {
+        for (int e = 0; e < ne; ++e) col[e] = mat->dG[(size_t(i) * ne + e) * nl + l];
+        dg[l] = interp(mat->e, col.data(), ne, E);
+      }
+      collision_coeffs(c->opt.collision, N, dg.data(), a.data(), gt.data());
+      for (int l = 0; l <= N; ++l) stepA[(size_t(k) * nm + i) * (N + 1) + l] = a[l];
+      // source column b n_mat + i: g_{i,b} = gt_l(p) T_M,b
+      for (int b = 0; b < nb; ++b)
+        for (int l = 0; l <= N; ++l)
+          for (int kk = -l; kk <= l; ++kk) {
+            int pidx = l * l + l + kk;
+            stepG[(size_t(k) * ns_ + size_t(b) * nm + i) * m + pidx] =
+                gt[l] * TM[size_t(b) * m + pidx];
+          }
+    }
+  }
+  upload(c, p.stepS, stepS.data(), stepS.size() * 8);
+  upload(c, p.stepA, stepA.data(), stepA.size() * 8);
+  upload(c, p.stepG, stepG.data(), stepG.size() * 8);
   // ---- RK4 substeps: minimum stopping power per step
   launch_min_stop(n, c->at<double>(p.w_d), nm, c->at<double>(p.stepS), d.n_steps,
                   c->at<double>(p.minstop), c->st);
@@ -434,13 +551,14 @@ int init_impl(dlra_ctx *c, const dlra_materials *mat) {
   c->n_sub.resize(d.n_steps);
   for (int k = 0; k < d.n_steps; ++k) {
     if (!(minstop[k] > 0)) return fail(DLRA_E_INVALID, "stopping power must be positive in every cell");
-    int ns = std::max(1, int(std::ceil(c->dt / (nu * minstop[k] * hmin) - 1e-9)));
+    int ns = std::max(1, int(std::ceil(c->dtk[k] / (nu * minstop[k] * hmin) - 1e-9)));
     if (c->opt.n_sub_max > 0 && ns > c->opt.n_sub_max)
       return fail(DLRA_E_CFL, "energy step " + std::to_string(k) + " needs " +
                                   std::to_string(ns) + " RK4 substeps > n_sub_max");
     c->n_sub[k] = ns;
   }
-  // ---- initial state: S = 0, U unit vectors at floor((j+1/2) n / r), V from g_0
+  // ---- initial state: S = 0, U unit vectors at floor((j+1/2) n / r), V from
+  // the source directions of the first step
   const int r0 = c->opt.rank_mode == DLRA_RANK_FIXED ? c->opt.r : c->opt.r_min;
   c->r = r0;
   {
@@ -451,21 +569,22 @@ int init_impl(dlra_ctx *c, const dlra_materials *mat) {
                             hipMemcpyHostToDevice, c->st));
       HIPCHK(hipStreamSynchronize(c->st));
     }
-    std::vector<double> g0(stepG.begin(), stepG.begin() + size_t(m) * nm);
-    std::vector<double> V0 = initial_angular_basis(g0, m, nm, r0, c->opt.aug_tol, c->opt.fill_tol);
+    std::vector<double> g0(stepG.begin(), stepG.begin() + size_t(m) * ns_);
+    std::vector<double> V0 = initial_angular_basis(g0, m, ns_, r0, c->opt.aug_tol, c->opt.fill_tol);
     upload(c, p.V, V0.data(), V0.size() * 8);
   }
-  // ---- ray tracer tables
+  // ---- ray tracer tables (one DG grid on [E_cut, E_max] for all beams)
   {
     const int G = d.G;
     std::vector<double> diag(size_t(nm) * G * 9), up(size_t(nm) * G * 9), lo(size_t(nm) * G * 9);
     std::vector<double> stopw(size_t(nm) * 3 * G);
     EnergyOperator op;
     for (int i = 0; i < nm; ++i) {
-      std::vector<double> sig(ne), Si(mat->S + size_t(i) * ne, mat->S + size_t(i + 1) * ne),
+      std::vector<double> sig(ne, 0.0), Si(mat->S + size_t(i) * ne, mat->S + size_t(i + 1) * ne),
           Ti(mat->T + size_t(i) * ne, mat->T + size_t(i + 1) * ne);
-      for (int e = 0; e < ne; ++e) sig[e] = mat->dG[(size_t(i) * ne + e) * nl + N + 1];
-      energy_operator(c->opt.e_cut, c->e_max, G, mat->e, ne, Si.data(), Ti.data(), sig.data(), op);
+      if (c->opt.collision == DLRA_BOLTZMANN)
+        for (int e = 0; e < ne; ++e) sig[e] = mat->dG[(size_t(i) * ne + e) * nl + N + 1];
+      energy_operator(c->e_cut, c->e_max, G, mat->e, ne, Si.data(), Ti.data(), sig.data(), op);
       std::copy(op.diag.begin(), op.diag.end(), diag.begin() + size_t(i) * G * 9);
       std::copy(op.up.begin(), op.up.end(), up.begin() + size_t(i) * G * 9);
       std::copy(op.lo.begin(), op.lo.end(), lo.begin() + size_t(i) * G * 9);
@@ -477,76 +596,101 @@ int init_impl(dlra_ctx *c, const dlra_materials *mat) {
     upload(c, p.rt_stopw, stopw.data(), stopw.size() * 8);
     double mass[3] = {op.h, op.h / 3.0, op.h / 5.0};
     upload(c, p.rt_mass, mass, sizeof(mass));
-    std::vector<double> c0(3 * G);
-    project_gaussian(op, c->beam.E0, c->beam.sigma_E, c0.data());
+    std::vector<double> c0(size_t(nb) * 3 * G);
+    for (int b = 0; b < nb; ++b)
+      project_gaussian(op, c->beams[b].E0, c->beams[b].sigma_E, c0.data() + size_t(b) * 3 * G);
     upload(c, p.rt_c0, c0.data(), c0.size() * 8);
+    // step windows: a step of width dt overlaps at most dt/h_E + 2 groups
+    double dt_max = 0.0;
+    for (double v : c->dtk) dt_max = std::max(dt_max, v);
+    const int ng_step = std::min(G, int(std::ceil(dt_max / op.h - 1e-9)) + 3);
     std::vector<int> g0s(d.n_steps);
-    std::vector<double> sw(size_t(d.n_steps) * d.ng_step * 3);
+    std::vector<double> sw(size_t(d.n_steps) * ng_step * 3);
     for (int k = 0; k < d.n_steps; ++k) {
-      double hi = c->e_max - k * c->dt, lo_ = c->e_max - (k + 1) * c->dt;
-      g0s[k] = step_integral(op, lo_, hi, d.ng_step, sw.data() + size_t(k) * d.ng_step * 3);
-      for (int t = 0; t < d.ng_step * 3; ++t) sw[size_t(k) * d.ng_step * 3 + t] /= c->dt;
+      double hi = c->edges[k], lo_ = c->edges[k + 1];
+      g0s[k] = step_integral(op, lo_, hi, ng_step, sw.data() + size_t(k) * ng_step * 3);
+      for (int t = 0; t < ng_step * 3; ++t) sw[size_t(k) * ng_step * 3 + t] /= c->dtk[k];
     }
     upload(c, p.rt_g0, g0s.data(), g0s.size() * 4);
     upload(c, p.rt_sw, sw.data(), sw.size() * 8);
-    // rows along the beam axis
-    const double *dir = c->beam.dir;
-    int axis = -1, nnz = 0;
-    for (int a = 0; a < 3; ++a)
-      if (dir[a] != 0.0) {
-        axis = a;
-        ++nnz;
-      }
-    if (nnz != 1)
-      return fail(DLRA_E_INVALID, "the ray tracer supports beams along a grid axis");
-    if (d.dim == 2 && axis == 2) return fail(DLRA_E_INVALID, "2D problems need in-plane beams");
+    // rays of each beam: the grid rows of an axis-aligned beam, else one ray
+    // per target cell; cells beyond beam_cut_sigmas spot sigmas get none
+    c->rps.assign(nb, RayParams{});
+    c->rgeo.assign(nb, RayGeom{});
     const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
     const double D[3] = {c->grid.dx, c->grid.dy, c->grid.dz};
-    const int len = axis == 0 ? nx : (axis == 1 ? ny : nz);
-    const int stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
-    std::vector<int> starts;
-    std::vector<double> fs;
-    const double sgm = c->beam.spot_sigma, cut = c->opt.beam_cut_sigmas * sgm;
-    for (int k = 0; k < nz; ++k)
-      for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-          int ijk[3] = {i, j, k};
-          if (ijk[axis] != 0) continue;
-          double xc[3] = {(i + 0.5) * D[0], (j + 0.5) * D[1], d.dim == 3 ? (k + 0.5) * D[2] : 0.0};
-          double rel[3], dot = 0.0, nrm2 = 0.0;
-          for (int a = 0; a < 3; ++a) rel[a] = xc[a] - c->beam.pos[a];
-          double dn = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-          for (int a = 0; a < 3; ++a) dot += rel[a] * dir[a] / dn;
-          for (int a = 0; a < 3; ++a) {
-            double v = rel[a] - dot * dir[a] / dn;
-            nrm2 += v * v;
-          }
-          double dp = std::sqrt(nrm2);
-          if (dp > cut) continue;
-          double f = d.dim == 2 ? std::exp(-0.5 * dp * dp / (sgm * sgm)) / (std::sqrt(2.0 * kPi) * sgm)
-                                : std::exp(-0.5 * dp * dp / (sgm * sgm)) / (2.0 * kPi * sgm * sgm);
-          starts.push_back((k * ny + j) * nx + i);
-          fs.push_back(f);
+    for (int b = 0; b < nb; ++b) {
+      const dlra_beam &bm = c->beams[b];
+      const double *dir = bm.dir;
+      int axis = -1, nnz = 0;
+      for (int a = 0; a < 3; ++a)
+        if (dir[a] != 0.0) {
+          axis = a;
+          ++nnz;
         }
-    c->n_rows = int(starts.size());
-    if (c->n_rows > d.max_rows) return fail(DLRA_E_INVALID, "ray rows exceed the plan");
-    if (c->n_rows) {
-      upload(c, p.rt_rows, starts.data(), starts.size() * 4);
-      upload(c, p.rt_f, fs.data(), fs.size() * 8);
+      if (d.dim == 2 && dir[2] != 0.0) return fail(DLRA_E_INVALID, "2D problems need in-plane beams");
+      if (nnz != 1) axis = -1;
+      const double sgm = bm.spot_sigma, cut = c->opt.beam_cut_sigmas * sgm;
+      // lateral weight f_perp(d_perp) of a cell centre, times the beam weight
+      auto lateral = [&](int i, int j, int k, double &f) {
+        double xc[3] = {(i + 0.5) * D[0], (j + 0.5) * D[1], d.dim == 3 ? (k + 0.5) * D[2] : 0.0};
+        double rel[3], dot = 0.0, nrm2 = 0.0;
+        for (int a = 0; a < 3; ++a) rel[a] = xc[a] - bm.pos[a];
+        for (int a = 0; a < 3; ++a) dot += rel[a] * dir[a];
+        for (int a = 0; a < 3; ++a) {
+          double v = rel[a] - dot * dir[a];
+          nrm2 += v * v;
+        }
+        double dp = std::sqrt(nrm2);
+        if (dp > cut) return false;
+        f = bm.weight * (d.dim == 2 ? std::exp(-0.5 * dp * dp / (sgm * sgm)) / (std::sqrt(2.0 * kPi) * sgm)
+                                    : std::exp(-0.5 * dp * dp / (sgm * sgm)) / (2.0 * kPi * sgm * sgm));
+        return true;
+      };
+      std::vector<int> rays;
+      std::vector<double> fs;
+      for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+          for (int i = 0; i < nx; ++i) {
+            int ijk[3] = {i, j, k};
+            if (axis >= 0 && ijk[axis] != 0) continue;   // rows: their first cell
+            double f;
+            if (!lateral(i, j, k, f)) continue;
+            rays.push_back((k * ny + j) * nx + i);
+            fs.push_back(f);
+          }
+      const int n_rays = int(rays.size());
+      if (n_rays) {
+        upload(c, p.rt_rays + size_t(b) * n * 4, rays.data(), rays.size() * 4);
+        upload(c, p.rt_f + size_t(b) * n * 8, fs.data(), fs.size() * 8);
+      }
+      RayParams &rp = c->rps[b];
+      rp.G = G;
+      rp.n_mat = nm;
+      rp.n_steps = d.n_steps;
+      rp.ng_step = ng_step;
+      rp.n_rays = n_rays;
+      rp.n = n;
+      rp.axis = axis;
+      rp.h_max = c->opt.ray_h_max;
+      if (axis >= 0) {
+        rp.sign = dir[axis] > 0 ? 1 : -1;
+        rp.row_len = axis == 0 ? nx : (axis == 1 ? ny : nz);
+        rp.row_stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
+        rp.half = 0.5 * D[axis];
+        rp.n_half = std::max(1, int(std::ceil(rp.half / c->opt.ray_h_max - 1e-9)));
+      }
+      RayGeom &gm = c->rgeo[b];
+      gm.nx = nx;
+      gm.ny = ny;
+      gm.nz = nz;
+      gm.dim = d.dim;
+      for (int a = 0; a < 3; ++a) {
+        gm.D[a] = D[a];
+        gm.L[a] = (a == 0 ? nx : (a == 1 ? ny : nz)) * D[a];
+        gm.om[a] = dir[a];
+      }
     }
-    RayParams &rp = c->rp;
-    rp.G = G;
-    rp.n_mat = nm;
-    rp.n_steps = d.n_steps;
-    rp.ng_step = d.ng_step;
-    rp.axis = axis;
-    rp.sign = dir[axis] > 0 ? 1 : -1;
-    rp.n_rows = c->n_rows;
-    rp.row_len = len;
-    rp.row_stride = stride;
-    rp.n = n;
-    rp.half = 0.5 * D[axis];
-    rp.n_half = std::max(1, int(std::ceil(rp.half / c->opt.ray_h_max - 1e-9)));
   }
   HIPCHK(hipStreamSynchronize(c->st));
   return DLRA_OK;
@@ -628,7 +772,7 @@ struct Stepper {
       launch_small_gemm(0, 0, r1, 1, r1, 1.0, D(p.Sp), R, 0, D(p.tmp), P, 0, 0.0, D(p.dc), P, 0,
                         1, st);
       dcv = D(p.dc);
-      dscale = c->dt * std::sqrt(4.0 * kPi);
+      dscale = c->dtk[c->step] * std::sqrt(4.0 * kPi);
     }
     launch_update<T>(n, tall(0), ld, 2 * r, D(p.Pp), P, 1.0, nullptr, 0, 0.0, tall(2), ld, r1,
                      with_dose ? D(p.dose_c) : nullptr, dcv, dscale, st);
@@ -644,9 +788,10 @@ struct Stepper {
     const Plan &p = c->plan;
     const Dims &dd = d();
     const int n = dd.n, ld = dd.ld, P = dd.P, m = dd.m, R = dd.R, N = dd.N, nm = dd.n_mat;
+    const int nb = dd.n_beams, nsrc = dd.n_src;
     const int k = c->step;
     const int ns = c->n_sub[k];
-    const double dt = c->dt, h = dt / ns;
+    const double dt = c->dtk[k], h = dt / ns;
     hipStream_t st = c->st;
     Ctl *ctl = c->ctl();
     int r = c->r;
@@ -745,17 +890,19 @@ struct Stepper {
       std::swap(c->V, c->Vn);
     }
     // ---------------- uncollided in-scattering source (explicit Euler K, L, S)
+    // beam b's table of step k: psi + b * pstride
     const T *psi = c->at<T>(p.psibar) + size_t(k) * n;
-    const double *gk = D(p.stepG) + size_t(k) * m * nm;
+    const size_t pstride = size_t(dd.n_steps) * n;
+    const double *gk = D(p.stepG) + size_t(k) * m * nsrc;
     {
       PhaseTimer t(c, DLRA_PH_SOURCE);
-      launch_xt_source<T, Acc>(n, tall(0), ld, r, c->at<T>(p.w_t), nm, psi, D(p.H), P,
-                               D(p.partial), p.partial_elems, st);
-      launch_small_gemm(1, 0, r, nm, m, 1.0, c->V, m, 0, gk, m, 0, 0.0, D(p.Cg), P, 0, 1, st);
-      launch_source_k<T>(n, tall(0), ld, r, D(p.S), R, c->at<T>(p.w_t), nm, psi, D(p.Cg), P, dt,
-                         tall(1), st);
+      launch_xt_source<T, Acc>(n, tall(0), ld, r, c->at<T>(p.w_t), nm, nb, psi, pstride, D(p.H),
+                               P, D(p.partial), p.partial_elems, st);
+      launch_small_gemm(1, 0, r, nsrc, m, 1.0, c->V, m, 0, gk, m, 0, 0.0, D(p.Cg), P, 0, 1, st);
+      launch_source_k<T>(n, tall(0), ld, r, D(p.S), R, c->at<T>(p.w_t), nm, nb, psi, pstride,
+                         D(p.Cg), P, dt, tall(1), st);
       launch_small_gemm(0, 1, m, r, r, 1.0, c->V, m, 0, D(p.S), R, 0, 0.0, D(p.Lm), m, 0, 1, st);
-      launch_small_gemm(0, 1, m, r, nm, dt, gk, m, 0, D(p.H), P, 0, 1.0, D(p.Lm), m, 0, 1, st);
+      launch_small_gemm(0, 1, m, r, nsrc, dt, gk, m, 0, D(p.H), P, 0, 1.0, D(p.Lm), m, 0, 1, st);
     }
     // V-side augmentation on the side stream beside the U-side one
     HIPCHK(hipEventRecord(c->ev_fork, st));
@@ -772,12 +919,13 @@ struct Stepper {
     HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
     {
       PhaseTimer t(c, DLRA_PH_SOURCE);
-      launch_xt_source<T, Acc>(n, tall(0), ld, 2 * r, c->at<T>(p.w_t), nm, psi, D(p.H), P,
-                               D(p.partial), p.partial_elems, st);
-      launch_small_gemm(1, 0, 2 * r, nm, m, 1.0, c->V, m, 0, gk, m, 0, 0.0, D(p.Cg), P, 0, 1, st);
+      launch_xt_source<T, Acc>(n, tall(0), ld, 2 * r, c->at<T>(p.w_t), nm, nb, psi, pstride,
+                               D(p.H), P, D(p.partial), p.partial_elems, st);
+      launch_small_gemm(1, 0, 2 * r, nsrc, m, 1.0, c->V, m, 0, gk, m, 0, 0.0, D(p.Cg), P, 0, 1,
+                        st);
       launch_copy_block(r, r, D(p.S), R, D(p.Sh), P, P, P, 1.0, st);
-      launch_small_gemm(0, 1, 2 * r, 2 * r, nm, dt, D(p.H), P, 0, D(p.Cg), P, 0, 1.0, D(p.Sh), P,
-                        0, 1, st);
+      launch_small_gemm(0, 1, 2 * r, 2 * r, nsrc, dt, D(p.H), P, 0, D(p.Cg), P, 0, 1.0, D(p.Sh),
+                        P, 0, 1, st);
     }
     {
       PhaseTimer t(c, DLRA_PH_TRUNCATE);
@@ -789,14 +937,29 @@ struct Stepper {
   }
 };
 
+// Waits for the context's streams and reports (then clears) the error flags
+// its kernels raised.
 int sync_flags(dlra_ctx *c) {
   Ctl h;
+  HIPCHK(hipStreamSynchronize(c->st2));
   HIPCHK(hipMemcpyAsync(&h, c->ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
+  if (h.flags) {
+    const int zero = 0;
+    HIPCHK(hipMemcpyAsync(&c->ctl()->flags, &zero, sizeof(int), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+  }
   if (h.flags & kFlagNonFinite) return fail(DLRA_E_NUMERIC, "non-finite value in the low-rank state");
   if (h.flags & kFlagStop) return fail(DLRA_E_NUMERIC, "non-positive stopping power");
   if (h.flags & kFlagCompletion) return fail(DLRA_E_RANK, "basis completion failed");
+  if (h.flags) return fail(DLRA_E_NUMERIC, "error flag raised by a kernel");
   return DLRA_OK;
+}
+
+void clear_flags(dlra_ctx *c) {
+  const int zero = 0;
+  HIPCHK(hipMemcpyAsync(&c->ctl()->flags, &zero, sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
 }
 
 __global__ void k_dose_out(int n, int n_mat, const double *__restrict__ Du,
@@ -812,7 +975,8 @@ __global__ void k_dose_out(int n, int n_mat, const double *__restrict__ Du,
     for (int i = 0; i < n_mat; ++i) rho += w[size_t(i) * n + x];
     v = rho > 0.0 ? v / rho : 0.0;
   }
-  out[x] = v;
+  if (flags & 8) out[x] += v;
+  else out[x] = v;
 }
 
 template <typename T>
@@ -863,6 +1027,75 @@ int set_state_impl(dlra_ctx *c, const double *U, const double *S, const double *
     for (int j = 0; j < r; ++j) hv[p + size_t(j) * d.m] = V[size_t(p) * r + j];
   HIPCHK(hipMemcpy(c->V, hv.data(), hv.size() * 8, hipMemcpyHostToDevice));
   c->r = r;
+  clear_flags(c);
+  return DLRA_OK;
+}
+
+// ------------------------------------------------------------------ checkpoints
+struct SaveHeader {
+  unsigned long long magic;
+  int version, n, m, R, tsize, n_beams, n_steps, r, step;
+};
+constexpr unsigned long long kSaveMagic = 0x31544b4344524c44ULL;   // "DLRCDKT1"
+
+size_t save_bytes(const dlra_ctx *c) {
+  const Dims &d = c->d;
+  return sizeof(SaveHeader) + size_t(d.n) * d.R * d.tsize + size_t(d.R) * d.R * 8 +
+         size_t(d.m) * d.R * 8 + size_t(d.n) * 8;
+}
+
+// header, then U (r columns of n values in the storage precision), S (r x r,
+// column-major, leading dimension R), V (m x r, column-major), collided dose
+void save_impl(dlra_ctx *c, char *buf) {
+  const Dims &d = c->d;
+  SaveHeader h{kSaveMagic, 1, d.n, d.m, d.R, int(d.tsize), d.n_beams, d.n_steps, c->r, c->step};
+  std::memcpy(buf, &h, sizeof(h));
+  char *q = buf + sizeof(h);
+  for (int j = 0; j < c->r; ++j) {
+    HIPCHK(hipMemcpy(q, static_cast<char *>(c->tall[0]) + size_t(j) * d.ld * d.tsize,
+                     size_t(d.n) * d.tsize, hipMemcpyDeviceToHost));
+    q += size_t(d.n) * d.tsize;
+  }
+  HIPCHK(hipMemcpy(q, c->base + c->plan.S, size_t(d.R) * d.R * 8, hipMemcpyDeviceToHost));
+  q += size_t(d.R) * d.R * 8;
+  HIPCHK(hipMemcpy(q, c->V, size_t(d.m) * c->r * 8, hipMemcpyDeviceToHost));
+  q += size_t(d.m) * c->r * 8;
+  HIPCHK(hipMemcpy(q, c->base + c->plan.dose_c, size_t(d.n) * 8, hipMemcpyDeviceToHost));
+}
+
+int load_impl(dlra_ctx *c, const char *buf, size_t bytes) {
+  const Dims &d = c->d;
+  SaveHeader h;
+  if (bytes < sizeof(h)) return fail(DLRA_E_INVALID, "checkpoint too short");
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kSaveMagic || h.version != 1)
+    return fail(DLRA_E_INVALID, "not a checkpoint of this library");
+  if (h.n != d.n || h.m != d.m || h.R != d.R || h.tsize != int(d.tsize) ||
+      h.n_beams != d.n_beams || h.n_steps != d.n_steps)
+    return fail(DLRA_E_INVALID, "checkpoint of a different problem");
+  if (h.r < 1 || h.r > d.R || h.step < 0 || h.step > d.n_steps)
+    return fail(DLRA_E_INVALID, "checkpoint rank or step out of range");
+  const size_t need = sizeof(h) + size_t(d.n) * h.r * d.tsize + size_t(d.R) * d.R * 8 +
+                      size_t(d.m) * h.r * 8 + size_t(d.n) * 8;
+  if (bytes < need) return fail(DLRA_E_INVALID, "checkpoint truncated");
+  HIPCHK(hipStreamSynchronize(c->st));
+  HIPCHK(hipStreamSynchronize(c->st2));
+  const char *q = buf + sizeof(h);
+  HIPCHK(hipMemset(c->tall[0], 0, size_t(d.ld) * d.P * d.tsize));
+  for (int j = 0; j < h.r; ++j) {
+    HIPCHK(hipMemcpy(static_cast<char *>(c->tall[0]) + size_t(j) * d.ld * d.tsize, q,
+                     size_t(d.n) * d.tsize, hipMemcpyHostToDevice));
+    q += size_t(d.n) * d.tsize;
+  }
+  HIPCHK(hipMemcpy(c->base + c->plan.S, q, size_t(d.R) * d.R * 8, hipMemcpyHostToDevice));
+  q += size_t(d.R) * d.R * 8;
+  HIPCHK(hipMemset(c->V, 0, size_t(d.m) * d.P * 8));
+  HIPCHK(hipMemcpy(c->V, q, size_t(d.m) * h.r * 8, hipMemcpyHostToDevice));
+  q += size_t(d.m) * h.r * 8;
+  HIPCHK(hipMemcpy(c->base + c->plan.dose_c, q, size_t(d.n) * 8, hipMemcpyHostToDevice));
+  c->r = h.r;
+  c->step = h.step;
+  clear_flags(c);
   return DLRA_OK;
 }
 
@@ -871,25 +1104,25 @@ int set_state_impl(dlra_ctx *c, const double *U, const double *S, const double *
 // ==================================================================== C ABI
 extern "C" {
 
-int dlra_workspace_size(const dlra_grid *grid, int n_mat, const dlra_options *opt,
+int dlra_workspace_size(const dlra_grid *grid, int n_mat, int n_beams, const dlra_options *opt,
                         size_t *bytes) {
   Dims d;
   std::string err;
   if (!bytes) return fail(DLRA_E_INVALID, "bytes is NULL");
-  if (!make_dims(grid, n_mat, opt, d, err)) return fail(DLRA_E_INVALID, err);
+  if (!make_dims(grid, n_mat, n_beams, opt, d, err)) return fail(DLRA_E_INVALID, err);
   *bytes = make_plan(d).bytes;
   return DLRA_OK;
 }
 
-int dlra_init(const dlra_grid *grid, const dlra_materials *mat, const dlra_beam *beam,
-              const dlra_options *opt, void *workspace, size_t workspace_bytes, void *stream,
-              dlra_ctx **out) {
+int dlra_init(const dlra_grid *grid, const dlra_materials *mat, int n_beams,
+              const dlra_beam *beams, const dlra_options *opt, void *workspace,
+              size_t workspace_bytes, void *stream, dlra_ctx **out) {
   if (!out) return fail(DLRA_E_INVALID, "out is NULL");
   *out = nullptr;
-  if (!mat || !beam || !workspace) return fail(DLRA_E_INVALID, "null materials, beam or workspace");
+  if (!mat || !beams || !workspace) return fail(DLRA_E_INVALID, "null materials, beams or workspace");
   Dims d;
   std::string err;
-  if (!make_dims(grid, mat->n_mat, opt, d, err)) return fail(DLRA_E_INVALID, err);
+  if (!make_dims(grid, mat->n_mat, n_beams, opt, d, err)) return fail(DLRA_E_INVALID, err);
   if (!mat->w || !mat->e || !mat->S || !mat->T || !mat->dG || mat->n_e < 2)
     return fail(DLRA_E_INVALID, "material tables missing");
   if (mat->n_leg < d.N + 2) return fail(DLRA_E_INVALID, "n_leg must be >= pn_degree + 2");
@@ -898,12 +1131,23 @@ int dlra_init(const dlra_grid *grid, const dlra_materials *mat, const dlra_beam 
   for (size_t t = 0; t < size_t(mat->n_mat) * d.n; ++t)
     if (!(mat->w[t] >= 0.0) || !std::isfinite(mat->w[t]))
       return fail(DLRA_E_INVALID, "partial densities must be finite and >= 0");
-  double dn = std::sqrt(beam->dir[0] * beam->dir[0] + beam->dir[1] * beam->dir[1] +
-                        beam->dir[2] * beam->dir[2]);
-  if (!(std::fabs(dn - 1.0) < 1e-9)) return fail(DLRA_E_INVALID, "beam direction must be a unit vector");
-  if (!(beam->sigma_E > 0) || !(beam->spot_sigma > 0) || !(opt->e_cut > 0) ||
-      !(beam->E0 > opt->e_cut))
-    return fail(DLRA_E_INVALID, "need sigma_E > 0, spot_sigma > 0 and E0 > e_cut > 0");
+  double e_cut = opt->e_cut;
+  if (opt->egrid == DLRA_EGRID_USER) {
+    const double *E = opt->egrid_points;
+    if (!E) return fail(DLRA_E_INVALID, "egrid_points is NULL");
+    for (int k = 0; k <= opt->n_steps; ++k)
+      if (!std::isfinite(E[k]) || !(E[k] > 0.0) || (k > 0 && !(E[k] < E[k - 1])))
+        return fail(DLRA_E_INVALID, "egrid_points must be n_steps + 1 descending energies > 0");
+    e_cut = E[opt->n_steps];
+  }
+  for (int b = 0; b < n_beams; ++b) {
+    const dlra_beam &bm = beams[b];
+    double dn = std::sqrt(bm.dir[0] * bm.dir[0] + bm.dir[1] * bm.dir[1] + bm.dir[2] * bm.dir[2]);
+    if (!(std::fabs(dn - 1.0) < 1e-9)) return fail(DLRA_E_INVALID, "beam direction must be a unit vector");
+    if (!(bm.sigma_E > 0) || !(bm.spot_sigma > 0) || !(e_cut > 0) || !(bm.E0 > e_cut))
+      return fail(DLRA_E_INVALID, "need sigma_E > 0, spot_sigma > 0 and E0 > e_cut > 0");
+    if (!std::isfinite(bm.weight)) return fail(DLRA_E_INVALID, "beam weight must be finite");
+  }
   if (!(opt->aug_tol > 0) || !(opt->fill_tol > 0) || !(opt->fill_tol < 0.1) || !(opt->floor_tol >= 0) ||
       !(opt->ray_h_max > 0) || !(opt->beam_cut_sigmas > 0) || !(opt->e_max_sigmas > 0))
     return fail(DLRA_E_INVALID, "tolerances out of range");
@@ -919,7 +1163,8 @@ int dlra_init(const dlra_grid *grid, const dlra_materials *mat, const dlra_beam 
   c->plan = plan;
   c->grid = *grid;
   c->opt = *opt;
-  c->beam = *beam;
+  c->opt.egrid_points = nullptr;   // copied into c->edges during init
+  c->beams.assign(beams, beams + n_beams);
   c->st = reinterpret_cast<hipStream_t>(stream);
   if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
   if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
@@ -949,7 +1194,11 @@ int dlra_init(const dlra_grid *grid, const dlra_materials *mat, const dlra_beam 
   c->Vn = c->at<double>(plan.Vn);
   int rc;
   try {
+    if (opt->egrid == DLRA_EGRID_USER) c->opt.egrid_points = opt->egrid_points;
     rc = d.tsize == 8 ? init_impl<double>(c, mat) : init_impl<float>(c, mat);
+    c->opt.egrid_points = nullptr;
+  } catch (const std::invalid_argument &e) {
+    rc = fail(DLRA_E_INVALID, e.what());
   } catch (const std::exception &e) {
     rc = fail(DLRA_E_HIP, e.what());
   }
@@ -966,21 +1215,25 @@ int uncollided_raytrace(dlra_ctx *c) {
   try {
     const Plan &p = c->plan;
     const Dims &d = c->d;
-    HIPCHK(hipMemsetAsync(c->base + p.psibar, 0, size_t(d.n_steps) * d.n * d.tsize, c->st));
+    HIPCHK(hipMemsetAsync(c->base + p.psibar, 0, size_t(d.n_beams) * d.n_steps * d.n * d.tsize,
+                          c->st));
     HIPCHK(hipMemsetAsync(c->base + p.dose_u, 0, size_t(d.n) * 8, c->st));
-    auto go = [&](auto *psib) {
+    auto go = [&](int b, auto *psib) {
       using T = std::remove_pointer_t<decltype(psib)>;
-      launch_raytrace_rows<T>(c->rp, c->at<int>(p.rt_rows), c->at<double>(p.rt_f),
-                              c->at<double>(p.w_d), c->at<double>(p.rt_diag),
-                              c->at<double>(p.rt_up), c->at<double>(p.rt_lo),
-                              c->at<double>(p.rt_mass), c->at<double>(p.rt_c0),
-                              c->at<int>(p.rt_g0), c->at<double>(p.rt_sw),
-                              c->at<double>(p.rt_stopw), c->at<double>(p.rt_scratch), psib,
-                              c->at<double>(p.dose_u), c->st);
+      launch_raytrace<T>(c->rps[b], c->rgeo[b], c->at<int>(p.rt_rays) + size_t(b) * d.n,
+                         c->at<double>(p.rt_f) + size_t(b) * d.n, c->at<double>(p.w_d),
+                         c->at<double>(p.rt_diag), c->at<double>(p.rt_up),
+                         c->at<double>(p.rt_lo), c->at<double>(p.rt_mass),
+                         c->at<double>(p.rt_c0) + size_t(b) * 3 * d.G, c->at<int>(p.rt_g0),
+                         c->at<double>(p.rt_sw), c->at<double>(p.rt_stopw),
+                         c->at<double>(p.rt_scratch), size_t(d.ray_batch),
+                         psib + size_t(b) * d.n_steps * d.n, c->at<double>(p.dose_u), c->st);
     };
     PhaseTimer t(c, DLRA_PH_RAYTRACE, nullptr, kBoth);
-    if (d.tsize == 8) go(c->at<double>(p.psibar));
-    else go(c->at<float>(p.psibar));
+    for (int b = 0; b < d.n_beams; ++b) {
+      if (d.tsize == 8) go(b, c->at<double>(p.psibar));
+      else go(b, c->at<float>(p.psibar));
+    }
     HIPCHK(hipGetLastError());
   } catch (const std::exception &e) {
     return fail(DLRA_E_HIP, e.what());
@@ -1010,8 +1263,10 @@ int dlra_step(dlra_ctx *c, int *rank_out) {
 
 int dose_deposit(dlra_ctx *c, double *dose, int flags) {
   if (!c || !dose) return fail(DLRA_E_INVALID, "null ctx or dose");
-  if (flags & ~7) return fail(DLRA_E_INVALID, "unknown flag bits");
+  if (flags & ~15) return fail(DLRA_E_INVALID, "unknown flag bits");
   try {
+    int rc = sync_flags(c);
+    if (rc != DLRA_OK) return rc;
     const Plan &p = c->plan;
     k_dose_out<<<(c->d.n + 255) / 256, 256, 0, c->st>>>(c->d.n, c->d.n_mat,
                                                         c->at<double>(p.dose_u),
@@ -1057,7 +1312,7 @@ int dlra_get_uncollided(dlra_ctx *c, double *psibar, double *Du) {
     const Dims &d = c->d;
     HIPCHK(hipStreamSynchronize(c->st));
     if (psibar) {
-      size_t cnt = size_t(d.n_steps) * d.n;
+      size_t cnt = size_t(d.n_beams) * d.n_steps * d.n;
       if (d.tsize == 8) {
         HIPCHK(hipMemcpy(psibar, c->base + c->plan.psibar, cnt * 8, hipMemcpyDeviceToHost));
       } else {
@@ -1073,6 +1328,58 @@ int dlra_get_uncollided(dlra_ctx *c, double *psibar, double *Du) {
   return DLRA_OK;
 }
 
+int dlra_set_uncollided(dlra_ctx *c, int beam, int step, const double *psibar, const double *Du) {
+  if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
+  const Dims &d = c->d;
+  if (psibar && (beam < 0 || beam >= d.n_beams || step < 0 || step >= d.n_steps))
+    return fail(DLRA_E_INVALID, "beam or step out of range");
+  try {
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (psibar) {
+      char *dst = c->base + c->plan.psibar + (size_t(beam) * d.n_steps + step) * d.n * d.tsize;
+      if (d.tsize == 8) {
+        HIPCHK(hipMemcpy(dst, psibar, size_t(d.n) * 8, hipMemcpyHostToDevice));
+      } else {
+        std::vector<float> h(psibar, psibar + d.n);
+        HIPCHK(hipMemcpy(dst, h.data(), size_t(d.n) * 4, hipMemcpyHostToDevice));
+      }
+    }
+    if (Du) HIPCHK(hipMemcpy(c->base + c->plan.dose_u, Du, size_t(d.n) * 8, hipMemcpyHostToDevice));
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  c->traced = true;
+  return DLRA_OK;
+}
+
+int dlra_save(dlra_ctx *c, void *buf, size_t *bytes) {
+  if (!c || !bytes) return fail(DLRA_E_INVALID, "null ctx or bytes");
+  const size_t need = save_bytes(c);
+  if (!buf) {
+    *bytes = need;
+    return DLRA_OK;
+  }
+  if (*bytes < need) return fail(DLRA_E_INVALID, "buffer smaller than the checkpoint");
+  try {
+    int rc = sync_flags(c);
+    if (rc != DLRA_OK) return rc;
+    save_impl(c, static_cast<char *>(buf));
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  *bytes = need;
+  return DLRA_OK;
+}
+
+int dlra_load(dlra_ctx *c, const void *buf, size_t bytes) {
+  if (!c || !buf) return fail(DLRA_E_INVALID, "null ctx or buffer");
+  try {
+    return load_impl(c, static_cast<const char *>(buf), bytes);
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+}
+
 int dlra_substeps(dlra_ctx *c, int k, int *n_sub) {
   if (!c || !n_sub) return fail(DLRA_E_INVALID, "null argument");
   if (k < 0 || k >= c->d.n_steps) return fail(DLRA_E_INVALID, "k outside [0, n_steps)");
@@ -1082,9 +1389,11 @@ int dlra_substeps(dlra_ctx *c, int k, int *n_sub) {
 
 int dlra_sync(dlra_ctx *c) {
   if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
-  hipError_t e = hipStreamSynchronize(c->st);
-  if (e != hipSuccess) return fail(DLRA_E_HIP, hipGetErrorString(e));
-  return DLRA_OK;
+  try {
+    return sync_flags(c);
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
 }
 
 int dlra_profile(dlra_ctx *c, int on) {

@@ -14,7 +14,9 @@
 
 namespace dlra {
 
-constexpr int kMaxMat = 8;      // base materials per problem
+constexpr int kMaxMat = 16;     // base materials per problem
+constexpr int kMaxBeams = 64;   // beams of one joint context
+constexpr int kMaxSrc = 64;     // source columns n_mat * n_beams of one context
 constexpr int kMaxDim = 3;
 
 // Device control block (one per context).
@@ -72,10 +74,12 @@ void launch_gram(int n, const T *X, int ldx, int p, const T *Y, int ldy, int q,
                  const T *wmat, const T *s, double *G, int ldg, double *partial,
                  size_t partial_elems, hipStream_t st);
 
-// H(a, i) = sum_x X(x, a) w_i(x) psi(x) for i < n_mat (p x n_mat, ldh).
+// H(a, b n_mat + i) = sum_x X(x, a) w_i(x) psi_b(x) for i < n_mat, b < n_beams
+// (p x n_mat n_beams, ldh); psi_b = psi + b * pstride.
 template <typename T, typename Acc>
-void launch_xt_source(int n, const T *X, int ld, int p, const T *w, int n_mat, const T *psi,
-                      double *H, int ldh, double *partial, size_t partial_elems, hipStream_t st);
+void launch_xt_source(int n, const T *X, int ld, int p, const T *w, int n_mat, int n_beams,
+                      const T *psi, size_t pstride, double *H, int ldh, double *partial,
+                      size_t partial_elems, hipStream_t st);
 
 // sum of squares of an n x q tall matrix -> *out (double)
 template <typename T>
@@ -89,11 +93,12 @@ void launch_update(int n, const T *X, int ldx, int p, const double *G, int ldg, 
                    const T *Y, int ldy, double alpha, T *Z, int ldz, int q, double *dose,
                    const double *dc, double dscale, hipStream_t st);
 
-// K(x, c) = sum_a U(x,a) St(a,c) + dt sum_i w_i(x) psi(x) Cg(c, i)  (uncollided K)
+// K(x, c) = sum_a U(x,a) St(a,c) + dt sum_{b,i} w_i(x) psi_b(x) Cg(c, b n_mat + i)
+// (uncollided K; psi_b = psi + b * pstride)
 template <typename T>
 void launch_source_k(int n, const T *U, int ld, int r, const double *St, int lds,
-                     const T *w, int n_mat, const T *psi, const double *Cg, int ldcg, double dt,
-                     T *K, hipStream_t st);
+                     const T *w, int n_mat, int n_beams, const T *psi, size_t pstride,
+                     const double *Cg, int ldcg, double dt, T *K, hipStream_t st);
 
 // ----------------------------------------------------------------- small kernels (double)
 // C[z] = alpha op(A[z]) op(B[z]) + beta C[z], batched over blockIdx.z with
@@ -155,27 +160,39 @@ size_t plan_objective_work(int n, int nb);
 void launch_plan_objective(int n, int nb, const double *doses, const PlanWeights &pw,
                            const unsigned char *target, double dhat, double lam, double *work,
                            double *out, hipStream_t st);
-
 // ----------------------------------------------------------------- ray tracer
 struct RayParams {
   int G;                 // energy groups
   int n_mat;
   int n_steps;
   int ng_step;           // groups per step-integral window
-  int axis, sign;        // beam axis (0,1,2) and direction
-  int n_rows;            // active rows
+  int n_rays;            // rays of the beam
+  int n;                 // cells
+  // grid rows of an axis-aligned beam (axis >= 0): rays[r] is the first cell
+  // of row r; oblique beams (axis = -1): rays[r] is the target cell
+  int axis, sign;        // beam axis (0, 1, 2) and direction
   int row_len;           // cells per row
   int row_stride;        // cell index stride along the row
-  int n;                 // cells
   double half;           // half-cell length along the axis
   int n_half;            // CN substeps per half cell
+  double h_max;          // longest CN substep (cm)
 };
+struct RayGeom {
+  int nx, ny, nz, dim;
+  double D[3];           // cell sizes (cm)
+  double L[3];           // box lengths (cm)
+  double om[3];          // unit direction of flight
+};
+// scratch doubles per ray of a batch: c, y (3G each), Dinv, E (9G each)
+constexpr int kRayScratchPerGroup = 24;
+// uncollided tables of one beam: rays in batches of `batch` (the scratch
+// holds kRayScratchPerGroup * G * batch doubles)
 template <typename T>
-void launch_raytrace_rows(const RayParams &rp, const int *row_start, const double *row_f,
-                          const double *w, const double *Adiag, const double *Aup,
-                          const double *Alo, const double *mass, const double *c0,
-                          const int *step_g0, const double *step_w, const double *stop_w,
-                          double *scratch, T *psibar, double *Du, hipStream_t st);
+void launch_raytrace(const RayParams &rp, const RayGeom &geo, const int *rays,
+                     const double *ray_f, const double *w, const double *Adiag,
+                     const double *Aup, const double *Alo, const double *mass, const double *c0,
+                     const int *step_g0, const double *step_w, const double *stop_w,
+                     double *scratch, size_t batch, T *psibar, double *Du, hipStream_t st);
 
 // min over cells of sum_i w_i S_i(E_k) for every step k
 void launch_min_stop(int n, const double *w, int n_mat, const double *Sk, int n_steps,

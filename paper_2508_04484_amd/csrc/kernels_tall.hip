@@ -45,12 +45,17 @@ struct YMat {
   int ld;
   __device__ T operator()(int x, int c) const { return Y[size_t(c) * ld + x]; }
 };
+// source column c = b n_mat + i of a context's beams: w_i(x) psi_b(x)
 template <typename T>
 struct YSrc {
   const T *w;
   const T *psi;
-  int n;
-  __device__ T operator()(int x, int i) const { return w[size_t(i) * n + x] * psi[x]; }
+  int n, n_mat;
+  size_t pstride;
+  __device__ T operator()(int x, int c) const {
+    const int b = c / n_mat, i = c - b * n_mat;
+    return w[size_t(i) * n + x] * psi[size_t(b) * pstride + x];
+  }
 };
 template <typename T>
 struct WOne {
@@ -1221,12 +1226,12 @@ __global__ __launch_bounds__(256) void k_update_mfma(
     int n, const T *__restrict__ X, int ldx, int p, const double *__restrict__ G, int ldg,
     double beta, const T *Y, int ldy, double alpha, T *Z, int ldz, int q,
     double *__restrict__ dose, const double *__restrict__ dc, double dscale,
-    const T *__restrict__ sw, int n_mat, const T *__restrict__ spsi,
+    const T *__restrict__ sw, int n_mat, int n_src, const T *__restrict__ spsi, size_t pstride,
     const double *__restrict__ sC, int ldsc, double sdt) {
   using acc_t = typename Mfma<T>::acc_t;
   constexpr int QS = 16 * NQ;
   extern __shared__ unsigned char smem_raw[];
-  const int ne = p + (sw != nullptr ? n_mat : 0);
+  const int ne = p + (sw != nullptr ? n_src : 0);
   const int nk = (ne + 3) & ~3;
   T *Gs = reinterpret_cast<T *>(smem_raw);                 // [nk][QS]
   double *dcs = reinterpret_cast<double *>(Gs + nk * QS);  // [QS]
@@ -1268,9 +1273,6 @@ __global__ __launch_bounds__(256) void k_update_mfma(
           for (int v = 0; v < 4; ++v)
             yraw[h][jt][v] = Y[size_t(min(16 * jt + Mfma<T>::row(qd, v), q - 1)) * ldy + xc[h]];
     }
-    double srcs[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) srcs[h] = sw != nullptr ? sdt * double(spsi[xc[h]]) : 0.0;
     acc_t acc[2][NQ];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -1285,8 +1287,11 @@ __global__ __launch_bounds__(256) void k_update_mfma(
           const int k = k0 + 4 * u + qd;
           T v = X[size_t(min(k, p - 1)) * ldx + xc[h]];
           if (sw != nullptr) {
-            const T sv =
-                T(double(sw[size_t(min(max(k - p, 0), n_mat - 1)) * n + xc[h]]) * srcs[h]);
+            // source column e = b n_mat + i: sdt w_i(x) psi_b(x)
+            const int e = min(max(k - p, 0), n_src - 1);
+            const int b = e / n_mat, i = e - b * n_mat;
+            const double src = sdt * double(spsi[size_t(b) * pstride + xc[h]]);
+            const T sv = T(double(sw[size_t(i) * n + xc[h]]) * src);
             v = k < p ? v : sv;
           }
           b[h][u] = (valid[h] && k < ne) ? v : T(0);
@@ -1341,12 +1346,12 @@ __global__ __launch_bounds__(256) void k_update_vec(
     int n, const float *__restrict__ X, int ldx, int p, const double *__restrict__ G, int ldg,
     double beta, const float *Y, int ldy, double alpha, float *Z, int ldz, int q,
     double *__restrict__ dose, const double *__restrict__ dc, double dscale,
-    const float *__restrict__ sw, int n_mat, const float *__restrict__ spsi,
-    const double *__restrict__ sC, int ldsc, double sdt) {
+    const float *__restrict__ sw, int n_mat, int n_src, const float *__restrict__ spsi,
+    size_t pstride, const double *__restrict__ sC, int ldsc, double sdt) {
   using acc_t = typename Mfma<float>::acc_t;
   constexpr int QS = 16 * NQ;
   extern __shared__ unsigned char smem_raw[];
-  const int ne = p + (sw != nullptr ? n_mat : 0);
+  const int ne = p + (sw != nullptr ? n_src : 0);
   const int nk = (ne + 3) & ~3;
   float *Gs = reinterpret_cast<float *>(smem_raw);             // [nk][QS]
   double *dcs = reinterpret_cast<double *>(Gs + nk * QS);      // [QS]
@@ -1391,14 +1396,6 @@ __global__ __launch_bounds__(256) void k_update_vec(
         for (int v = 0; v < 4; ++v)
           yraw[jt][v] = ld4(Y + size_t(min(16 * jt + Mfma<float>::row(qd, v), q - 1)) * ldy);
     }
-    double srcs[4];
-    if (sw != nullptr) {
-      const float4 ps = ld4(spsi);
-      srcs[0] = sdt * double(ps.x);
-      srcs[1] = sdt * double(ps.y);
-      srcs[2] = sdt * double(ps.z);
-      srcs[3] = sdt * double(ps.w);
-    }
     acc_t acc[4][NQ];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -1412,10 +1409,16 @@ __global__ __launch_bounds__(256) void k_update_vec(
         const float4 xv = ld4(X + size_t(min(k, p - 1)) * ldx);
         float v[4] = {xv.x, xv.y, xv.z, xv.w};
         if (sw != nullptr) {
-          const float4 wv = ld4(sw + size_t(min(max(k - p, 0), n_mat - 1)) * n);
+          // source column e = b n_mat + i: sdt w_i(x) psi_b(x)
+          const int e = min(max(k - p, 0), n_src - 1);
+          const int b = e / n_mat, im = e - b * n_mat;
+          const float4 wv = ld4(sw + size_t(im) * n);
+          const float4 ps = ld4(spsi + size_t(b) * pstride);
           const float wa[4] = {wv.x, wv.y, wv.z, wv.w};
+          const float pa[4] = {ps.x, ps.y, ps.z, ps.w};
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] = k < p ? v[i] : float(double(wa[i]) * srcs[i]);
+          for (int i = 0; i < 4; ++i)
+            v[i] = k < p ? v[i] : float(double(wa[i]) * (sdt * double(pa[i])));
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) b[u][i] = (valid[i] && k < ne) ? v[i] : 0.0f;
@@ -1728,23 +1731,23 @@ void launch_gram(int n, const T *X, int ldx, int p, const T *Y, int ldy, int q, 
 }
 
 template <typename T, typename Acc>
-void launch_xt_source(int n, const T *X, int ld, int p, const T *w, int n_mat, const T *psi,
-                      double *H, int ldh, double *partial, size_t partial_elems,
-                      hipStream_t st) {
+void launch_xt_source(int n, const T *X, int ld, int p, const T *w, int n_mat, int n_beams,
+                      const T *psi, size_t pstride, double *H, int ldh, double *partial,
+                      size_t partial_elems, hipStream_t st) {
   int nb = 0;
-  if (p <= 112 && n_mat <= 16) {
-    gram<T, Acc, false>(n, X, ld, p, YSrc<T>{w, psi, n}, n_mat, WOne<T>{}, partial,
-                        partial_elems, st, nb);
+  const int q = n_mat * n_beams;
+  const YSrc<T> ys{w, psi, n, n_mat, pstride};
+  if (p <= 112 && q <= 16) {
+    gram<T, Acc, false>(n, X, ld, p, ys, q, WOne<T>{}, partial, partial_elems, st, nb);
   } else {
     GridDev g{};
     g.n = n;
-    contract<T, Acc>(g, X, ld, p, YSrc<T>{w, psi, n}, n_mat, WOne<T>{}, partial, partial_elems,
-                     st, nb);
+    contract<T, Acc>(g, X, ld, p, ys, q, WOne<T>{}, partial, partial_elems, st, nb);
   }
-  const size_t per = size_t(p) * n_mat;
+  const size_t per = size_t(p) * q;
   double *red = partial + size_t(nb) * per;
   reduce_partials(partial, nb, int(per), red, st, red + per, room_after(partial_elems, nb + 1, per));
-  k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, n_mat, 1, H, ldh, 0);
+  k_scatter<<<(per + kBlock - 1) / kBlock, kBlock, 0, st>>>(red, p, q, 1, H, ldh, 0);
 }
 
 template <typename T>
@@ -1759,11 +1762,13 @@ void launch_sumsq(int n, const T *X, int ld, int q, double *out, double *partial
 template <typename T>
 static void update(int n, const T *X, int ldx, int p, const double *G, int ldg, double beta,
                    const T *Y, int ldy, double alpha, T *Z, int ldz, int q, double *dose,
-                   const double *dc, double dscale, const T *sw, int n_mat, const T *spsi,
-                   const double *sC, int ldsc, double sdt, hipStream_t st) {
+                   const double *dc, double dscale, const T *sw, int n_mat, int n_beams,
+                   const T *spsi, size_t pstride, const double *sC, int ldsc, double sdt,
+                   hipStream_t st) {
   if (n <= 0 || q <= 0) return;
   const int nq = (q + 15) / 16;   // q <= 64: ranks are capped at 50
-  const int ne = p + (sw != nullptr ? n_mat : 0);
+  const int n_src = n_mat * n_beams;
+  const int ne = p + (sw != nullptr ? n_src : 0);
   const int nk = (ne + 3) & ~3;
   const size_t shm = size_t(nk) * 16 * nq * sizeof(T) + size_t(16) * nq * sizeof(double);
   const int blocks = std::max(1, std::min(kUpdBlocks, (n + 127) / 128));
@@ -1775,14 +1780,15 @@ static void update(int n, const T *X, int ldx, int p, const double *G, int ldg, 
       (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                        \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));     \
     kern<<<blocks, 256, shm, st>>>(n, X, ldx, p, G, ldg, beta, Y, ldy, alpha, Z, ldz, q,    \
-                                   dose, dc, dscale, sw, n_mat, spsi, sC, ldsc, sdt);       \
+                                   dose, dc, dscale, sw, n_mat, n_src, spsi, pstride, sC,   \
+                                   ldsc, sdt);                                              \
   } while (0)
   auto a16 = [](const void *ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; };
   if constexpr (sizeof(T) == 4) {
     // 16-byte form where every column start is 16-byte aligned
     const bool vec = ldx % 4 == 0 && ldz % 4 == 0 && a16(X) && a16(Z) &&
                      (!HY || (ldy % 4 == 0 && a16(Y))) &&
-                     (sw == nullptr || (n % 4 == 0 && a16(sw) && a16(spsi)));
+                     (sw == nullptr || (n % 4 == 0 && pstride % 4 == 0 && a16(sw) && a16(spsi)));
     if (vec) {
       const int vblocks = std::max(1, std::min(kUpdBlocks, (n + 255) / 256));
 #define DLRA_UPDATE_VEC(NQ)                                                                 \
@@ -1792,7 +1798,8 @@ static void update(int n, const T *X, int ldx, int p, const double *G, int ldg, 
       (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                        \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));     \
     kern<<<vblocks, 256, shm, st>>>(n, X, ldx, p, G, ldg, beta, Y, ldy, alpha, Z, ldz, q,   \
-                                    dose, dc, dscale, sw, n_mat, spsi, sC, ldsc, sdt);      \
+                                    dose, dc, dscale, sw, n_mat, n_src, spsi, pstride, sC,  \
+                                    ldsc, sdt);                                             \
   } while (0)
       switch (nq) {
         case 1: DLRA_UPDATE_VEC(1); break;
@@ -1817,16 +1824,16 @@ template <typename T>
 void launch_update(int n, const T *X, int ldx, int p, const double *G, int ldg, double beta,
                    const T *Y, int ldy, double alpha, T *Z, int ldz, int q, double *dose,
                    const double *dc, double dscale, hipStream_t st) {
-  update<T>(n, X, ldx, p, G, ldg, beta, Y, ldy, alpha, Z, ldz, q, dose, dc, dscale, nullptr, 0,
-            nullptr, nullptr, 0, 0.0, st);
+  update<T>(n, X, ldx, p, G, ldg, beta, Y, ldy, alpha, Z, ldz, q, dose, dc, dscale, nullptr, 1,
+            1, nullptr, 0, nullptr, 0, 0.0, st);
 }
 
 template <typename T>
 void launch_source_k(int n, const T *U, int ld, int r, const double *St, int lds, const T *w,
-                     int n_mat, const T *psi, const double *Cg, int ldcg, double dt, T *K,
-                     hipStream_t st) {
+                     int n_mat, int n_beams, const T *psi, size_t pstride, const double *Cg,
+                     int ldcg, double dt, T *K, hipStream_t st) {
   update<T>(n, U, ld, r, St, lds, 1.0, nullptr, 0, 0.0, K, ld, r, nullptr, nullptr, 0.0, w,
-            n_mat, psi, Cg, ldcg, dt, st);
+            n_mat, n_beams, psi, pstride, Cg, ldcg, dt, st);
 }
 
 // ------------------------------------------------------------------ plan objective
@@ -1903,16 +1910,17 @@ void launch_plan_objective(int n, int nb, const double *doses, const PlanWeights
                                                   hipStream_t);                               \
   template void launch_gram<T, Acc>(int, const T *, int, int, const T *, int, int, const T *, \
                                     const T *, double *, int, double *, size_t, hipStream_t); \
-  template void launch_xt_source<T, Acc>(int, const T *, int, int, const T *, int, const T *, \
-                                         double *, int, double *, size_t, hipStream_t);       \
+  template void launch_xt_source<T, Acc>(int, const T *, int, int, const T *, int, int,      \
+                                         const T *, size_t, double *, int, double *, size_t,  \
+                                         hipStream_t);                                        \
   template void launch_sumsq<T>(int, const T *, int, int, double *, double *, size_t,         \
                                 hipStream_t);                                                 \
   template void launch_update<T>(int, const T *, int, int, const double *, int, double,       \
                                  const T *, int, double, T *, int, int, double *,             \
                                  const double *, double, hipStream_t);                        \
   template void launch_source_k<T>(int, const T *, int, int, const double *, int, const T *,  \
-                                   int, const T *, const double *, int, double, T *,          \
-                                   hipStream_t);
+                                   int, int, const T *, size_t, const double *, int, double,  \
+                                   T *, hipStream_t);
 
 DLRA_INSTANTIATE(double, double)
 DLRA_INSTANTIATE(float, float)

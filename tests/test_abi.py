@@ -34,7 +34,7 @@ def test_struct_layouts_match_header():
     # field order and sizes as in include/dlra.h (LP64)
     assert C.sizeof(B.Grid) == 3 * 4 + 4 + 3 * 8
     assert C.sizeof(B.Beam) == 10 * 8
-    assert C.sizeof(B.Options) == 9 * 4 + 4 + 9 * 8
+    assert C.sizeof(B.Options) == 9 * 4 + 4 + 9 * 8 + 2 * 4 + 8
     assert C.sizeof(B.Materials) == 3 * 4 + 4 + 5 * 8
 
 
@@ -46,30 +46,62 @@ def test_workspace_size_scales_with_problem():
 
 @pytest.mark.parametrize("bad", [
     dict(r=0), dict(r=60, r_max=60), dict(n_steps=0), dict(precision="half"),
-    dict(rank_mode="adaptive", r_min=5, r_max=3),
+    dict(rank_mode="adaptive", r_min=5, r_max=3), dict(collision=5), dict(egrid=9),
 ])
 def test_invalid_options_rejected(bad):
     p = configs.small_2d()
+    raw = {k: bad.pop(k) for k in ("collision", "egrid") if k in bad}
     opts = p.options.with_(**bad)
     if opts.precision not in ("fp64", "mixed"):
-        o = B.make_options(p.options)
+        o, _ = B.make_options(p.options)
         o.precision = 7
     else:
-        o = B.make_options(opts)
+        o, _ = B.make_options(opts)
+    for k, v in raw.items():
+        setattr(o, k, v)
     out = C.c_size_t(0)
-    rc = B.load().dlra_workspace_size(C.byref(B.make_grid(p.grid)), p.materials.n_mat,
+    rc = B.load().dlra_workspace_size(C.byref(B.make_grid(p.grid)), p.materials.n_mat, 1,
                                       C.byref(o), C.byref(out))
     assert rc == -1
     assert B.load().dlra_last_error()
+
+
+@pytest.mark.parametrize("n_mat,n_beams,ok", [(12, 1, True), (16, 4, True), (17, 1, False),
+                                              (3, 21, True), (3, 22, False), (1, 65, False),
+                                              (1, 0, False)])
+def test_material_and_beam_limits(n_mat, n_beams, ok):
+    # up to 16 base materials (the paper's twelve elements fit), up to 64
+    # beams per joint context, at most 64 source columns n_mat * n_beams
+    p = configs.small_2d()
+    o, _ = B.make_options(p.options)
+    out = C.c_size_t(0)
+    rc = B.load().dlra_workspace_size(C.byref(B.make_grid(p.grid)), n_mat, n_beams, C.byref(o),
+                                      C.byref(out))
+    assert (rc == 0) == ok
+
+
+def test_workspace_size_grows_with_beams():
+    p = configs.small_2d()
+    assert B.workspace_size(p, 3) > B.workspace_size(p, 1)
 
 
 def test_init_rejects_null_workspace_without_touching_the_gpu():
     p = configs.small_2d()
     lib = B.load()
     ctx = C.c_void_p(0)
-    rc = lib.dlra_init(C.byref(B.make_grid(p.grid)), None, None,
-                       C.byref(B.make_options(p.options)), None, 0, None, C.byref(ctx))
+    o, _ = B.make_options(p.options)
+    rc = lib.dlra_init(C.byref(B.make_grid(p.grid)), None, 1, None, C.byref(o), None, 0, None,
+                       C.byref(ctx))
     assert rc == -1 and not ctx.value
+
+
+def test_checkpoint_and_flag_calls_reject_null_context():
+    lib = B.load()
+    n = C.c_size_t(0)
+    assert lib.dlra_save(None, None, C.byref(n)) == -1
+    assert lib.dlra_load(None, None, 0) == -1
+    assert lib.dlra_sync(None) == -1
+    assert lib.dlra_set_uncollided(None, 0, 0, None, None) == -1
 
 
 def test_plan_objective_rejects_bad_arguments_without_touching_the_gpu():

@@ -276,3 +276,44 @@ def small_3d(n=8, N=3, E0=25.0, n_steps=8, spot=0.15, mats="random", r=6, dx=0.0
     m = make_materials(names, w, o.pn_degree)
     c = 0.5 * n * dx
     return Problem(grid, m, [beam_along_x(E0, spot, c + 0.011, c - 0.007)], o, name="small_3d")
+
+
+def small_oblique_2d(angle_deg=30.0, nx=16, ny=14, N=3, E0=25.0, n_steps=10, mats="slab", r=6,
+                     dx=0.05, n_groups=32, **opt) -> Problem:
+    """Small 2D case with one beam at an oblique angle in the plane, aimed at
+    the grid centre from outside (one ray per target cell)."""
+    p = small_2d(nx=nx, ny=ny, N=N, E0=E0, n_steps=n_steps, mats=mats, r=r, dx=dx,
+                 n_groups=n_groups, **opt)
+    c = (0.5 * nx * dx + 0.004, 0.5 * ny * dx - 0.006, 0.0)
+    b = aimed_beam(E0, 0.15, math.radians(angle_deg), c, nx * dx)
+    return Problem(p.grid, p.materials, [b], p.options, name="small_oblique_2d")
+
+
+def small_oblique_3d(n=8, N=3, E0=25.0, n_steps=8, r=6, dx=0.05, n_groups=32,
+                     direction=(0.8, 0.5, 0.33), **opt) -> Problem:
+    """Small 3D random phantom with one beam along an oblique (non-planar)
+    direction through the grid centre."""
+    p = small_3d(n=n, N=N, E0=E0, n_steps=n_steps, r=r, dx=dx, n_groups=n_groups, **opt)
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    c = np.full(3, 0.5 * n * dx) + np.array([0.003, -0.005, 0.002])
+    pos = tuple(c - n * dx * d)
+    b = Beam(E0=E0, sigma_E=0.01 * E0, spot_sigma=0.15, pos=pos, dir=tuple(d))
+    return Problem(p.grid, p.materials, [b], p.options, name="small_oblique_3d")
+
+
+def small_arc_2d(n_beams=3, nx=16, ny=16, N=3, n_steps=10, mats="slab", r=8, dx=0.05,
+                 n_groups=32, **opt) -> Problem:
+    """Small 2D case with several beams of different energies and weights aimed
+    at the centre from angles spread over the plane (a reduced arc of the
+    adjoint configuration's beams)."""
+    p = small_2d(nx=nx, ny=ny, N=N, n_steps=n_steps, mats=mats, r=r, dx=dx, n_groups=n_groups,
+                 **opt)
+    c = (0.5 * nx * dx + 0.003, 0.5 * ny * dx - 0.002, 0.0)
+    beams = []
+    for b in range(n_beams):
+        E = 22.0 + 3.0 * b
+        bm = aimed_beam(E, 0.15, math.radians(40.0 * b + 5.0), c, nx * dx)
+        beams.append(dataclasses.replace(bm, weight=1.0 - 0.2 * b))
+    return Problem(p.grid, p.materials, beams, p.options, name="small_arc_2d")
+

@@ -83,6 +83,7 @@ class Options:
     floor_tol: float = 1e-7        # singular-value floor for kept directions
     fill_tol: float = 1e-2         # acceptance threshold for filler directions
     nu_max: float = 0.0            # CFL number; 0 -> 0.45 (2D) / 0.35 (3D)
+    n_sub_max: int = 0             # bound on RK4 substeps per energy step (0: none)
     ray_h_max: float = 0.01        # cm, ray-tracer step bound (Sec. 3.2)
     n_groups: int = 128            # DG energy groups of the ray tracer (Sec. 3.2)
     beam_cut_sigmas: float = 8.0   # rays are traced where d_perp <= cut * spot sigma
