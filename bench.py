@@ -103,20 +103,58 @@ def measured_traffic(config):
 
 
 def kstage_algorithmic(problem):
-    """(flops, bytes) of one K-step RK4 stage over all cells: per cell the
-    contraction of 2*dim difference vectors with r x r couplings (2 ndk r^2),
-    the differences (4 ndk r) and the stage combine (2 r); bytes = read the
-    stage input, K0 and s, write the stage output."""
+    """(flops, bytes, flops with the differences) of one K-step RK4 stage over
+    all cells.  Flops: the contraction of the 2*dim one-sided difference
+    vectors with the r x r couplings, 2 ndk r^2 per cell (12 n r^2 per stage
+    in 3D, a quarter of the 48 n r^2 per substep of the cost model); the
+    differences (4 ndk r) and the stage combine (2 r) are given separately.
+    Bytes: read the stage input, K0 and s, write the stage output."""
     g, o = problem.grid, problem.options
     ndk = 2 * g.dim
     r = o.r if o.rank_mode == "fixed" else o.r_max
     b = 8 if o.precision == "fp64" else 4
-    flops = g.n * (2 * ndk * r * r + 4 * ndk * r + 2 * r)
+    flops = g.n * (2 * ndk * r * r)
+    flops_all = g.n * (2 * ndk * r * r + 4 * ndk * r + 2 * r)
     nbytes = g.n * (3 * r + 1) * b
-    return flops, nbytes
+    return flops, nbytes, flops_all
 
 
-def cpu_baseline(problem, budget_planes=32):
+# Algorithmic work of the ray tracer per energy group: one Crank-Nicolson
+# substep forms (M + h/2 A) c (three 3x3 blocks, 54 flops) and solves the
+# block-tridiagonal system with a stored factorisation (forward 39, backward
+# 21 flops): 114 flops; one factorisation mixes the three blocks of n_mat
+# materials (54 n_mat flops) and forms L E, the 3x3 inverse and Dinv U
+# (150 flops).
+RAY_FLOPS_PER_SUBSTEP_GROUP = 114
+
+
+def ray_factor_flops_per_group(n_mat):
+    return 150 + 54 * n_mat
+
+
+def raytrace_roofline(problem, work, kernel_ms):
+    """FP64-ALU roofline of the ray tracer from its work counts and duration,
+    with the bytes it must write (uncollided tables and D_u)."""
+    substeps, factors, rays = work
+    G = problem.options.n_groups
+    flops = G * (substeps * RAY_FLOPS_PER_SUBSTEP_GROUP
+                 + factors * ray_factor_flops_per_group(problem.materials.n_mat))
+    b = 8 if problem.options.precision == "fp64" else 4
+    out_cells = problem.grid.n   # upper bound: every cell gets a table
+    nbytes = out_cells * (problem.options.n_steps * b + 8)
+    t = kernel_ms / 1000.0
+    achieved = flops / t / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": 78.6, "unit": "TFLOP/s",
+            "frac": round(achieved / 78.6, 4), "kernel": "k_raytrace",
+            "ms": round(kernel_ms, 3), "rays": rays, "cn_substeps": substeps,
+            "factorizations": factors, "algorithmic_flops": flops,
+            "output_bytes_upper": nbytes, "output_gbs": round(nbytes / t / 1e9, 1),
+            "scratch_gbs_model": round(substeps * G * 30 * 8 / t / 1e9, 1),
+            "note": "per group: 114 flops per CN substep, 150 + 54 n_mat per factorisation; "
+                    "scratch model: 30 doubles per group per substep"}
+
+
+def cpu_baseline(problem, budget_planes=32, window=None):
     """Time one reference (CPU, FP64) step on a z-slab of the phantom from a
     seeded random rank-r state at the step whose substep count is closest to
     the run's mean, and scale to the whole phantom."""
@@ -134,6 +172,7 @@ def cpu_baseline(problem, budget_planes=32):
         threads = os.cpu_count() or 1
     g = problem.grid
     o = problem.options
+    window = list(window) if window is not None else None
     nzs = min(budget_planes, g.nz)
     z0 = (g.nz - nzs) // 2
     sub = Grid(g.nx, g.ny, nzs, g.dx, g.dy, g.dz)
@@ -145,6 +184,8 @@ def cpu_baseline(problem, budget_planes=32):
     p = dataclasses.replace(problem, grid=sub, materials=mats, beams=[beam],
                             options=o.with_(precision="fp64"))
     nsub = [coeffs.step_coeffs(problem, problem.beams[0], k).n_sub for k in range(o.n_steps)]
+    if window is not None:   # the GPU's timed steps: scale to their substeps
+        nsub = [nsub[k] for k in window]
     mean_nsub = sum(nsub) / len(nsub)
     k = min(range(o.n_steps), key=lambda j: abs(nsub[j] - mean_nsub))
     rng = np.random.default_rng(7)
@@ -168,8 +209,119 @@ def cpu_baseline(problem, budget_planes=32):
                    f"{g.nx}x{g.ny}x{nzs} slab of the phantom from a seeded random rank-{r} "
                    f"state with a synthetic source, {dt:.2f} s, scaled by cells "
                    f"x{g.n / sub.n:.0f} and substeps x{mean_nsub / c.n_sub:.3f} "
-                   f"(run mean n_sub {mean_nsub:.2f})"),
+                   f"(mean n_sub {mean_nsub:.2f} of the GPU's timed steps)"),
     }
+
+
+def cpu_baseline_2d(problem, window, budget_s=15.0):
+    """The FP64 reference on the whole 2D problem from the first energy step,
+    as many steps as fit in about budget_s seconds, scaled to the substeps of
+    the GPU's timed steps."""
+    import numpy as np
+
+    from oracle import coeffs, dlra, solver
+    try:
+        import threadpoolctl
+        threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    o = problem.options
+    beam = problem.beams[0]
+    edges = coeffs.energy_edges(problem, [beam])
+    t0 = time.perf_counter()
+    psibar, Du = solver.uncollided(problem, beam, edges=edges)
+    t_ray = time.perf_counter() - t0
+    Apm = solver.streaming_split(problem)
+    st = dlra.initial_state(problem, coeffs.step_coeffs(problem, beam, 0, edges).g)
+    nsub, k, t_steps = [], 0, 0.0
+    while k < o.n_steps and (k == 0 or t_steps < budget_s):
+        c = coeffs.step_coeffs(problem, beam, k, edges)
+        t0 = time.perf_counter()
+        st = dlra.step(st, c, Apm, problem, psibar[k])
+        t_steps += time.perf_counter() - t0
+        nsub.append(c.n_sub)
+        k += 1
+    gpu_nsub = [coeffs.step_coeffs(problem, beam, j, edges).n_sub for j in window]
+    scale = (sum(gpu_nsub) / len(gpu_nsub)) / (sum(nsub) / len(nsub))
+    return {"value": k / t_steps / scale, "unit": "energy-steps/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"FP64 reference steps 0..{k - 1} of the whole problem ({t_steps:.2f} s, "
+                       f"mean n_sub {sum(nsub) / len(nsub):.2f}), scaled to the mean n_sub of "
+                       f"the GPU's timed steps (x{scale:.3f}); its ray tracer took {t_ray:.2f} s")}
+
+
+def bench_plan(problem, args):
+    """c5's nine oblique beams on the slab phantom: the plan dose solved as
+    separate beams through the batch scheduler, and as one joint collided
+    solve (Sec. 4.3), each timed with its ray traces; then the plan objective
+    and its exact gradient over the beam weights on the separate doses."""
+    import numpy as np
+    import torch
+
+    import paper_2508_04484_amd as dl
+    from workloads.plan import centre_target
+    B = len(problem.beams)
+    o = problem.options
+    g = problem.grid
+    # warm-up
+    s = dl.BeamSolver(problem, 0)
+    s.raytrace()
+    s.step()
+    s.sync()
+    s.close()
+    torch.cuda.synchronize()
+    solvers = [dl.Solver(problem, [b], stream=torch.cuda.Stream()) for b in range(B)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dl.run_batch(solvers)
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t0
+    print(f"separate beams (batched): {t_sep:.2f} s", file=sys.stderr, flush=True)
+    total = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    for sv in solvers:
+        sv.dose(dl.binding.DOSE_UNCOLLIDED | dl.binding.DOSE_COLLIDED | dl.binding.DOSE_ACCUMULATE,
+                 out=total)
+    doses = torch.stack([sv.dose() for sv in solvers]).contiguous()
+    for sv in solvers:
+        sv.close()
+    j = dl.Solver(problem)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    j.raytrace()
+    j.run()
+    torch.cuda.synchronize()
+    t_joint = time.perf_counter() - t0
+    joint = j.dose()
+    j.close()
+    print(f"joint solve: {t_joint:.2f} s", file=sys.stderr, flush=True)
+    target = torch.from_numpy(centre_target(g, 1.0)).cuda()
+    tmask = target.bool()
+    dhat = float(total[tmask].mean()) if bool(tmask.any()) else 1.0
+    w = np.array([b.weight for b in problem.beams])
+    dl.binding.plan_objective(doses, w, target, dhat, 0.1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        J, grad = dl.binding.plan_objective(doses, w, target, dhat, 0.1)
+    t_grad = (time.perf_counter() - t0) / 20
+    diff = float(torch.linalg.norm(joint - total) / torch.linalg.norm(total))
+    out = {
+        "metric": "plan of 9 beams: separate (batched) vs joint solve",
+        "value": round(B / t_sep, 5), "unit": "beams/s", "n_gpus": 1, "steps": o.n_steps,
+        "warmup": 1, "ms_per_step": round(1000.0 * t_sep / o.n_steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if o.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": (f"{problem.name}: {g.nx}x{g.ny} cells of {g.dx * 10:g} mm, "
+                                f"{B} oblique beams {problem.beams[0].E0:.0f}.."
+                                f"{problem.beams[-1].E0:.0f} MeV every 40 deg, P_{o.pn_degree}, "
+                                f"adaptive rank <= {o.r_max}, {o.n_steps} steps, {o.precision}")},
+        "separate_s": round(t_sep, 3), "joint_s": round(t_joint, 3),
+        "joint_over_separate_time": round(t_joint / t_sep, 4),
+        "joint_vs_separate_rel_l2_dose": diff,
+        "weight_gradient": {"ms": round(1000.0 * t_grad, 4), "J": J,
+                            "dJ_dw": [round(float(x), 6) for x in grad]},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(problem, args):
@@ -274,15 +426,38 @@ def bench_batch(problem, args):
     print(json.dumps(out), flush=True)
 
 
+def fp64_check(problem, K, dose_mixed):
+    """Relative L2 difference of the deposited energy after K steps between the
+    benchmarked mixed-precision run and the same run through the library's
+    FP64 path (which matches the FP64 reference to 1e-10 on the test cases)."""
+    import numpy as np
+
+    import paper_2508_04484_amd as dl
+    p64 = problem.with_options(precision="fp64")
+    s = dl.BeamSolver(p64, 0)
+    s.raytrace()
+    t0 = time.perf_counter()
+    s.run(K)
+    t = time.perf_counter() - t0
+    d64 = s.dose().cpu().numpy()
+    s.close()
+    return {"rel_l2_dose": float(np.linalg.norm(dose_mixed - d64) / np.linalg.norm(d64)),
+            "steps": K, "fp64_run_s": round(t, 3),
+            "note": "mixed (FP32 storage/stencil/projections) against the library's FP64 path"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=250)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4_axis"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c4_axis", "c5"])
     ap.add_argument("--beams", type=int, default=8,
-                    help="c4_axis: number of the plan's beams timed plain and batched")
+                    help="c4, c4_axis: number of the plan's beams timed plain and batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-check", action="store_true",
+                    help="also run the timed steps through the FP64 path and report the "
+                         "relative L2 dose difference of the mixed-precision run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (a known-size "
                          "reference for hardware byte counters)")
@@ -314,8 +489,10 @@ def main():
         del a, b
     problem = configs.CONFIGS[args.config]()
     o = problem.options
-    if args.config == "c4_axis":
+    if args.config in ("c4", "c4_axis"):
         return bench_batch(problem, args)
+    if args.config == "c5":
+        return bench_plan(problem, args)
     K = min(args.steps, o.n_steps)
 
     # warm-up: a separate solver runs W steps (code objects, allocator,
@@ -347,6 +524,7 @@ def main():
     s.sync()
     t_ray = time.perf_counter() - t0
     prof_ray = s.profile_read()["raytrace"]
+    ray_work = s.raytrace_work()
     s.profile(True, light=True)   # reset counters for the timed region
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -361,10 +539,11 @@ def main():
     prof = s.profile_read()
     s.profile(False)
     nsub = [s.substeps(k) for k in range(K)]
+    s_dose = s.dose().cpu().numpy() if args.fp64_check else None
     s.close()
 
     ms_step = 1000.0 * wall / K
-    flops, nbytes = kstage_algorithmic(problem)
+    flops, nbytes, flops_all = kstage_algorithmic(problem)
     ks_ms, ks_n = prof["kstage"]
     avg = ks_ms / max(ks_n, 1) / 1000.0
     achieved_flops = flops / avg / 1e12
@@ -383,7 +562,8 @@ def main():
     roof.update({"kernel": "K-step RK4 stage (k_kstage_*)", "avg_launch_ms": round(avg * 1e3, 4),
                  "launches": ks_n, "algorithmic_flops_per_launch": flops,
                  "algorithmic_bytes_per_launch": nbytes,
-                 "hbm_frac": round(frac_hbm, 4), "mfma_frac": round(frac_mfma, 4)})
+                 "hbm_frac": round(frac_hbm, 4), "mfma_frac": round(frac_mfma, 4),
+                 "frac_incl_differences": round(flops_all / avg / 1e12 / peak, 4)})
     g = problem.grid
     out = {
         "metric": METRIC,
@@ -406,6 +586,7 @@ def main():
             "cells": g.n, "moments": problem.m, "rank": o.r, "energy_steps_total": o.n_steps,
             "timed_steps": f"0..{K - 1}", "mean_rk4_substeps": round(sum(nsub) / len(nsub), 3),
         },
+        "rk4_substeps_per_s": round(sum(nsub) / wall, 2),
         "event_ms_per_step": round(ev0.elapsed_time(ev1) / K, 3),
         "raytrace_ms": round(1000.0 * t_ray, 2),
         "raytrace_kernel_ms": round(prof_ray[0], 2),
@@ -416,11 +597,14 @@ def main():
                         if warm_prof is not None else None),
         "kstage_timing": "one event pair per step around its RK4 loop (launch gaps included)",
         "roofline": roof,
+        "raytrace_roofline": raytrace_roofline(problem, ray_work, prof_ray[0]),
     }
+    if args.fp64_check:
+        out["mixed_vs_fp64"] = fp64_check(problem, K, s_dose)
     if not args.no_cpu_baseline and args.config == "c3":
-        out["cpu_baseline"] = cpu_baseline(problem)
+        out["cpu_baseline"] = cpu_baseline(problem, window=range(K))
     elif not args.no_cpu_baseline:
-        out["cpu_baseline"] = None
+        out["cpu_baseline"] = cpu_baseline_2d(problem, window=range(K))
     print(json.dumps(out), flush=True)
 
 

@@ -243,6 +243,21 @@ int dlra_set_uncollided(dlra_ctx *ctx, int beam, int step, const double *psibar,
 int dlra_save(dlra_ctx *ctx, void *buf, size_t *bytes);
 int dlra_load(dlra_ctx *ctx, const void *buf, size_t bytes);
 
+/* Work of the last uncollided_raytrace (measurement support): Crank-Nicolson
+ * substeps marched and block factorisations of M - h/2 A, summed over all
+ * rays, and the number of rays.  Synchronous. */
+int dlra_raytrace_work(dlra_ctx *ctx, long long *substeps, long long *factorizations,
+                       long long *rays);
+
+/* Test access (rank replay): the next `count` truncations take the ranks
+ * ranks[0..count) instead of the rank rule, two per energy step (after the
+ * streaming step, then after the uncollided source step), clamped to
+ * [1, min(2r, r_max)]; count = 0 clears the schedule.  In adaptive mode the
+ * rank rule's decisions can flip under rounding-level input changes (a tail
+ * sum at the threshold); replaying another implementation's ranks makes the
+ * two comparable step by step. */
+int dlra_replay_ranks(dlra_ctx *ctx, int count, const int *ranks);
+
 /* Number of RK4 substeps of energy step k (host-side, from dlra_init). */
 int dlra_substeps(dlra_ctx *ctx, int k, int *n_sub);
 

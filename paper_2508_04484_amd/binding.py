@@ -26,7 +26,7 @@ DOSE_UNCOLLIDED, DOSE_COLLIDED, DOSE_PER_MASS, DOSE_ACCUMULATE = 1, 2, 4, 8
 EXPORTS = ["dlra_workspace_size", "dlra_init", "uncollided_raytrace", "dlra_step",
            "dose_deposit", "dlra_get_state", "dlra_set_state", "dlra_get_uncollided",
            "dlra_set_uncollided", "dlra_save", "dlra_load",
-           "dlra_substeps", "dlra_sync", "dlra_profile", "dlra_profile_read", "dlra_run_batch",
+           "dlra_substeps", "dlra_raytrace_work", "dlra_replay_ranks", "dlra_sync", "dlra_profile", "dlra_profile_read", "dlra_run_batch",
            "dlra_plan_objective", "dlra_plan_objective_work", "dlra_destroy", "dlra_last_error"]
 PHASES = ["kstage", "projection", "lstep", "augment", "sstep", "truncate", "collided", "source",
           "step", "raytrace"]
@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
     lib.dlra_save.argtypes = [P, V, C.POINTER(C.c_size_t)]
     lib.dlra_load.argtypes = [P, V, C.c_size_t]
     lib.dlra_substeps.argtypes = [P, I, C.POINTER(I)]
+    lib.dlra_raytrace_work.argtypes = [P] + [C.POINTER(C.c_longlong)] * 3
+    lib.dlra_replay_ranks.argtypes = [P, I, C.POINTER(I)]
     lib.dlra_sync.argtypes = [P]
     lib.dlra_profile.argtypes = [P, I]
     lib.dlra_profile_read.argtypes = [P, I, D, C.POINTER(C.c_longlong)]
@@ -254,6 +256,17 @@ class Solver:
             check(self.lib.dlra_profile_read(self.ctx, i, C.byref(ms), C.byref(cnt)))
             out[name] = (ms.value, cnt.value)
         return out
+
+    def replay_ranks(self, ranks):
+        """Prescribe the ranks of the next truncations (two per energy step)."""
+        arr = (C.c_int * max(len(ranks), 1))(*[int(r) for r in ranks])
+        check(self.lib.dlra_replay_ranks(self.ctx, len(ranks), arr))
+
+    def raytrace_work(self):
+        """(Crank-Nicolson substeps, block factorisations, rays) of the last ray trace."""
+        a, b, c = C.c_longlong(0), C.c_longlong(0), C.c_longlong(0)
+        check(self.lib.dlra_raytrace_work(self.ctx, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
 
     def substeps(self, k):
         v = C.c_int(0)

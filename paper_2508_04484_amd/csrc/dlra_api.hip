@@ -240,6 +240,8 @@ struct dlra_ctx {
   std::vector<double> dtk;     // dt_k = E_k - E_{k+1}
   std::vector<int> n_sub;
   TruncOpt topt;
+  std::vector<int> replay;   // prescribed ranks of the next truncations (test access)
+  size_t replay_pos = 0;
   // rays of every beam
   std::vector<RayParams> rps;
   std::vector<RayGeom> rgeo;
@@ -752,10 +754,18 @@ struct Stepper {
     const int n = d().n, ld = d().ld, P = d().P, m = d().m, R = d().R;
     Ctl *ctl = c->ctl();
     hipStream_t st = c->st;
-    launch_truncate(D(p.Sh), P, kU, kV, r, c->topt, D(p.Pp), D(p.Qp), D(p.Sp), R, ctl, D(p.work),
+    TruncOpt topt = c->topt;
+    int replayed = 0;
+    if (c->replay_pos < c->replay.size()) {
+      // a prescribed rank (clamped like the rule's) replaces the rank rule
+      replayed = std::max(1, std::min(c->replay[c->replay_pos++], std::min(2 * r, R)));
+      topt.fixed = 1;
+      topt.r_fixed = replayed;
+    }
+    launch_truncate(D(p.Sh), P, kU, kV, r, topt, D(p.Pp), D(p.Qp), D(p.Sp), R, ctl, D(p.work),
                     st);
     int r1 = r;
-    if (c->opt.rank_mode == DLRA_RANK_ADAPTIVE) {
+    if (replayed || c->opt.rank_mode == DLRA_RANK_ADAPTIVE) {
       Ctl h;
       HIPCHK(hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -1218,6 +1228,7 @@ int uncollided_raytrace(dlra_ctx *c) {
     HIPCHK(hipMemsetAsync(c->base + p.psibar, 0, size_t(d.n_beams) * d.n_steps * d.n * d.tsize,
                           c->st));
     HIPCHK(hipMemsetAsync(c->base + p.dose_u, 0, size_t(d.n) * 8, c->st));
+    HIPCHK(hipMemsetAsync(&c->ctl()->rt_substeps, 0, 2 * sizeof(unsigned long long), c->st));
     auto go = [&](int b, auto *psib) {
       using T = std::remove_pointer_t<decltype(psib)>;
       launch_raytrace<T>(c->rps[b], c->rgeo[b], c->at<int>(p.rt_rays) + size_t(b) * d.n,
@@ -1227,7 +1238,8 @@ int uncollided_raytrace(dlra_ctx *c) {
                          c->at<double>(p.rt_c0) + size_t(b) * 3 * d.G, c->at<int>(p.rt_g0),
                          c->at<double>(p.rt_sw), c->at<double>(p.rt_stopw),
                          c->at<double>(p.rt_scratch), size_t(d.ray_batch),
-                         psib + size_t(b) * d.n_steps * d.n, c->at<double>(p.dose_u), c->st);
+                         psib + size_t(b) * d.n_steps * d.n, c->at<double>(p.dose_u), c->ctl(),
+                         c->st);
     };
     PhaseTimer t(c, DLRA_PH_RAYTRACE, nullptr, kBoth);
     for (int b = 0; b < d.n_beams; ++b) {
@@ -1378,6 +1390,34 @@ int dlra_load(dlra_ctx *c, const void *buf, size_t bytes) {
   } catch (const std::exception &e) {
     return fail(DLRA_E_HIP, e.what());
   }
+}
+
+int dlra_raytrace_work(dlra_ctx *c, long long *substeps, long long *factorizations,
+                       long long *rays) {
+  if (!c || !substeps || !factorizations || !rays) return fail(DLRA_E_INVALID, "null argument");
+  if (!c->traced) return fail(DLRA_E_STATE, "uncollided_raytrace has not run");
+  try {
+    Ctl h;
+    HIPCHK(hipMemcpyAsync(&h, c->ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    *substeps = (long long)h.rt_substeps;
+    *factorizations = (long long)h.rt_factors;
+    long long nr = 0;
+    for (const RayParams &rp : c->rps) nr += rp.n_rays;
+    *rays = nr;
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  return DLRA_OK;
+}
+
+int dlra_replay_ranks(dlra_ctx *c, int count, const int *ranks) {
+  if (!c || count < 0 || (count > 0 && !ranks)) return fail(DLRA_E_INVALID, "bad arguments");
+  for (int i = 0; i < count; ++i)
+    if (ranks[i] < 1 || ranks[i] > c->d.R) return fail(DLRA_E_INVALID, "rank outside [1, r_max]");
+  c->replay.assign(ranks, ranks + count);
+  c->replay_pos = 0;
+  return DLRA_OK;
 }
 
 int dlra_substeps(dlra_ctx *c, int k, int *n_sub) {

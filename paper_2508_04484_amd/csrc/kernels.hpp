@@ -27,6 +27,8 @@ struct Ctl {
   int flags;      // error bits (kFlag*)
   int pad[3];
   double normsq;  // scratch: squared Frobenius norm of the last augmented matrix
+  unsigned long long rt_substeps;   // ray tracer: Crank-Nicolson substeps marched
+  unsigned long long rt_factors;    // ray tracer: block factorisations
 };
 constexpr int kFlagNonFinite = 1;
 constexpr int kFlagRank = 2;
@@ -192,7 +194,8 @@ void launch_raytrace(const RayParams &rp, const RayGeom &geo, const int *rays,
                      const double *ray_f, const double *w, const double *Adiag,
                      const double *Aup, const double *Alo, const double *mass, const double *c0,
                      const int *step_g0, const double *step_w, const double *stop_w,
-                     double *scratch, size_t batch, T *psibar, double *Du, hipStream_t st);
+                     double *scratch, size_t batch, T *psibar, double *Du, Ctl *ctl,
+                     hipStream_t st);
 
 // min over cells of sum_i w_i S_i(E_k) for every step k
 void launch_min_stop(int n, const double *w, int n_mat, const double *Sk, int n_steps,

@@ -225,7 +225,8 @@ __global__ __launch_bounds__(64) void k_raytrace(
     const double *__restrict__ Alo, const double *__restrict__ mass,
     const double *__restrict__ c0, const int *__restrict__ step_g0,
     const double *__restrict__ step_w, const double *__restrict__ stop_w,
-    double *__restrict__ scratch, size_t B, T *__restrict__ psibar, double *__restrict__ Du) {
+    double *__restrict__ scratch, size_t B, T *__restrict__ psibar, double *__restrict__ Du,
+    Ctl *__restrict__ ctl) {
   const int lr = blockIdx.x * blockDim.x + threadIdx.x;   // ray within the batch
   if (lr >= nray) return;
   const int ray = ray0 + lr;
@@ -248,8 +249,11 @@ __global__ __launch_bounds__(64) void k_raytrace(
       ray_outputs<T>(rp, s, x, f, wv, step_g0, step_w, stop_w, psibar, Du);
       for (int sub = 0; sub < rp.n_half; ++sub) cn_substep(rp, s, wv, Alo, m, hh);
     }
+    atomicAdd(&ctl->rt_substeps, (unsigned long long)(2 * rp.n_half) * rp.row_len);
+    atomicAdd(&ctl->rt_factors, (unsigned long long)rp.row_len);
     return;
   }
+  unsigned long long n_cn = 0, n_fac = 0;
   // oblique ray from the domain entry to the centre of its target cell
   const int xt = rays[ray];
   const int n3[3] = {geo.nx, geo.ny, geo.nz};
@@ -321,12 +325,16 @@ __global__ __launch_bounds__(64) void k_raytrace(
         const double hh = 0.5 * (lens[q] / ns);
         factorise(rp, s, wv, Adiag, Aup, Alo, m, hh);
         for (int sub = 0; sub < ns; ++sub) cn_substep(rp, s, wv, Alo, m, hh);
+        n_cn += ns;
+        ++n_fac;
       }
     }
     a = b;
   }
   for (int i = 0; i < rp.n_mat; ++i) wv[i] = w[size_t(i) * rp.n + xt];
   ray_outputs<T>(rp, s, xt, f, wv, step_g0, step_w, stop_w, psibar, Du);
+  atomicAdd(&ctl->rt_substeps, n_cn);
+  atomicAdd(&ctl->rt_factors, n_fac);
 }
 
 }  // namespace
@@ -336,12 +344,13 @@ void launch_raytrace(const RayParams &rp, const RayGeom &geo, const int *rays,
                      const double *ray_f, const double *w, const double *Adiag,
                      const double *Aup, const double *Alo, const double *mass, const double *c0,
                      const int *step_g0, const double *step_w, const double *stop_w,
-                     double *scratch, size_t batch, T *psibar, double *Du, hipStream_t st) {
+                     double *scratch, size_t batch, T *psibar, double *Du, Ctl *ctl,
+                     hipStream_t st) {
   for (int r0 = 0; r0 < rp.n_rays; r0 += int(batch)) {
     const int nr = std::min<int>(int(batch), rp.n_rays - r0);
     k_raytrace<T><<<(nr + 63) / 64, 64, 0, st>>>(rp, geo, r0, nr, rays, ray_f, w, Adiag, Aup,
                                                   Alo, mass, c0, step_g0, step_w, stop_w,
-                                                  scratch, batch, psibar, Du);
+                                                  scratch, batch, psibar, Du, ctl);
   }
 }
 
@@ -350,12 +359,12 @@ template void launch_raytrace<double>(const RayParams &, const RayGeom &, const 
                                       const double *, const double *, const double *,
                                       const double *, const int *, const double *,
                                       const double *, double *, size_t, double *, double *,
-                                      hipStream_t);
+                                      Ctl *, hipStream_t);
 template void launch_raytrace<float>(const RayParams &, const RayGeom &, const int *,
                                      const double *, const double *, const double *,
                                      const double *, const double *, const double *,
                                      const double *, const int *, const double *,
                                      const double *, double *, size_t, float *, double *,
-                                     hipStream_t);
+                                     Ctl *, hipStream_t);
 
 }  // namespace dlra
