@@ -307,6 +307,21 @@ int dlra_plan_objective(int n_cells, int n_beams, const double *doses, const dou
                         const unsigned char *target, double dhat, double lam, double *work,
                         size_t work_doubles, void *stream, double *J, double *grad);
 
+/* Allocation-free form of dlra_plan_objective, for callers that cannot
+ * allocate device memory or pass a work space (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments and results as dlra_plan_objective without work / work_doubles;
+ * the partial sums of its reduction live in a static device array of the
+ * library (about 300 KB, one per GPU, held until the process ends) instead
+ * of a caller work space, and the residual g(x) is formed per cell inside a
+ * single pass instead of being stored, so n_cells is not limited.  The call
+ * allocates nothing on the device.  Limit: n_beams <= 64 (DLRA_E_INVALID
+ * beyond).  Calls that overlap on one GPU share the array and race; the
+ * call synchronises its stream before it returns. */
+int dlra_plan_objective_noalloc(int n_cells, int n_beams, const double *doses,
+                                const double *weights, const unsigned char *target, double dhat,
+                                double lam, void *stream, double *J, double *grad);
+
 /* Timing of the library's own work with HIP events recorded on the context's
  * stream (measurement support).  Every event record between two kernels
  * leaves the device idle for a few microseconds.

@@ -27,7 +27,8 @@ EXPORTS = ["dlra_workspace_size", "dlra_init", "uncollided_raytrace", "dlra_step
            "dose_deposit", "dlra_get_state", "dlra_set_state", "dlra_get_uncollided",
            "dlra_set_uncollided", "dlra_save", "dlra_load",
            "dlra_substeps", "dlra_raytrace_work", "dlra_replay_ranks", "dlra_sync", "dlra_profile", "dlra_profile_read", "dlra_run_batch",
-           "dlra_plan_objective", "dlra_plan_objective_work", "dlra_destroy", "dlra_last_error"]
+           "dlra_plan_objective", "dlra_plan_objective_work", "dlra_plan_objective_noalloc",
+           "dlra_destroy", "dlra_last_error"]
 PHASES = ["kstage", "projection", "lstep", "augment", "sstep", "truncate", "collided", "source",
           "step", "raytrace"]
 
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.dlra_plan_objective.argtypes = [I, I, V, D, V, C.c_double, C.c_double, V, C.c_size_t, V,
                                         D, D]
     lib.dlra_plan_objective_work.argtypes = [I, I]
+    lib.dlra_plan_objective_noalloc.argtypes = [I, I, V, D, V, C.c_double, C.c_double, V, D, D]
     lib.dlra_destroy.argtypes = [P]
     lib.dlra_destroy.restype = None
     lib.dlra_last_error.restype = C.c_char_p

@@ -1111,6 +1111,37 @@ int load_impl(dlra_ctx *c, const char *buf, size_t bytes) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ static scratch
+// Device memory of dlra_plan_objective_noalloc: the block partials of its
+// reduction and the result row, for up to kPlanMaxBeams beams.  Each GPU the
+// library runs on holds its own copy until the process ends; calls on one GPU
+// share it.
+constexpr size_t kNoallocDoubles = size_t(kPlanBlocks + 64 + 1) * (kPlanMaxBeams + 1) +
+                                   (kPlanMaxBeams + 1);
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the static scratch on the current device, looked up once
+// per device (the array's name is only a host-side stand-in).
+static int noalloc_scratch(double **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(DLRA_E_HIP, "no current HIP device");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(DLRA_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return DLRA_OK;
+}
+
 // ==================================================================== C ABI
 extern "C" {
 
@@ -1497,6 +1528,41 @@ int dlra_plan_objective(int n_cells, int n_beams, const double *doses, const dou
     HIPCHK(hipGetLastError());
     std::vector<double> h(size_t(n_beams) + 1);
     HIPCHK(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *J = h[0];
+    for (int b = 0; b < n_beams; ++b) grad[b] = h[1 + b];
+  } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  return DLRA_OK;
+}
+
+int dlra_plan_objective_noalloc(int n_cells, int n_beams, const double *doses,
+                                const double *weights, const unsigned char *target, double dhat,
+                                double lam, void *stream, double *J, double *grad) {
+  if (n_cells <= 0 || n_beams < 1 || n_beams > kPlanMaxBeams)
+    return fail(DLRA_E_INVALID, "n_cells must be positive and n_beams in [1, 64] (the static "
+                                "scratch holds the partial sums of at most 64 beams)");
+  if (!doses || !weights || !target || !J || !grad) return fail(DLRA_E_INVALID, "null argument");
+  if (!(lam >= 0.0) || !std::isfinite(lam) || !std::isfinite(dhat))
+    return fail(DLRA_E_INVALID, "lam must be finite and >= 0, dhat finite");
+  if (plan_objective_fused_scratch(n_beams) + size_t(n_beams + 1) > kNoallocDoubles)
+    return fail(DLRA_E_INVALID, "static scratch too small");
+  PlanWeights pw{};
+  for (int b = 0; b < n_beams; ++b) {
+    if (!std::isfinite(weights[b])) return fail(DLRA_E_INVALID, "non-finite weight");
+    pw.w[b] = weights[b];
+  }
+  double *buf = nullptr;
+  int rc = noalloc_scratch(&buf);
+  if (rc != DLRA_OK) return rc;
+  try {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *out = buf + plan_objective_fused_scratch(n_beams);
+    launch_plan_objective_fused(n_cells, n_beams, doses, pw, target, dhat, lam, buf, out, st);
+    HIPCHK(hipGetLastError());
+    double h[kPlanMaxBeams + 1];
+    HIPCHK(hipMemcpyAsync(h, out, size_t(n_beams + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     *J = h[0];
     for (int b = 0; b < n_beams; ++b) grad[b] = h[1 + b];

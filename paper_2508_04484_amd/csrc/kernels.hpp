@@ -162,6 +162,14 @@ size_t plan_objective_work(int n, int nb);
 void launch_plan_objective(int n, int nb, const double *doses, const PlanWeights &pw,
                            const unsigned char *target, double dhat, double lam, double *work,
                            double *out, hipStream_t st);
+// the same in one pass over the doses with only block partials as scratch:
+// plan_objective_fused_scratch(nb) doubles, partial rows first; out may lie
+// behind them in the same buffer
+size_t plan_objective_fused_scratch(int nb);
+void launch_plan_objective_fused(int n, int nb, const double *doses, const PlanWeights &pw,
+                                 const unsigned char *target, double dhat, double lam,
+                                 double *scratch, double *out, hipStream_t st);
+
 // ----------------------------------------------------------------- ray tracer
 struct RayParams {
   int G;                 // energy groups

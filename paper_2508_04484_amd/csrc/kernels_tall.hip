@@ -1899,6 +1899,59 @@ void launch_plan_objective(int n, int nb, const double *doses, const PlanWeights
   reduce_partials(partial, nblk, nb + 1, out, st, scratch, size_t(64) * (nb + 1));
 }
 
+// One-pass form: every block forms the residual g(x) of its cells and
+// multiplies it into every beam's dose at once, so no n-sized buffer is
+// needed; per-block arithmetic (cell order, reduction tree) is that of
+// k_plan_residual followed by k_plan_dots.
+__global__ __launch_bounds__(256) void k_plan_fused(int n, int nb, const double *__restrict__ doses,
+                                                    PlanWeights pw,
+                                                    const unsigned char *__restrict__ target,
+                                                    double dhat, double lam, int chunk,
+                                                    double *__restrict__ partial) {
+  __shared__ double red[4][kPlanMaxBeams + 1];
+  const int x0 = blockIdx.x * chunk, x1 = min(n, x0 + chunk);
+  double acc[kPlanMaxBeams + 1];
+#pragma unroll
+  for (int b = 0; b <= kPlanMaxBeams; ++b) acc[b] = 0.0;
+  for (int x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
+    double D = 0.0;
+    for (int b = 0; b < nb; ++b) D += pw.w[b] * doses[size_t(b) * n + x];
+    const bool in = target[x] != 0;
+    const double e = in ? D - dhat : D;
+    acc[0] += in ? e * e : lam * e * e;
+    const double g = in ? 2.0 * e : 2.0 * lam * e;
+#pragma unroll
+    for (int b = 0; b < kPlanMaxBeams; ++b)
+      if (b < nb) acc[1 + b] += g * doses[size_t(b) * n + x];
+  }
+#pragma unroll
+  for (int b = 0; b <= kPlanMaxBeams; ++b) {
+    if (b <= nb) {
+      double v = acc[b];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][b] = v;
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b <= nb; b += blockDim.x)
+    partial[size_t(blockIdx.x) * (nb + 1) + b] = (red[0][b] + red[1][b]) + (red[2][b] + red[3][b]);
+}
+
+size_t plan_objective_fused_scratch(int nb) {
+  return size_t(kPlanBlocks + 64 + 1) * size_t(nb + 1);
+}
+
+void launch_plan_objective_fused(int n, int nb, const double *doses, const PlanWeights &pw,
+                                 const unsigned char *target, double dhat, double lam,
+                                 double *scratch, double *out, hipStream_t st) {
+  const int nblk = plan_blocks(n);
+  const int chunk = (n + nblk - 1) / nblk;
+  double *partial = scratch;
+  double *seg = partial + size_t(nblk) * (nb + 1);
+  k_plan_fused<<<nblk, 256, 0, st>>>(n, nb, doses, pw, target, dhat, lam, chunk, partial);
+  reduce_partials(partial, nblk, nb + 1, out, st, seg, size_t(64) * (nb + 1));
+}
+
 #define DLRA_INSTANTIATE(T, Acc)                                                              \
   template void launch_inverse_stop<T>(const GridDev &, const T *, int, const double *, T *,  \
                                        Ctl *, hipStream_t);                                   \
