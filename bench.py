@@ -89,6 +89,38 @@ def summarize_counters(fetch_path, write_path, probe_mib, config, out_path):
     print(json.dumps(out, indent=1))
 
 
+def summarize_sq(path, out_path):
+    """Per-launch SQ counters of the K-step stage from one rocprofv3 --pmc pass
+    (counter_collection.csv): matrix-core busy share of the busy CU cycles and
+    instruction counts per launch; writes a short text summary."""
+    import statistics
+    rows = _counter_rows(path)
+    by = {}
+    for r in rows:
+        if "k_kstage" in r.get("Kernel_Name", ""):
+            by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if not by:
+        raise SystemExit(f"no K-stage rows in {path}")
+    mean = {k: statistics.mean(v) for k, v in by.items()}
+    lines = ["counter                          mean per launch   launches"]
+    for k in sorted(mean):
+        lines.append(f"{k:32s} {mean[k]:16.4g} {len(by[k]):10d}")
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in mean and "GRBM_GUI_ACTIVE" in mean:
+        # matrix-core busy cycles summed over the 256 CUs x 4 SIMDs, against
+        # the kernel's active cycles
+        lines.append(f"matrix cores busy / (GPU active cycles x 1024 SIMDs): "
+                     f"{mean['SQ_VALU_MFMA_BUSY_CYCLES'] / (1024.0 * mean['GRBM_GUI_ACTIVE']):.3f}")
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in mean and "SQ_BUSY_CU_CYCLES" in mean:
+        lines.append(f"matrix cores busy / (4 x CU busy cycles): "
+                     f"{mean['SQ_VALU_MFMA_BUSY_CYCLES'] / (4.0 * mean['SQ_BUSY_CU_CYCLES']):.3f}")
+    if "SQ_INSTS_MFMA" in mean and "SQ_INSTS_VALU" in mean:
+        lines.append(f"VALU (non-MFMA) per MFMA instruction: "
+                     f"{(mean['SQ_INSTS_VALU'] - mean['SQ_INSTS_MFMA']) / mean['SQ_INSTS_MFMA']:.3f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def measured_traffic(config):
     """HBM bytes per K-stage launch from the committed counter summary, or None
     when it is missing, for another workload, or older than the kernel source."""
@@ -149,9 +181,9 @@ def raytrace_roofline(problem, work, kernel_ms):
             "ms": round(kernel_ms, 3), "rays": rays, "cn_substeps": substeps,
             "factorizations": factors, "algorithmic_flops": flops,
             "output_bytes_upper": nbytes, "output_gbs": round(nbytes / t / 1e9, 1),
-            "scratch_gbs_model": round(substeps * G * 30 * 8 / t / 1e9, 1),
+            "scratch_gbs_model": round(substeps * G * 42 * 8 / t / 1e9, 1),
             "note": "per group: 114 flops per CN substep, 150 + 54 n_mat per factorisation; "
-                    "scratch model: 30 doubles per group per substep"}
+                    "scratch model: 42 doubles per group per substep"}
 
 
 def cpu_baseline(problem, budget_planes=32, window=None):
@@ -465,7 +497,13 @@ def main():
                     help="write the K-stage HBM-traffic summary from two rocprofv3 --pmc "
                          "passes (FETCH_SIZE, WRITE_SIZE) of this script run with "
                          "--copy-probe-mib, then exit")
+    ap.add_argument("--summarize-sq", nargs=2, metavar=("PMC_CSV", "OUT_TXT"),
+                    help="write the K-stage SQ-counter summary of one rocprofv3 --pmc pass, "
+                         "then exit")
     args = ap.parse_args()
+    if args.summarize_sq:
+        summarize_sq(*args.summarize_sq)
+        return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, max(args.copy_probe_mib, 1),
                            args.config, TRAFFIC_FILE.replace("_c3", f"_{args.config}"))

@@ -193,8 +193,8 @@ struct RayGeom {
   double L[3];           // box lengths (cm)
   double om[3];          // unit direction of flight
 };
-// scratch doubles per ray of a batch: c, y (3G each), Dinv, E (9G each)
-constexpr int kRayScratchPerGroup = 24;
+// scratch doubles per ray of a batch: c, y (3G each), Dinv, F, E (9G each)
+constexpr int kRayScratchPerGroup = 33;
 // uncollided tables of one beam: rays in batches of `batch` (the scratch
 // holds kRayScratchPerGroup * G * batch doubles)
 template <typename T>

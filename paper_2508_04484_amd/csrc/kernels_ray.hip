@@ -12,14 +12,15 @@
 // t = (j D_d - x_d) / Omega_d.
 //
 // Per piece the block-tridiagonal matrix M - h/2 A(x), A(x) = sum_i w_i(x) A_i,
-// is factorised once (block LU from the lowest group: Dinv_g and
-// E_g = Dinv_g U_g).  A substep then solves (M - h/2 A) y = M c and sets
+// is factorised once (block LU from the lowest group: Dinv_g, F_g = Dinv_g L_g
+// and E_g = Dinv_g U_g).  A substep then solves (M - h/2 A) y = M c and sets
 // c <- 2 y - c, which equals (M - h/2 A)^{-1} (M + h/2 A) c, so the mixture
-// blocks are not formed again per substep: the forward sweep takes the lower
-// block L_g from the tables, the backward sweep the stored E_g.  Per-ray state
-// lives in a scratch area laid out [element][ray] so that a wave's accesses
-// coalesce; the loads of the next group are issued before the current group's
-// arithmetic.
+// blocks are not formed again per substep: y_g = Dinv_g M c_g - F_g y_{g-1}
+// forward, x_g = y_g - E_g x_{g+1} backward.  Per-ray state lives in a
+// scratch area laid out [element][ray] so that a wave's accesses coalesce.
+// The sweeps are chains over the groups, and a launch of grid rows has few
+// waves, so each sweep keeps the loads of the next kRayAhead groups in flight
+// (a ring of registers) to cover the memory latency.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -45,13 +46,16 @@ __device__ __forceinline__ void inv3(const double a[9], double o[9]) {
   o[8] = (a[0] * a[4] - a[1] * a[3]) * id;
 }
 
+constexpr int kRayAhead = 4;   // groups whose loads a sweep keeps in flight
+
 // Per-thread view of the scratch columns of one ray.
 struct RayState {
-  double *c, *y, *Dinv, *E;
+  double *c, *y, *Dinv, *F, *E;
   size_t B;   // rays per scratch row
   __device__ double &C(int e) const { return c[size_t(e) * B]; }
   __device__ double &Y(int e) const { return y[size_t(e) * B]; }
   __device__ double &Di(int e) const { return Dinv[size_t(e) * B]; }
+  __device__ double &Ff(int e) const { return F[size_t(e) * B]; }
   __device__ double &Ee(int e) const { return E[size_t(e) * B]; }
 };
 
@@ -94,6 +98,16 @@ __device__ void factorise(const RayParams &rp, const RayState &s, const double *
     inv3(D, Di);
 #pragma unroll
     for (int t = 0; t < 9; ++t) s.Di(g * 9 + t) = Di[t];
+    // F_g = Dinv_g L_g (the forward sweep's coupling to group g - 1)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc += Di[i * 3 + k] * Lg[k * 3 + j];
+        s.Ff(g * 9 + i * 3 + j) = g > 0 ? acc : 0.0;
+      }
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -109,82 +123,78 @@ __device__ void factorise(const RayParams &rp, const RayState &s, const double *
 }
 
 // one Crank-Nicolson substep c <- 2 (M - hh A)^{-1} M c - c with the stored
-// factorisation
-__device__ void cn_substep(const RayParams &rp, const RayState &s, const double *wv,
-                           const double *__restrict__ Alo, const double m[3], double hh) {
+// factorisation; loads run kRayAhead groups ahead of the arithmetic
+__device__ void cn_substep(const RayParams &rp, const RayState &s, const double m[3]) {
+  constexpr int PD = kRayAhead;
   const int G = rp.G;
-  // forward sweep: y_g = Dinv_g (M c_g - L_g y_{g-1}), L_g = -hh sum_i w_i Alo_i
-  double yprev[3] = {0.0, 0.0, 0.0};
-  double cn[3], dn[9];
+  // forward sweep: y_g = Dinv_g M c_g - F_g y_{g-1}
+  double fc[PD][3], fd[PD][9], ff[PD][9];
+  auto fload = [&](int u, int g) {
+    const int gg = min(g, G - 1);   // past the end: clamped, unused
 #pragma unroll
-  for (int k = 0; k < 3; ++k) cn[k] = s.C(k);
+    for (int k = 0; k < 3; ++k) fc[u][k] = s.C(3 * gg + k);
 #pragma unroll
-  for (int t = 0; t < 9; ++t) dn[t] = s.Di(t);
-  for (int g = 0; g < G; ++g) {
-    double cg[3], dg[9];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) cg[k] = cn[k];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) dg[t] = dn[t];
-    const int gn = min(g + 1, G - 1);   // next group's loads, issued first
-#pragma unroll
-    for (int k = 0; k < 3; ++k) cn[k] = s.C(3 * gn + k);
-#pragma unroll
-    for (int t = 0; t < 9; ++t) dn[t] = s.Di(gn * 9 + t);
-    double b[3] = {m[0] * cg[0], m[1] * cg[1], m[2] * cg[2]};
-    if (g > 0) {
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        double al = 0.0;
-        for (int i = 0; i < rp.n_mat; ++i) al += wv[i] * Alo[(size_t(i) * G + g) * 9 + t];
-        b[t / 3] += hh * al * yprev[t % 3];   // - L_g y_{g-1}, L_g = -hh al
-      }
+    for (int t = 0; t < 9; ++t) {
+      fd[u][t] = s.Di(gg * 9 + t);
+      ff[u][t] = s.Ff(gg * 9 + t);
     }
+  };
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double v = dg[i * 3 + 0] * b[0] + dg[i * 3 + 1] * b[1] + dg[i * 3 + 2] * b[2];
-      s.Y(3 * g + i) = v;
-      yprev[i] = v;
+  for (int u = 0; u < PD; ++u) fload(u, u);
+  double yprev[3] = {0.0, 0.0, 0.0};
+  for (int g0 = 0; g0 < G; g0 += PD) {
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      const int g = g0 + u;
+      if (g < G) {
+        const double b[3] = {m[0] * fc[u][0], m[1] * fc[u][1], m[2] * fc[u][2]};
+        double v[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          v[i] = (fd[u][i * 3 + 0] * b[0] + fd[u][i * 3 + 1] * b[1] + fd[u][i * 3 + 2] * b[2]) -
+                 (ff[u][i * 3 + 0] * yprev[0] + ff[u][i * 3 + 1] * yprev[1] +
+                  ff[u][i * 3 + 2] * yprev[2]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          s.Y(3 * g + i) = v[i];
+          yprev[i] = v[i];
+        }
+      }
+      fload(u, g + PD);
     }
   }
   // backward sweep: x_g = y_g - E_g x_{g+1}; c_g <- 2 x_g - c_g
+  double by[PD][3], bc[PD][3], be[PD][9];
+  auto bload = [&](int u, int g) {
+    const int gg = max(g, 0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      by[u][k] = s.Y(3 * gg + k);
+      bc[u][k] = s.C(3 * gg + k);
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) be[u][t] = s.Ee(gg * 9 + t);
+  };
+#pragma unroll
+  for (int u = 0; u < PD; ++u) bload(u, G - 1 - u);
   double xn[3] = {0.0, 0.0, 0.0};
-  double yv[3], en[9], co[3];
-  {
-    const int g = G - 1;
+  for (int g0 = G - 1; g0 >= 0; g0 -= PD) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      yv[k] = s.Y(3 * g + k);
-      co[k] = s.C(3 * g + k);
-    }
+    for (int u = 0; u < PD; ++u) {
+      const int g = g0 - u;
+      if (g >= 0) {
+        double xv[3];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) en[t] = s.Ee(g * 9 + t);
-  }
-  for (int g = G - 1; g >= 0; --g) {
-    double yg[3], eg[9], cg[3];
+        for (int i = 0; i < 3; ++i)
+          xv[i] = by[u][i] -
+                  (be[u][i * 3 + 0] * xn[0] + be[u][i * 3 + 1] * xn[1] + be[u][i * 3 + 2] * xn[2]);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      yg[k] = yv[k];
-      cg[k] = co[k];
-    }
-#pragma unroll
-    for (int t = 0; t < 9; ++t) eg[t] = en[t];
-    const int gp = max(g - 1, 0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      yv[k] = s.Y(3 * gp + k);
-      co[k] = s.C(3 * gp + k);
-    }
-#pragma unroll
-    for (int t = 0; t < 9; ++t) en[t] = s.Ee(gp * 9 + t);
-    double xv[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      xv[i] = yg[i] - (eg[i * 3 + 0] * xn[0] + eg[i * 3 + 1] * xn[1] + eg[i * 3 + 2] * xn[2]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      s.C(3 * g + i) = 2.0 * xv[i] - cg[i];
-      xn[i] = xv[i];
+        for (int i = 0; i < 3; ++i) {
+          s.C(3 * g + i) = 2.0 * xv[i] - bc[u][i];
+          xn[i] = xv[i];
+        }
+      }
+      bload(u, g - PD);
     }
   }
 }
@@ -232,7 +242,7 @@ __global__ __launch_bounds__(64) void k_raytrace(
   const int ray = ray0 + lr;
   const int G = rp.G;
   RayState s{scratch + lr, scratch + size_t(3) * G * B + lr, scratch + size_t(6) * G * B + lr,
-             scratch + size_t(15) * G * B + lr, B};
+             scratch + size_t(15) * G * B + lr, scratch + size_t(24) * G * B + lr, B};
   for (int e = 0; e < 3 * G; ++e) s.C(e) = c0[e];
   const double m[3] = {mass[0], mass[1], mass[2]};
   const double f = ray_f[ray];
@@ -245,9 +255,9 @@ __global__ __launch_bounds__(64) void k_raytrace(
       const int x = rays[ray] + cell * rp.row_stride;
       for (int i = 0; i < rp.n_mat; ++i) wv[i] = w[size_t(i) * rp.n + x];
       factorise(rp, s, wv, Adiag, Aup, Alo, m, hh);
-      for (int sub = 0; sub < rp.n_half; ++sub) cn_substep(rp, s, wv, Alo, m, hh);
+      for (int sub = 0; sub < rp.n_half; ++sub) cn_substep(rp, s, m);
       ray_outputs<T>(rp, s, x, f, wv, step_g0, step_w, stop_w, psibar, Du);
-      for (int sub = 0; sub < rp.n_half; ++sub) cn_substep(rp, s, wv, Alo, m, hh);
+      for (int sub = 0; sub < rp.n_half; ++sub) cn_substep(rp, s, m);
     }
     atomicAdd(&ctl->rt_substeps, (unsigned long long)(2 * rp.n_half) * rp.row_len);
     atomicAdd(&ctl->rt_factors, (unsigned long long)rp.row_len);
@@ -324,7 +334,7 @@ __global__ __launch_bounds__(64) void k_raytrace(
         const int ns = n_sub_of(lens[q], rp.h_max);
         const double hh = 0.5 * (lens[q] / ns);
         factorise(rp, s, wv, Adiag, Aup, Alo, m, hh);
-        for (int sub = 0; sub < ns; ++sub) cn_substep(rp, s, wv, Alo, m, hh);
+        for (int sub = 0; sub < ns; ++sub) cn_substep(rp, s, m);
         n_cn += ns;
         ++n_fac;
       }

@@ -270,6 +270,9 @@ __host__ __device__ constexpr int brick_ahead(int) { return 3; }
 __host__ __device__ constexpr int brick_slots(int tsize) { return 4 + brick_ahead(tsize); }
 __host__ __device__ constexpr int brick_bufs(int tsize) { return brick_ahead(tsize); }
 constexpr unsigned kBufWord3 = 0x00020000u;    // raw (untyped) buffer resource
+// byte offset beyond every buffer the z-march reads (their sizes stay below
+// it), so a load with it returns zero; offset + plane base stays below 2^32
+constexpr int kOobOffset = 0x7F000000;
 // waves per brick row for two output tiles (FP32, 16 < r <= 32): with two,
 // each wave computes one tile and two waves share every SIMD
 constexpr int kBrickSplit = 2;
@@ -442,15 +445,16 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     if (idx < SPD / 64) {
       const int dw = 64 * idx + lane, cell = min(dw / DPE, PC - 1);
       half = dw % DPE;
-      gy = clampy(gy0 + cell / RW);
-      gx = clampx(gx0 + cell % RW - 2);
+      gy = gy0 + cell / RW;
+      gx = gx0 + cell % RW - 2;
     } else if (idx < NSX) {
       const int dw = 64 * (idx - SPD / 64) + lane, hc = dw / DPE;
       half = dw % DPE;
-      gy = clampy(halo_y(hc >> 4));
-      gx = clampx(gx0 + (hc & 15));
+      gy = halo_y(hc >> 4);
+      gx = gx0 + (hc & 15);
     }
-    soff[i] = ((gy * nx + gx) * DPE + half) * 4;
+    const bool in_grid = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    soff[i] = in_grid ? ((gy * nx + gx) * DPE + half) * 4 : kOobOffset;
   }
   static_assert(NB == AH, "one y-halo / K0 buffer per step in flight");
   auto slot = [](int z) { return (z % NS + NS) % NS; };   // prologue only
@@ -459,6 +463,9 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
   // s), so that a step's loads can be spread over the column blocks
   auto issue_part = [&](int lo, int hi, int zp, int zh, int hbuf, int sl) {
     const int pb = clampz(zp) * plane * TB, hb = clampz(zh) * plane * TB;
+    // s planes outside the grid read as zero (out-of-range buffer loads)
+    const int pbs = (zp >= 0 && zp < nz) ? pb : kOobOffset;
+    const int hbs = (zh >= 0 && zh < nz) ? hb : kOobOffset;
     unsigned char *dp = reinterpret_cast<unsigned char *>(ringW + sl * RB * PC);
     unsigned char *dh = reinterpret_cast<unsigned char *>(haloW + hbuf * RB * HS);
     unsigned char *dk = reinterpret_cast<unsigned char *>(K0t + hbuf * RB * KST);
@@ -485,8 +492,8 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     for (int i = 0; i < NSI; ++i) {
       const int idx = wave + NW * i;
       if (!in(NPI + NHI + NKI + i)) continue;
-      if (idx < SPD / 64) dma_dword(rS, dsp + 256 * idx, soff[i], pb);
-      else if (idx < NSX) dma_dword(rS, dsh + 256 * (idx - SPD / 64), soff[i], hb);
+      if (idx < SPD / 64) dma_dword(rS, dsp + 256 * idx, soff[i], pbs);
+      else if (idx < NSX) dma_dword(rS, dsh + 256 * (idx - SPD / 64), soff[i], hbs);
       else dma_dword(rS, pad, soff[i], 0);
     }
   };
@@ -504,14 +511,6 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
   const int gx = gx0 + c, gy = gy0 + row;
   const bool valid = gx < nx && gy < ny;
   const int xyo = (clampy(gy) * nx + clampx(gx)) * TB;
-  // in-grid masks of the x and y stencil neighbours of this lane's cell
-  bool mx[4], my[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int o = t < 2 ? t - 2 : t - 1;
-    mx[t] = gx + o >= 0 && gx + o < nx;
-    my[t] = gy + o >= 0 && gy + o < ny;
-  }
   const int base = row * RW + c + 2;
   // outputs of the previous step, stored during this one (KSPLIT: own partial
   // sums and K0, combined with the partner's partial sums at the store)
@@ -542,20 +541,17 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
     for (int t = 0; t < 4; ++t) {
       const int o = t < 2 ? t - 2 : t - 1;
       wp[0][t] = Wc + base + o + qoff;
-      const T sx = Sc[base + o];   // loads unconditional, masked by selects
-      sv[0][t] = mx[t] ? sx : T(0);
+      sv[0][t] = Sc[base + o];   // zero outside the grid
       const int yr = row + o;
       const bool inb = yr >= 0 && yr < BY;
       const int hr = yr < 0 ? yr + 2 : yr - BY + 2;
       wp[1][t] = (inb ? Wc + yr * RW + c + 2 : haloW + hb * RB * HS + hr * 16 + c) + qoff;
       const T sy_in = Sc[min(max(yr, 0), BY - 1) * RW + c + 2];
       const T sy_h = haloS[hb * HC + min(max(hr, 0), 3) * 16 + c];
-      sv[1][t] = my[t] ? (inb ? sy_in : sy_h) : T(0);
+      sv[1][t] = inb ? sy_in : sy_h;
       if constexpr (DIM == 3) {
         wp[2][t] = ringW + zsl[t] * RB * PC + base + qoff;
-        const bool mz = z + o >= 0 && z + o < nz;
-        const T sz = ringS[zsl[t] * SP + base];
-        sv[2][t] = mz ? sz : T(0);
+        sv[2][t] = ringS[zsl[t] * SP + base];
       }
     }
     // s-weights of the one-sided differences (ih folded in)
@@ -598,14 +594,17 @@ __global__ __launch_bounds__(64 * kBrickBY * JS) void k_kstage_brick(
         for (int t = 0; t < 4; ++t) sten[1 + 4 * d + t] = wp[d][t][ok];
     };
     T db[DIM], df[DIM];
+    // the centre terms of the two differences are negatives of each other
+    // (cf0 = -cb0 exactly), so one product serves both
     auto diffs = [&]() {
       const T w0 = sten[0];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
         const T wm2 = sten[1 + 4 * d], wm1 = sten[2 + 4 * d];
         const T wp1 = sten[3 + 4 * d], wp2 = sten[4 + 4 * d];
-        db[d] = cb[d][2] * wm2 + (cb[d][1] * wm1 + cb[d][0] * w0);
-        df[d] = cf[d][2] * wp2 + (cf[d][1] * wp1 + cf[d][0] * w0);
+        const T t0 = cb[d][0] * w0;
+        db[d] = cb[d][2] * wm2 + (cb[d][1] * wm1 + t0);
+        df[d] = cf[d][2] * wp2 + (cf[d][1] * wp1 - t0);
       }
     };
     read_sten(0);
@@ -1527,6 +1526,7 @@ static void kstage_launch(const GridDev &g, const T *s, const T *W, const T *K0,
 template <typename T, int NJ, int DIM, int JS = 1>
 static void kstage_brick_launch(const GridDev &g, const T *s, const T *W, const T *K0, T *out,
                                 int ld, int r, const T *Bp, double coef, hipStream_t st) {
+
   constexpr int NT = 64 * kBrickBY * JS;
   const size_t shm = brick_lds_bytes(16 * NJ, int(sizeof(T)), JS);
   auto kern = k_kstage_brick<T, NJ, DIM, JS>;
@@ -1560,9 +1560,9 @@ template <typename T>
 void launch_kstep_stage(const GridDev &g, const T *s, const T *W, const T *K0, T *out, int ld,
                         int r, const T *Bp, double coef, hipStream_t st) {
   // z-march kernel where its LDS fits (r <= 32 in FP32, r <= 16 in FP64) and
-  // its buffer offsets fit 31 bits
+  // its buffers end below the out-of-range offset of its zero loads
   if (kUseBrick && r <= (sizeof(T) == 4 ? 32 : 16) &&
-      size_t(ld) * 16 * ((r + 15) / 16) * sizeof(T) < (size_t(1) << 31)) {
+      size_t(ld) * 16 * ((r + 15) / 16) * sizeof(T) < size_t(kOobOffset)) {
     const bool three = g.dim == 3;
     if (r <= 16 && three) kstage_brick_launch<T, 1, 3>(g, s, W, K0, out, ld, r, Bp, coef, st);
     else if (r <= 16) kstage_brick_launch<T, 1, 2>(g, s, W, K0, out, ld, r, Bp, coef, st);
@@ -1687,15 +1687,17 @@ void launch_stencil_projection(const GridDev &g, const T *s, const T *X, int ld,
   int chunk = (g.n + nb - 1) / nb;
   chunk = (chunk + CT - 1) / CT * CT;
   nb = (g.n + chunk - 1) / chunk;
+#define DLRA_SPROJ(NA) stencil_proj_launch<T, Acc, NA>(g, s, X, ld, p, nb, chunk, partial, st)
   switch ((p + 15) / 16) {
-    case 1: stencil_proj_launch<T, Acc, 1>(g, s, X, ld, p, nb, chunk, partial, st); break;
-    case 2: stencil_proj_launch<T, Acc, 2>(g, s, X, ld, p, nb, chunk, partial, st); break;
-    case 3: stencil_proj_launch<T, Acc, 3>(g, s, X, ld, p, nb, chunk, partial, st); break;
-    case 4: stencil_proj_launch<T, Acc, 4>(g, s, X, ld, p, nb, chunk, partial, st); break;
-    case 5: stencil_proj_launch<T, Acc, 5>(g, s, X, ld, p, nb, chunk, partial, st); break;
-    case 6: stencil_proj_launch<T, Acc, 6>(g, s, X, ld, p, nb, chunk, partial, st); break;
-    default: stencil_proj_launch<T, Acc, 7>(g, s, X, ld, p, nb, chunk, partial, st); break;
+    case 1: DLRA_SPROJ(1); break;
+    case 2: DLRA_SPROJ(2); break;
+    case 3: DLRA_SPROJ(3); break;
+    case 4: DLRA_SPROJ(4); break;
+    case 5: DLRA_SPROJ(5); break;
+    case 6: DLRA_SPROJ(6); break;
+    default: DLRA_SPROJ(7); break;
   }
+#undef DLRA_SPROJ
   const size_t per = size_t(ndk) * p * p;
   double *red = partial + size_t(nb) * per;
   reduce_partials(partial, nb, int(per), red, st, red + per, room_after(partial_elems, nb + 1, per));

@@ -124,17 +124,41 @@ def test_mixed_precision_dose(name):
 
 
 def test_c1_water_full_run():
-    # 64x64 water, 70 MeV, P_7, rank 10, 100 energy steps, FP64
+    # 64x64 water, 70 MeV, P_7, rank 10, 100 energy steps, FP64.  The fixed
+    # rank cuts through a cluster of singular values (1, 0.1, 0.03 .. 0.01), so
+    # this run amplifies rounding: scaling every entry of the reference's
+    # uncollided tables by 1 + 1e-15 noise moves the reference's own dose by
+    # 4e-11, and two exact implementations end about 1e-10 apart.  Every step
+    # is therefore compared starting from the reference's own state (on the
+    # reference's tables) at the injected-state bar, and the whole chain, with
+    # the library's ray tracer, at 1e-8.
     dl = _gpu()
     p = configs.c1()
     say("c1 full run")
+    states = []
+    want = ref.run_beam_dlra(p, p.beams[0], callback=lambda k, st: states.append(st))
+    s = dl.BeamSolver(p, 0)
+    for k in range(p.options.n_steps):
+        s.set_uncollided(0, k, want["psibar"][k], want["dose_u"] if k == 0 else None)
+    prev = dlra.initial_state(p, coeffs.step_coeffs(p, p.beams[0], 0).g)
+    worst = 0.0
+    for k in range(p.options.n_steps):
+        s.set_state(prev.U, prev.S, prev.V, k)
+        s.step(sync=True)
+        U, S, V, _ = s.state()
+        err, nrm = _fro_diff(U, S, V, states[k].U, states[k].S, states[k].V)
+        worst = max(worst, err / nrm)
+        prev = states[k]
+    s.close()
     s = dl.BeamSolver(p, 0)
     s.raytrace()
     s.run()
-    dose = s.dose().cpu().numpy()
-    want = ref.run_beam_dlra(p, p.beams[0])
-    assert rel(dose, want["dose"]) <= 1e-10
+    end_to_end = rel(s.dose().cpu().numpy(), want["dose"])
     s.close()
+    say(f"  worst single-step rel Frobenius error {worst:.3e}; rel-L2 dose error "
+        f"{end_to_end:.3e} over the whole run with the library's ray tracer")
+    assert worst <= 1e-11
+    assert end_to_end <= 1e-8
 
 
 def test_call_order_and_arguments():
@@ -215,11 +239,21 @@ def test_mixed_precision_rank_edges(name):
 
 
 def _fro_diff(U1, S1, V1, U2, S2, V2):
-    """||U1 S1 V1^T - U2 S2 V2^T||_F and ||U2 S2 V2^T||_F from r x r traces."""
-    a2 = np.trace((U1.T @ U1) @ S1 @ (V1.T @ V1) @ S1.T)
-    b2 = np.trace((U2.T @ U2) @ S2 @ (V2.T @ V2) @ S2.T)
-    ab = np.trace((U1.T @ U2) @ S2 @ (V2.T @ V1) @ S1.T)
-    return float(np.sqrt(max(a2 + b2 - 2.0 * ab, 0.0))), float(np.sqrt(b2))
+    """||U1 S1 V1^T - U2 S2 V2^T||_F and ||U2 S2 V2^T||_F without forming the
+    n x m products: with [U1 U2] = Qu Ru and [V1 V2] = Qv Rv (thin QR) the
+    difference is Qu Ru diag(S1, -S2) Rv^T Qv^T, whose norm is that of the
+    small middle factor (accurate to rounding relative to the factors, unlike
+    the expansion by traces, which cancels at ~1e-8 of the norm)."""
+    r1, r2 = S1.shape[0], S2.shape[0]
+    _, Ru = np.linalg.qr(np.hstack([U1, U2]))
+    _, Rv = np.linalg.qr(np.hstack([V1, V2]))
+    M = np.zeros((r1 + r2, r1 + r2))
+    M[:r1, :r1] = S1
+    M[r1:, r1:] = -S2
+    diff = np.linalg.norm(Ru @ M @ Rv.T)
+    _, Ru2 = np.linalg.qr(U2)
+    _, Rv2 = np.linalg.qr(V2)
+    return float(diff), float(np.linalg.norm(Ru2 @ S2 @ Rv2.T))
 
 
 @pytest.mark.parametrize("k", [100, 245])
@@ -290,49 +324,52 @@ def test_profile_levels():
     s.close()
 
 
-@pytest.mark.skip(reason="single c2 steps from the reference's own states differ from it by ~1e-7 "
-                         "(diagnosis in progress; seeded random states agree to 1e-14)")
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_c2_opening_steps(precision):
     # c2 as configured (200 x 200 cells of 0.5 mm, bone and lung slabs, P_21:
-    # 484 moments, adaptive rank <= 40, 300-step grid), the first 24 energy
-    # steps against the reference (its full run takes too long for a test).
-    # The adaptive rank rule is at its threshold here: the reference itself
-    # ends at rank 26 instead of 25, with a dose 4.5e-5 apart, when its
-    # densities change by 1e-14 relative.  So the library replays the
-    # reference's ranks (two truncations per step) for the parity bar, and
-    # the free-running ranks and dose are reported.
+    # 484 moments, adaptive rank <= 40, 300-step grid) over its first 24
+    # energy steps.  Each step starts from the reference's state of the step
+    # before and is compared with the reference's next state: the adaptive
+    # decisions of this run sit at their thresholds (the reference itself ends
+    # at rank 26 instead of 25, with a dose 4.5e-5 apart, when its densities
+    # change by 1e-14 relative), so free-running trajectories of two exact
+    # implementations separate; their ranks and doses are reported.
     dl = _gpu()
     p = configs.c2(precision=precision)
     K = 24
     say(f"c2 opening {K} steps, {precision}")
     p64 = p.with_options(precision="fp64")
-    want = ref.run_beam_dlra(p64, p64.beams[0], n_steps=K)
-    ranks = [r for l in want["state"].log for r in (l["r_half"], l["r"])]
+    states = []
+    want = ref.run_beam_dlra(p64, p64.beams[0], n_steps=K,
+                             callback=lambda k, st: states.append(st))
+    st0 = dlra.initial_state(p64, coeffs.step_coeffs(p64, p64.beams[0], 0).g)
     s = dl.BeamSolver(p, 0)
     s.raytrace()
     ps, Du = s.uncollided()
-    s.replay_ranks(ranks)
-    s.run(K)
-    dose_c = s.dose(flags=2).cpu().numpy()
-    r = s.state()[0].shape[1]
-    s.close()
     if precision == "fp64":
         ps_ref = want["psibar"]
         assert np.abs(ps - ps_ref).max() <= 1e-12 * np.abs(ps_ref).max()
-    err = rel(dose_c, want["dose_c"])
+    worst = 0.0
+    prev = st0
+    for k in range(K):
+        s.set_state(prev.U, prev.S, prev.V, k)
+        s.step(sync=True)
+        U, S, V, _ = s.state()
+        nxt = states[k]
+        err, nrm = _fro_diff(U, S, V, nxt.U, nxt.S, nxt.V)
+        assert U.shape[1] == nxt.U.shape[1], k
+        worst = max(worst, err / nrm)
+        prev = nxt
+    s.close()
     free = dl.BeamSolver(p, 0)
     free.raytrace()
-    got_free = []
-    for _ in range(K):
-        got_free.append(free.step(sync=True))
+    got_free = [free.step(sync=True) for _ in range(K)]
     dose_free = free.dose(flags=2).cpu().numpy()
     free.close()
-    say(f"  replayed ranks (final {r}): rel-L2 collided dose {err:.3e}; free-running ranks "
-        f"{got_free} vs reference {[l['r'] for l in want['state'].log]}, dose "
+    say(f"  worst single-step rel Frobenius error {worst:.3e}; free-running ranks "
+        f"{got_free} vs reference {[l['r'] for l in want['state'].log]}, collided dose "
         f"{rel(dose_free, want['dose_c']):.3e}")
-    assert r == want["state"].U.shape[1]
-    assert err <= (1e-10 if precision == "fp64" else 1e-4)
+    assert worst <= (1e-10 if precision == "fp64" else 1e-4)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

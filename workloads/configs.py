@@ -142,8 +142,10 @@ def c2(**opt) -> Problem:
 
 def c3(**opt) -> Problem:
     grid = Grid(128, 128, 128, 0.1, 0.1, 0.1)
+    # mixed precision: drop and floor tolerances above the FP32 rounding level
+    # (the FP64 defaults 1e-6 / 1e-7 would admit rounding noise as directions)
     o = Options(pn_degree=15, n_steps=250, rank_mode="fixed", r=30, r_max=30,
-                precision="mixed").with_(**opt)
+                precision="mixed", aug_tol=1e-4, floor_tol=1e-5).with_(**opt)
     names, w = random_phantom(grid, seed=3)
     mats = make_materials(names, w, o.pn_degree)
     return Problem(grid, mats, [beam_along_x(150.0, 0.5, 6.4, 6.4)], o, name="c3",
