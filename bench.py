@@ -158,6 +158,7 @@ def kstage_algorithmic(problem):
 # materials (54 n_mat flops) and forms L E, the 3x3 inverse and Dinv U
 # (150 flops).
 RAY_FLOPS_PER_SUBSTEP_GROUP = 114
+RAY_WAVE_GROUPS = 128   # up to this many groups one wave marches a ray (no scratch)
 
 
 def ray_factor_flops_per_group(n_mat):
@@ -176,14 +177,18 @@ def raytrace_roofline(problem, work, kernel_ms):
     nbytes = out_cells * (problem.options.n_steps * b + 8)
     t = kernel_ms / 1000.0
     achieved = flops / t / 1e12
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": 78.6, "unit": "TFLOP/s",
-            "frac": round(achieved / 78.6, 4), "kernel": "k_raytrace",
-            "ms": round(kernel_ms, 3), "rays": rays, "cn_substeps": substeps,
-            "factorizations": factors, "algorithmic_flops": flops,
-            "output_bytes_upper": nbytes, "output_gbs": round(nbytes / t / 1e9, 1),
-            "scratch_gbs_model": round(substeps * G * 42 * 8 / t / 1e9, 1),
-            "note": "per group: 114 flops per CN substep, 150 + 54 n_mat per factorisation; "
-                    "scratch model: 42 doubles per group per substep"}
+    wave = G <= RAY_WAVE_GROUPS
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": 78.6, "unit": "TFLOP/s",
+           "frac": round(achieved / 78.6, 4),
+           "kernel": "k_raytrace_wave" if wave else "k_raytrace",
+           "ms": round(kernel_ms, 3), "rays": rays, "cn_substeps": substeps,
+           "factorizations": factors, "algorithmic_flops": flops,
+           "output_bytes_upper": nbytes, "output_gbs": round(nbytes / t / 1e9, 1),
+           "note": "per group: 114 flops per CN substep, 150 + 54 n_mat per factorisation "
+                   "(sequential block LU; the wave kernel's cyclic reduction does more)"}
+    if not wave:
+        out["scratch_gbs_model"] = round(substeps * G * 42 * 8 / t / 1e9, 1)
+    return out
 
 
 def cpu_baseline(problem, budget_planes=32, window=None):

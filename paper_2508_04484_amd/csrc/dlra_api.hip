@@ -212,7 +212,8 @@ Plan make_plan(const Dims &d) {
   p.rt_stopw = p.take(d.n_mat * 3 * G * 8);
   p.rt_rays = p.take(size_t(d.n_beams) * n * 4);
   p.rt_f = p.take(size_t(d.n_beams) * n * 8);
-  p.rt_scratch = p.take(size_t(kRayScratchPerGroup) * G * d.ray_batch * 8);
+  p.rt_scratch =
+      p.take(G > size_t(kRayWaveGroups) ? size_t(kRayScratchPerGroup) * G * d.ray_batch * 8 : 0);
   return p;
 }
 

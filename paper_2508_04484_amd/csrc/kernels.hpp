@@ -193,10 +193,13 @@ struct RayGeom {
   double L[3];           // box lengths (cm)
   double om[3];          // unit direction of flight
 };
-// scratch doubles per ray of a batch: c, y (3G each), Dinv, F, E (9G each)
+// Up to kRayWaveGroups groups a ray is marched by one wave (two groups per
+// lane) with no scratch; more groups take one thread per ray, and the scratch
+// then holds kRayScratchPerGroup * G * batch doubles (c, y: 3G each; Dinv, F,
+// E: 9G each, per ray of a batch).
+constexpr int kRayWaveGroups = 128;
 constexpr int kRayScratchPerGroup = 33;
-// uncollided tables of one beam: rays in batches of `batch` (the scratch
-// holds kRayScratchPerGroup * G * batch doubles)
+// uncollided tables of one beam (scratch and batch unused up to kRayWaveGroups)
 template <typename T>
 void launch_raytrace(const RayParams &rp, const RayGeom &geo, const int *rays,
                      const double *ray_f, const double *w, const double *Adiag,
