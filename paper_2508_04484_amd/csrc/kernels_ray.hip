@@ -366,16 +366,31 @@ __device__ __forceinline__ double lane_read(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-// out = v of lane (lane + delta), zero where that lane is outside the wave
+// v of lane - 1 (wave_shr:1) or lane + 1 (wave_shl:1) by DPP; 0 at the ends
+template <int CTRL>
+__device__ __forceinline__ double lane_shift1(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// out = v of lane (lane + delta).  Where that lane is outside the wave the
+// value is some finite lane's: every use multiplies it by a coupling block
+// that is exactly zero there (no row below group 0 or above group G - 1),
+// so no select is needed.  Distance 1 goes through DPP, longer ones through
+// ds_bpermute.
 template <int N>
 __device__ __forceinline__ void from_lane(const double *v, double *out, int lane, int delta) {
-  const int src = lane + delta;
-  const bool ok = src >= 0 && src < 64;
-  const int sl = ok ? src : lane;
+  if (delta == -1) {
 #pragma unroll
-  for (int t = 0; t < N; ++t) {
-    const double x = lane_read(v[t], sl);
-    out[t] = ok ? x : 0.0;
+    for (int t = 0; t < N; ++t) out[t] = lane_shift1<0x138>(v[t]);
+  } else if (delta == 1) {
+#pragma unroll
+    for (int t = 0; t < N; ++t) out[t] = lane_shift1<0x130>(v[t]);
+  } else {
+    const int sl = (lane + delta) & 63;
+#pragma unroll
+    for (int t = 0; t < N; ++t) out[t] = lane_read(v[t], sl);
   }
 }
 
