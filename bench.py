@@ -492,6 +492,8 @@ def main():
     ap.add_argument("--beams", type=int, default=8,
                     help="c4, c4_axis: number of the plan's beams timed plain and batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the second timing of the steps as one HIP graph (fixed rank)")
     ap.add_argument("--fp64-check", action="store_true",
                     help="also run the timed steps through the FP64 path and report the "
                          "relative L2 dose difference of the mixed-precision run")
@@ -583,7 +585,28 @@ def main():
     s.profile(False)
     nsub = [s.substeps(k) for k in range(K)]
     s_dose = s.dose().cpu().numpy() if args.fp64_check else None
+    eager_dose = s.dose() if (o.rank_mode == "fixed" and not args.no_graph) else None
     s.close()
+
+    # the same K steps recorded and launched as one HIP graph (fixed rank):
+    # recording, instantiation and launch all inside the timed region
+    graph = None
+    if eager_dose is not None:
+        s = dl.BeamSolver(problem, 0)
+        s.raytrace()
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run_graph(K)
+        s.sync()
+        wall_g = time.perf_counter() - t0
+        graph = {"value": round(K / wall_g, 4), "ms_per_step": round(1000.0 * wall_g / K, 3),
+                 "speedup_vs_eager": round(wall / wall_g, 4),
+                 "dose_bitwise_equal": bool(torch.equal(s.dose(), eager_dose)),
+                 "note": "dlra_run_graph: the K steps recorded once (both streams) and "
+                         "launched as one graph; recording and instantiation timed"}
+        s.close()
+        del eager_dose
 
     ms_step = 1000.0 * wall / K
     flops, nbytes, flops_all = kstage_algorithmic(problem)
@@ -630,6 +653,7 @@ def main():
             "timed_steps": f"0..{K - 1}", "mean_rk4_substeps": round(sum(nsub) / len(nsub), 3),
         },
         "rk4_substeps_per_s": round(sum(nsub) / wall, 2),
+        "graph": graph,
         "event_ms_per_step": round(ev0.elapsed_time(ev1) / K, 3),
         "raytrace_ms": round(1000.0 * t_ray, 2),
         "raytrace_kernel_ms": round(prof_ray[0], 2),

@@ -194,6 +194,16 @@ int uncollided_raytrace(dlra_ctx *ctx);
  *             DLRA_E_NUMERIC / DLRA_E_RANK raised by the step's kernels. */
 int dlra_step(dlra_ctx *ctx, int *rank_out);
 
+/* The next `count` energy steps, exactly as `count` dlra_step calls would
+ * compute them (bitwise), recorded once into a HIP graph (both streams of the
+ * context) and launched as one graph: the per-launch host overhead of the
+ * small kernels is paid once.  A fixed-rank context only (the adaptive rank
+ * rule decides on the host after each truncation), with profiling off and no
+ * rank replay pending; otherwise DLRA_E_STATE and nothing runs.  count in
+ * [1, steps left].  Asynchronous like dlra_step; a failed capture leaves the
+ * context as it was and returns DLRA_E_HIP. */
+int dlra_run_graph(dlra_ctx *ctx, int count);
+
 /* Deposited energy of the context's (weighted) beams into the caller's device
  * buffer dose[n_cells] (FP64).  The paper states the quantity (deposited
  * energy, Sec. 4) but not its formula; the library takes the energy lost by

@@ -24,6 +24,7 @@ EGRID = {"uniform": 0, "proportional": 1, "cfl": 2, "user": 3}
 DOSE_UNCOLLIDED, DOSE_COLLIDED, DOSE_PER_MASS, DOSE_ACCUMULATE = 1, 2, 4, 8
 
 EXPORTS = ["dlra_workspace_size", "dlra_init", "uncollided_raytrace", "dlra_step",
+           "dlra_run_graph",
            "dose_deposit", "dlra_get_state", "dlra_set_state", "dlra_get_uncollided",
            "dlra_set_uncollided", "dlra_save", "dlra_load",
            "dlra_substeps", "dlra_raytrace_work", "dlra_replay_ranks", "dlra_sync", "dlra_profile", "dlra_profile_read", "dlra_run_batch",
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
                               C.POINTER(Options), V, C.c_size_t, V, C.POINTER(P)]
     lib.uncollided_raytrace.argtypes = [P]
     lib.dlra_step.argtypes = [P, C.POINTER(I)]
+    lib.dlra_run_graph.argtypes = [P, I]
     lib.dose_deposit.argtypes = [P, V, I]
     lib.dlra_get_state.argtypes = [P, D, D, D, C.POINTER(I), C.POINTER(I)]
     lib.dlra_set_state.argtypes = [P, D, D, D, I, I]
@@ -226,6 +228,11 @@ class Solver:
             return r.value
         check(self.lib.dlra_step(self.ctx, None))
         return None
+
+    def run_graph(self, count: int):
+        """The next `count` steps recorded and launched as one HIP graph
+        (fixed rank only); bitwise the same as `count` step() calls."""
+        check(self.lib.dlra_run_graph(self.ctx, count))
 
     def run(self, n_steps=None):
         n_steps = self.problem.options.n_steps if n_steps is None else n_steps

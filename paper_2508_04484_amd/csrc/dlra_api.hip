@@ -57,7 +57,7 @@ struct Plan {
   // offsets
   size_t w_t, w_d, s, tall[4], psibar, dose_c, dose_u, Apm, AV, stepS, stepA, stepG, minstop,
       egrid_s, egrid_min;
-  size_t S, V, Vn, Bm, Bpk, Cm, Sh, Pp, Qp, Sp, G1, G2, Wg, T1, T2, Lm, L0, La, Lb, Mi, H, Cg, dc,
+  size_t S, V, Vn, Bm, Bpk, Cm, Ch, Sh, Pp, Qp, Sp, G1, G2, Wg, T1, T2, Lm, L0, La, Lb, Mi, H, Cg, dc,
       tmp, work, partial, ctl;
   size_t rt_diag, rt_up, rt_lo, rt_mass, rt_c0, rt_g0, rt_sw, rt_stopw, rt_rays, rt_f,
       rt_scratch;
@@ -176,6 +176,7 @@ Plan make_plan(const Dims &d) {
   p.Bm = p.take(d.ndk * P * P * 8);
   p.Bpk = p.take(d.ndk * 64 * 64 * 8);
   p.Cm = p.take(d.ndk * P * P * 8);
+  p.Ch = p.take(d.ndk * P * P * 8);
   p.Sh = p.take(P * P * 8);
   p.Pp = p.take(P * R * 8);
   p.Qp = p.take(P * R * 8);
@@ -230,7 +231,9 @@ struct dlra_ctx {
   hipStream_t st = nullptr;
   hipStream_t st2 = nullptr;            // side stream of the L-step (default priority)
   int device = 0;                       // HIP device the context was created on
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_kdone = nullptr;
+  hipGraphExec_t graph_exec = nullptr;   // the last dlra_run_graph launch
+  hipStream_t st_cap = nullptr;          // dlra_run_graph records on this stream
   char *base = nullptr;
   // host-side state
   int r = 0;
@@ -297,6 +300,12 @@ struct dlra_ctx {
     }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_kdone) (void)hipEventDestroy(ev_kdone);
+    if (graph_exec) {
+      (void)hipStreamSynchronize(st);
+      (void)hipGraphExecDestroy(graph_exec);
+    }
+    if (st_cap) (void)hipStreamDestroy(st_cap);
     if (!pending.empty() || !pool.empty()) {
       (void)hipStreamSynchronize(st);
       for (auto &r : pending) {
@@ -818,8 +827,9 @@ struct Stepper {
                                         p.partial_elems, st);
     }
     const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};   // Horner coefficients of RK4
-    // L-step: L0 = V S^T, Horner RK4 (m x r), on the side stream: it only
-    // needs V, S and the couplings C, and runs beside the K-step
+    // L-step: L0 = V S^T, Horner RK4 (m x r), on the side stream beside the
+    // K-step: it reads only V, S and this projection's couplings C (the
+    // S-step's projection writes its own buffer), one small launch per stage
     double *Lk = D(p.L0), *La = D(p.La), *Lb = D(p.Lb);
     HIPCHK(hipEventRecord(c->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(c->st2, c->ev_fork, 0));
@@ -839,12 +849,6 @@ struct Stepper {
         std::swap(Lk, Lb);
       }
     }
-    {
-      // the V-side augmentation needs only V and L1: on the side stream too
-      PhaseTimer t(c, DLRA_PH_AUGMENT, c->st2);
-      launch_vaug(m, r, c->V, m, Lk, c->opt.aug_tol, &ctl->kV, D(p.work), c->st2);
-    }
-    HIPCHK(hipEventRecord(c->ev_join, c->st2));
     // K-step: K0 = U S, Horner RK4
     launch_pack_couplings<T>(dd.ndk, r, D(p.Bm), P, c->at<T>(p.Bpk), st);
     launch_update<T>(n, tall(0), ld, r, D(p.S), R, 1.0, nullptr, 0, 0.0, tall(1), ld, r, nullptr,
@@ -865,7 +869,17 @@ struct Stepper {
         std::swap(c->tall[1], c->tall[3]);
       }
     }
-    HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
+    // The V-side augmentation (V and L1 only) waits for the end of the K-step
+    // and runs beside the U-side one: the K-step's stages hold one block per
+    // CU for the whole launch, so a long single-workgroup kernel on one CU
+    // would stretch a whole stage.
+    HIPCHK(hipEventRecord(c->ev_kdone, st));
+    HIPCHK(hipStreamWaitEvent(c->st2, c->ev_kdone, 0));
+    {
+      PhaseTimer t(c, DLRA_PH_AUGMENT, c->st2);
+      launch_vaug(m, r, c->V, m, Lk, c->opt.aug_tol, &ctl->kV, D(p.work), c->st2);
+    }
+    HIPCHK(hipEventRecord(c->ev_join, c->st2));
     // augmentation
     {
       PhaseTimer t(c, DLRA_PH_AUGMENT);
@@ -874,14 +888,15 @@ struct Stepper {
     // S-step on the augmented bases
     {
       PhaseTimer t(c, DLRA_PH_PROJECTION);
-      launch_stencil_projection<T, Acc>(c->gdev, s, tall(0), ld, 2 * r, D(p.Cm), P, D(p.partial),
+      launch_stencil_projection<T, Acc>(c->gdev, s, tall(0), ld, 2 * r, D(p.Ch), P, D(p.partial),
                                         p.partial_elems, st);
     }
+    HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
     {
       PhaseTimer t(c, DLRA_PH_SSTEP);
       angular(2 * r, c->V);
       launch_copy_block(r, r, D(p.S), R, D(p.Sh), P, P, P, 1.0, st);
-      launch_sstep(2 * r, P, dd.ndk, D(p.Cm), D(p.Bm), D(p.Sh), D(p.work), h, ns, st);
+      launch_sstep(2 * r, P, dd.ndk, D(p.Ch), D(p.Bm), D(p.Sh), D(p.work), h, ns, st);
     }
     {
       PhaseTimer t(c, DLRA_PH_TRUNCATE);
@@ -1211,7 +1226,8 @@ int dlra_init(const dlra_grid *grid, const dlra_materials *mat, int n_beams,
   if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
   if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_kdone, hipEventDisableTiming) != hipSuccess) {
     delete c;
     return fail(DLRA_E_HIP, "creating the side stream or its events failed");
   }
@@ -1300,6 +1316,71 @@ int dlra_step(dlra_ctx *c, int *rank_out) {
       *rank_out = c->r;
     }
   } catch (const std::exception &e) {
+    return fail(DLRA_E_HIP, e.what());
+  }
+  return DLRA_OK;
+}
+
+int dlra_run_graph(dlra_ctx *c, int count) {
+  if (!c) return fail(DLRA_E_INVALID, "ctx is NULL");
+  if (!c->traced) return fail(DLRA_E_STATE, "uncollided_raytrace must precede dlra_run_graph");
+  if (count < 1 || count > c->d.n_steps - c->step)
+    return fail(DLRA_E_INVALID, "count outside [1, steps left]");
+  if (c->opt.rank_mode != DLRA_RANK_FIXED || c->prof != 0 || c->replay_pos < c->replay.size())
+    return fail(DLRA_E_STATE, "graph runs need fixed rank, profiling off and no rank replay");
+  // host state the recording advances; restored if the capture fails.  The
+  // steps are recorded on a private stream (the caller's may be the legacy
+  // default stream, which cannot be captured) and the graph is launched on
+  // the caller's.
+  const int step0 = c->step, r0 = c->r;
+  void *tall0[4] = {c->tall[0], c->tall[1], c->tall[2], c->tall[3]};
+  double *V0 = c->V, *Vn0 = c->Vn;
+  hipStream_t user = c->st;
+  auto restore = [&]() {
+    c->st = user;
+    c->step = step0;
+    c->r = r0;
+    for (int i = 0; i < 4; ++i) c->tall[i] = tall0[i];
+    c->V = V0;
+    c->Vn = Vn0;
+  };
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  try {
+    // the previous graph (if any) has finished before it is released
+    if (c->graph_exec) {
+      HIPCHK(hipStreamSynchronize(c->st));
+      HIPCHK(hipGraphExecDestroy(c->graph_exec));
+      c->graph_exec = nullptr;
+    }
+    if (!c->st_cap) HIPCHK(hipStreamCreateWithFlags(&c->st_cap, hipStreamNonBlocking));
+    c->st = c->st_cap;
+    HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeRelaxed));
+    try {
+      for (int i = 0; i < count; ++i) {
+        if (c->d.tsize == 8) Stepper<double>{c}.run();
+        else Stepper<float>{c}.run();
+      }
+    } catch (...) {
+      (void)hipStreamEndCapture(c->st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(c->st, &g));
+    c->st = user;
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      throw std::runtime_error("graph instantiation failed");
+    }
+    (void)hipGraphDestroy(g);
+    if (hipGraphLaunch(ge, c->st) != hipSuccess) {
+      (void)hipGraphExecDestroy(ge);
+      throw std::runtime_error("graph launch failed");
+    }
+    c->graph_exec = ge;   // released after the stream has passed it
+  } catch (const std::exception &e) {
+    restore();
+    (void)hipGetLastError();
     return fail(DLRA_E_HIP, e.what());
   }
   return DLRA_OK;

@@ -621,6 +621,92 @@ __global__ __launch_bounds__(64 * kSmMaxDk) void k_sstep_mfma(
   }
 }
 
+// One L-step stage in one launch on the FP64 matrix cores:
+// out = L0 - coef sum_dk A_dk in C_dk^T (m x r, leading dim m).  Block b owns
+// the rows I = 16 b .. 16 b + 15 of out, wave dk the term dk.  The wave forms
+// T = A_dk(I, :) in (16 x RB) with A operands straight from A and B operands
+// from an LDS copy of in (chunks of kLsKC rows, zero past m and r), parks T in
+// LDS and multiplies it by C_dk^T (B operands from C); the ndk partial tiles
+// are then summed in order dk = 0, 1, ... .
+constexpr int kLsKC = 64;   // rows of in per LDS chunk
+
+template <int NKC>
+__global__ __launch_bounds__(64 * kSmMaxDk) void k_lstep_mfma(
+    int m, int r, int ndk, const double *__restrict__ A, const double *__restrict__ C, int ldc,
+    const double *__restrict__ in, const double *__restrict__ L0, double *__restrict__ out,
+    double coef) {
+  constexpr int RB = 16 * NKC, IS = RB + 2;   // LDS row stride of the in chunk
+  extern __shared__ double smem_d[];
+  double *Is = smem_d;                       // [kLsKC][IS]
+  double *Ts = Is + kLsKC * IS;              // [ndk][16][RB]: T, then the partial tile
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int dk = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c = lane & 15, q = lane >> 4;
+  const int I0 = 16 * blockIdx.x;
+  const double *Ad = A + size_t(dk) * m * m;
+  const int arow = min(I0 + c, m - 1);       // rows past m: clamped, never stored
+  sd4 acc[NKC];
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc) acc[kc] = sd4{0.0, 0.0, 0.0, 0.0};
+  for (int l0 = 0; l0 < m; l0 += kLsKC) {
+    // A operands of this chunk (column l0 + 4 s + q), all loads in flight together
+    double aop[kLsKC / 4];
+#pragma unroll
+    for (int s = 0; s < kLsKC / 4; ++s) aop[s] = Ad[arow + size_t(min(l0 + 4 * s + q, m - 1)) * m];
+    __syncthreads();   // the previous chunk's readers are done
+    for (int e = tid; e < kLsKC * RB; e += blockDim.x) {
+      const int l = e % kLsKC, k = e / kLsKC;
+      const double v = in[size_t(min(l0 + l, m - 1)) + size_t(min(k, r - 1)) * m];
+      Is[l * IS + k] = (l0 + l < m && k < r) ? v : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kLsKC / 4; ++s)
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc)
+        acc[kc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[s], Is[(4 * s + q) * IS + 16 * kc + c],
+                                                       acc[kc], 0, 0, 0);
+  }
+  // T (row q + 4 v, column 16 kc + c) into this wave's LDS tile
+  double *T = Ts + size_t(dk) * 16 * RB;
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[(q + 4 * v) * RB + 16 * kc + c] = acc[kc][v];
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's T stores landed
+  __builtin_amdgcn_wave_barrier();
+  // partial tile (I, J) = T C_dk^T over the RB columns of T; B lane l holds
+  // C_dk(j = 16 jt + c, k = 4 s + q) (k past r: T is zero there)
+  const double *Cd = C + size_t(dk) * ldc * ldc;
+  sd4 f[NKC];
+#pragma unroll
+  for (int jt = 0; jt < NKC; ++jt) {
+    f[jt] = sd4{0.0, 0.0, 0.0, 0.0};
+    const int j = min(16 * jt + c, r - 1);
+#pragma unroll
+    for (int s = 0; s < RB / 4; ++s) {
+      const int k = min(4 * s + q, r - 1);
+      f[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(T[c * RB + 4 * s + q], Cd[j + size_t(k) * ldc],
+                                                   f[jt], 0, 0, 0);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int jt = 0; jt < NKC; ++jt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[(q + 4 * v) * RB + 16 * jt + c] = f[jt][v];
+  __syncthreads();
+  for (int e = tid; e < 16 * RB; e += blockDim.x) {
+    const int i = e % 16, j = e / 16;
+    if (I0 + i < m && j < r) {
+      double F = 0.0;
+      for (int d = 0; d < ndk; ++d) F += Ts[(size_t(d) * 16 + i) * RB + j];
+      const size_t o = size_t(I0 + i) + size_t(j) * m;
+      out[o] = L0[o] - coef * F;
+    }
+  }
+}
+
 // L-step stage combine: out = L0 - coef sum_dk T_dk C_dk^T, T_dk = A_dk in
 // (m x r blocks, leading dim m, strided by ts).
 __global__ void k_lstep_combine(int m, int r, int ndk, const double *__restrict__ T, size_t ts,
@@ -671,7 +757,11 @@ __global__ __launch_bounds__(kWG) void k_gram_orth(int q, const double *__restri
     for (int e = threadIdx.x; e < q * q; e += blockDim.x) T[(e % q) + size_t(e / q) * ldt] = 0.0;
     __syncthreads();
   }
-  blk_jacobi(A, qq, qq, qq, V, qq, &flag, red);
+  // the QR-preconditioned SVD when its scratch is in the launch's LDS
+  if (qq <= 64)
+    blk_svd_qr(A, qq, qq, V, dyn + 2 * q * q, dyn + 3 * q * q, dyn + 4 * q * q, &flag, red);
+  else
+    blk_jacobi(A, qq, qq, qq, V, qq, &flag, red);
   __syncthreads();
   // for the PSD W, the column norms of W V are its eigenvalues
   blk_colnorms_sorted(A, qq, qq, qq, sig, order);
@@ -701,6 +791,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
   double *G = dyn;                     // r x r (LDS)
   double *W = G + r * r;               // r x r (LDS)
   double *Q = W + r * r;               // r x r (LDS)
+  double *Xs = Q + r * r;              // r x r, r x r, 2 r: SVD scratch (LDS, r <= 64)
   // ||L||_F^2
   double nl = 0.0;
   for (int e = threadIdx.x; e < m * r; e += blockDim.x) nl += L[e] * L[e];
@@ -719,7 +810,10 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
     __syncthreads();
   }
   blk_gemm_tn(r, r, m, 1.0, R, m, R, m, W, r);                           // W = R^T R
-  blk_jacobi(W, r, r, r, Q, r, &flag, red);
+  if (r <= 64)
+    blk_svd_qr(W, r, r, Q, Xs, Xs + r * r, Xs + 2 * r * r, &flag, red);
+  else
+    blk_jacobi(W, r, r, r, Q, r, &flag, red);
   __syncthreads();
   blk_colnorms_sorted(W, r, r, r, sig, order);
   const double thresh = tol * tol * nl;
@@ -1012,6 +1106,26 @@ void launch_small_gemm(int ta, int tb, int M, int N, int K, double alpha, const 
 void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C, int ldc,
                         const double *in, const double *L0, double *out, double coef,
                         double *T, size_t ts, hipStream_t st) {
+  if (r <= 64 && ndk <= kSmMaxDk) {
+    const int nkc = (r + 15) / 16;
+    const size_t shm = (size_t(kLsKC) * (16 * nkc + 2) + size_t(ndk) * 16 * 16 * nkc) * 8;
+#define DLRA_LSTEP(NKC)                                                                      \
+  do {                                                                                       \
+    auto kern = k_lstep_mfma<NKC>;                                                           \
+    if (shm > 65536)                                                                         \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                         \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));      \
+    kern<<<(m + 15) / 16, 64 * ndk, shm, st>>>(m, r, ndk, A, C, ldc, in, L0, out, coef);     \
+  } while (0)
+    switch (nkc) {
+      case 1: DLRA_LSTEP(1); break;
+      case 2: DLRA_LSTEP(2); break;
+      case 3: DLRA_LSTEP(3); break;
+      default: DLRA_LSTEP(4); break;
+    }
+#undef DLRA_LSTEP
+    return;
+  }
   launch_small_gemm(0, 0, m, r, m, 1.0, A, m, size_t(m) * m, in, m, 0, 0.0, T, m, ts, ndk, st);
   k_lstep_combine<<<(m * r + 255) / 256, 256, 0, st>>>(m, r, ndk, T, ts, C, ldc, L0, out, coef);
 }
@@ -1077,13 +1191,21 @@ void launch_copy_block(int rows, int cols, const double *src, int lds, double *d
 void launch_gram_orth(int q, const double *W, double *T, int ldt, double tol2,
                       const double *normsq, int *count, const int *restrict_count, double *work,
                       hipStream_t st) {
-  const size_t shm = size_t(2) * q * q * sizeof(double);   // q <= 50: 40 KiB
+  // A, V, and for q <= 64 the QR-preconditioned SVD's X, B (q x q) and 2 q
+  const size_t shm = (q <= 64 ? size_t(4) * q * q + 2 * q : size_t(2) * q * q) * sizeof(double);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_gram_orth),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
   k_gram_orth<<<1, kWG, shm, st>>>(q, W, T, ldt, tol2, normsq, count, restrict_count, work);
 }
 
 void launch_vaug(int m, int r, double *Vh, int ldv, const double *L, double tol, int *count,
                  double *work, hipStream_t st) {
-  const size_t shm = size_t(3) * r * r * sizeof(double);   // r <= 50: 60 KiB
+  // G, W, Q, and for r <= 64 the QR-preconditioned SVD's scratch (2 r^2 + 2 r)
+  const size_t shm = (r <= 64 ? size_t(5) * r * r + 2 * r : size_t(3) * r * r) * sizeof(double);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_vaug),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
   k_vaug<<<1, kWG, shm, st>>>(m, r, Vh, ldv, L, tol, count, work);
 }
 

@@ -309,3 +309,55 @@ def test_joint_arc_of_oblique_beams():
     err = rel(got, want)
     say(f"  rel-L2 dose error {err:.3e}")
     assert err <= 1e-10
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["c1", "small3d_mixed"])
+def test_graph_runs_match_eager_steps_bitwise(name):
+    """Steps recorded and launched as HIP graphs (several graphs, with eager
+    steps and synchronisations between them) give bitwise the doses and state
+    of plain steps after every graph."""
+    dl = _gpu()
+    import torch
+    if name == "c1":
+        p = configs.c1(n_steps=40)
+    else:
+        p = configs.small_3d(n=8, r=6, precision="mixed", n_steps=24)
+    say(f"graph runs {name}")
+    plan = [("graph", 7), ("eager", 2), ("graph", 1), ("graph", 12), ("eager", 1)]
+    n_total = sum(k for _, k in plan)
+    assert n_total <= p.options.n_steps
+    a = dl.BeamSolver(p, 0)
+    a.raytrace()
+    want = []
+    for _, k in plan:
+        a.run(k)
+        want.append((a.dose().clone(), a.state()))
+    a.close()
+    b = dl.BeamSolver(p, 0)
+    b.raytrace()
+    for (how, k), (dose, state) in zip(plan, want):
+        if how == "graph":
+            b.run_graph(k)
+        else:
+            b.run(k)
+        b.sync()
+        got = b.dose()
+        assert torch.equal(got, dose), how
+        for x, y in zip(b.state(), state):
+            if isinstance(x, int):
+                assert x == y
+            else:
+                assert np.array_equal(x, y)
+    b.close()
+
+
+@pytest.mark.gpu
+def test_graph_run_needs_fixed_rank():
+    dl = _gpu()
+    p = configs.small_2d(mats="slab", rank_mode="adaptive", r=4, r_min=2, r_max=12)
+    s = dl.BeamSolver(p, 0)
+    s.raytrace()
+    with pytest.raises(RuntimeError, match="fixed rank"):
+        s.run_graph(2)
+    s.close()
