@@ -718,6 +718,11 @@ struct Stepper {
   double *D(size_t off) { return c->at<double>(off); }
 
   // Uhat[:, r:2r] <- orth_tau((I - U U^T) K), count -> ctl->kU.  K (tall 1) is consumed.
+  // Classical Gram-Schmidt against U twice, then two Gram orthonormalisation
+  // (SVQB) passes.  After R = K - U G1 the second projection G2 = U^T R is not
+  // applied to R: the Gram of R - U G2 is R^T R - G2^T G2 (U has orthonormal
+  // columns) and (R - U G2) T1 = [U | R] [-G2 T1; T1] is formed in one update,
+  // one pass over the tall matrices fewer.
   void augment_u(int r, T *K) {
     const Plan &p = c->plan;
     const int n = d().n, ld = d().ld, P = d().P;
@@ -732,15 +737,18 @@ struct Stepper {
                      st);
     launch_gram<T, double>(n, U, ld, r, R, ld, r, nullptr, nullptr, D(p.G2), P, D(p.partial),
                            p.partial_elems, st);
-    launch_update<T>(n, U, ld, r, D(p.G2), P, -1.0, R, ld, 1.0, R, ld, r, nullptr, nullptr, 0,
-                     st);
     launch_gram<T, double>(n, R, ld, r, R, ld, r, nullptr, nullptr, D(p.Wg), r, D(p.partial),
                            p.partial_elems, st);
+    const double *G2 = D(p.G2);   // U^T R
+    launch_small_gemm(1, 0, r, r, r, -1.0, G2, P, 0, G2, P, 0, 1.0, D(p.Wg), r, 0, 1, st);
     const double tol = c->opt.aug_tol;
     launch_gram_orth(r, D(p.Wg), D(p.T1), P, tol * tol, &ctl->normsq, &ctl->kU, nullptr,
                      D(p.work), st);
-    launch_update<T>(n, R, ld, r, D(p.T1), P, 1.0, nullptr, 0, 0.0, K, ld, r, nullptr, nullptr,
-                     0, st);
+    // coefficients [-G2 T1; T1] (2r x r, ld P) of Uhat for K <- (R - U G2) T1
+    launch_small_gemm(0, 0, r, r, r, -1.0, G2, P, 0, D(p.T1), P, 0, 0.0, D(p.G1), P, 0, 1, st);
+    launch_copy_block(r, r, D(p.T1), P, D(p.G1) + r, P, r, r, 1.0, st);
+    launch_update<T>(n, U, ld, 2 * r, D(p.G1), P, 1.0, nullptr, 0, 0.0, K, ld, r, nullptr,
+                     nullptr, 0, st);
     launch_gram<T, double>(n, K, ld, r, K, ld, r, nullptr, nullptr, D(p.Wg), r, D(p.partial),
                            p.partial_elems, st);
     launch_gram_orth(r, D(p.Wg), D(p.T2), P, 0.0, nullptr, nullptr, &ctl->kU, D(p.work), st);
