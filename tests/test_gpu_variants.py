@@ -272,6 +272,33 @@ def test_oblique_raytrace_parity(name):
     assert e1 <= 1e-12 and e2 <= 1e-12
 
 
+# group counts around the wave kernel's two groups per lane: odd (the last
+# lane half empty) and beyond 128 groups (one thread per ray, scratch rows)
+RAY_GROUPS = {
+    "oblique2d_33_groups": lambda: configs.small_oblique_2d(angle_deg=60.0, n_groups=33),
+    "oblique2d_160_groups": lambda: configs.small_oblique_2d(angle_deg=30.0, n_groups=160),
+    "axis2d_160_groups": lambda: configs.small_2d(nx=16, ny=14, N=3, n_steps=10, mats="slab",
+                                                  r=6, dx=0.05, n_groups=160),
+}
+
+
+@pytest.mark.parametrize("name", list(RAY_GROUPS))
+def test_raytrace_group_counts(name):
+    dl = _gpu()
+    from oracle import raytrace
+    p = RAY_GROUPS[name]()
+    say(f"ray tracer group count {name}")
+    s = dl.BeamSolver(p, 0)
+    s.raytrace()
+    ps, Du = s.uncollided()
+    s.close()
+    ps_ref, Du_ref = raytrace.Tracer(p, p.beams[0]).trace()
+    e1 = np.abs(ps - ps_ref).max() / np.abs(ps_ref).max()
+    e2 = np.abs(Du - Du_ref).max() / np.abs(Du_ref).max()
+    say(f"  max error psibar {e1:.3e}, Du {e2:.3e}")
+    assert e1 <= 1e-12 and e2 <= 1e-12
+
+
 @pytest.mark.parametrize("name", list(OBLIQUE))
 def test_oblique_full_run_parity(name):
     dl = _gpu()
