@@ -871,12 +871,16 @@ __global__ __launch_bounds__(256) void k_stencil_proj(GridDev g, const T *__rest
     {
       const int cc = tid % CT, x = x0 + cc, xc = min(x, x_end - 1);
       const bool xin = x < x_end;
-      const T s0 = Sw[cc], sm1 = Sw[CT + cc], sm2 = Sw[2 * CT + cc];
-      const T sp1 = Sw[3 * CT + cc], sp2 = Sw[4 * CT + cc];
+      // s-weights of the one-sided differences with 1 / (2 Delta) folded in,
+      // formed once per cell; the centre terms of the two differences are
+      // negatives of each other, so one product serves both
+      const T cb0 = T(3) * ih * Sw[cc], cb1 = T(-4) * ih * Sw[CT + cc];
+      const T cb2 = ih * Sw[2 * CT + cc];
+      const T cf1 = T(4) * ih * Sw[3 * CT + cc], cf2 = -ih * Sw[4 * CT + cc];
       auto put = [&](int b, T w0, T wm1, T wm2, T wp1, T wp2) {
-        const T v0 = s0 * w0;
-        const T db = (T(3) * v0 - T(4) * (sm1 * wm1) + sm2 * wm2) * ih;
-        const T df = -(T(3) * v0 - T(4) * (sp1 * wp1) + sp2 * wp2) * ih;
+        const T t0 = cb0 * w0;
+        const T db = cb2 * wm2 + (cb1 * wm1 + t0);
+        const T df = cf2 * wp2 + (cf1 * wp1 - t0);
         const bool ok = xin && b < p;
         Yb[cc * PA + b] = ok ? Tc(db) : Tc(0);
         Yf[cc * PA + b] = ok ? Tc(df) : Tc(0);
