@@ -73,7 +73,8 @@ def summarize_counters(fetch_path, write_path, probe_mib, config, out_path):
     total = 0.0
     for ctr, path in (("FETCH_SIZE", fetch_path), ("WRITE_SIZE", write_path)):
         by = per_kernel(_counter_rows(path), ctr)
-        stage = [v for k, v in by.items() if "k_kstage" in k]
+        # the benchmarked stage kernel: the K-stage instance with the most dispatches
+        stage = sorted((v for k, v in by.items() if "k_kstage" in k), key=len, reverse=True)
         copies = [max(v) for k, v in by.items() if "copyBuffer" in k]
         if not stage or not copies:
             raise SystemExit(f"{ctr}: stage kernel or probe copy missing in {path}")
@@ -95,9 +96,16 @@ def summarize_sq(path, out_path):
     instruction counts per launch; writes a short text summary."""
     import statistics
     rows = _counter_rows(path)
+    # the benchmarked stage kernel: the K-stage instance with the most dispatches
+    names = {}
+    for r in rows:
+        n = r.get("Kernel_Name", "")
+        if "k_kstage" in n:
+            names[n] = names.get(n, 0) + 1
+    stage = max(names, key=names.get) if names else None
     by = {}
     for r in rows:
-        if "k_kstage" in r.get("Kernel_Name", ""):
+        if r.get("Kernel_Name", "") == stage:
             by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     if not by:
         raise SystemExit(f"no K-stage rows in {path}")
@@ -494,9 +502,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the second timing of the steps as one HIP graph (fixed rank)")
-    ap.add_argument("--fp64-check", action="store_true",
-                    help="also run the timed steps through the FP64 path and report the "
-                         "relative L2 dose difference of the mixed-precision run")
+    ap.add_argument("--no-fp64-check", action="store_true",
+                    help="skip the FP64 run of the timed steps that states the relative L2 "
+                         "dose difference of a mixed-precision run (done by default)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (a known-size "
                          "reference for hardware byte counters)")
@@ -584,7 +592,8 @@ def main():
     prof = s.profile_read()
     s.profile(False)
     nsub = [s.substeps(k) for k in range(K)]
-    s_dose = s.dose().cpu().numpy() if args.fp64_check else None
+    check64 = o.precision == "mixed" and not args.no_fp64_check
+    s_dose = s.dose().cpu().numpy() if check64 else None
     eager_dose = s.dose() if (o.rank_mode == "fixed" and not args.no_graph) else None
     s.close()
 
@@ -666,7 +675,7 @@ def main():
         "roofline": roof,
         "raytrace_roofline": raytrace_roofline(problem, ray_work, prof_ray[0]),
     }
-    if args.fp64_check:
+    if check64:
         out["mixed_vs_fp64"] = fp64_check(problem, K, s_dose)
     if not args.no_cpu_baseline and args.config == "c3":
         out["cpu_baseline"] = cpu_baseline(problem, window=range(K))
