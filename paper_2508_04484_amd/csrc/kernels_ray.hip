@@ -19,8 +19,9 @@
 // 2l and 2l+1.  The odd groups are eliminated inside each lane, then the even
 // groups by parallel cyclic reduction across the lanes (level j pairs lanes
 // 2^j apart; after ceil(log2(G/2)) levels every equation stands alone).  The
-// multipliers of all levels stay in registers for the piece and each substep
-// replays them on the right-hand side, so a substep touches no memory.
+// multipliers of a piece stay on chip (levels 0-1 in registers, 2-5 in the
+// wave's LDS rows) and each substep replays them on the right-hand side, so
+// a substep touches no global memory.
 //
 // Beyond that one thread marches one ray with a sequential block LU from the
 // lowest group (Dinv_g, F_g = Dinv_g L_g, E_g = Dinv_g U_g): y_g = Dinv_g M c_g
