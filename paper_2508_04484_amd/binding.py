@@ -383,11 +383,23 @@ def plan_objective(doses, weights, target, dhat, lam, stream=None):
     return J.value, grad
 
 
-def solve(problem, n_steps=None, joint=False):
+def batch_group_size(problem, reserve=0.1):
+    """Beams of a problem whose work spaces fit the free device memory at once
+    (keeping `reserve` of it free), at least 1."""
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    per = workspace_size(problem.single_beam(0), 1)
+    return max(1, min(len(problem.beams), int(free * (1.0 - reserve)) // max(per, 1)))
+
+
+def solve(problem, n_steps=None, joint=False, batch=1):
     """Deposited energy of all beams of a problem at their weights (torch
     float64 on the GPU): one joint collided solve (joint=True), or every beam
     solved on its own and its weighted dose added into one buffer by the
-    library (dose_deposit with DOSE_ACCUMULATE)."""
+    library (dose_deposit with DOSE_ACCUMULATE).  With batch > 1 (0: as many
+    as fit the free device memory) the separate beams run in groups through
+    the library's batch scheduler, each on a stream of its own; the doses are
+    added in beam order, so the result is bitwise the one-by-one solve's."""
     import torch
     if joint:
         s = Solver(problem)
@@ -397,10 +409,19 @@ def solve(problem, n_steps=None, joint=False):
         s.close()
         return d
     total = torch.zeros(problem.grid.n, dtype=torch.float64, device="cuda")
-    for b in range(len(problem.beams)):
-        s = Solver(problem, [b])
-        s.raytrace()
-        s.run(n_steps)
-        s.dose(DOSE_UNCOLLIDED | DOSE_COLLIDED | DOSE_ACCUMULATE, out=total)
-        s.close()
+    torch.cuda.current_stream().synchronize()   # the solvers' streams add into it
+    nb = len(problem.beams)
+    group = batch_group_size(problem) if batch == 0 else max(1, int(batch))
+    for b0 in range(0, nb, group):
+        idx = list(range(b0, min(nb, b0 + group)))
+        if len(idx) == 1:
+            solvers = [Solver(problem, idx)]
+            solvers[0].raytrace()
+            solvers[0].run(n_steps)
+        else:
+            solvers = [Solver(problem, [b], stream=torch.cuda.Stream()) for b in idx]
+            run_batch(solvers, n_steps)
+        for s in solvers:
+            s.dose(DOSE_UNCOLLIDED | DOSE_COLLIDED | DOSE_ACCUMULATE, out=total)
+            s.close()
     return total

@@ -388,3 +388,18 @@ def test_graph_run_needs_fixed_rank():
     with pytest.raises(RuntimeError, match="fixed rank"):
         s.run_graph(2)
     s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("batch", [2, 0])
+def test_grouped_batch_solve_matches_one_by_one(batch):
+    """Separate beams solved in groups through the batch scheduler (batch = 2,
+    or as many as fit the free memory) add up to bitwise the one-by-one dose."""
+    dl = _gpu()
+    import torch
+    p = configs.small_arc_2d(n_beams=3)
+    say(f"grouped batch solve, batch={batch}")
+    one = dl.solve(p, batch=1)
+    grouped = dl.solve(p, batch=batch)
+    assert torch.equal(one, grouped)
+    assert dl.binding.batch_group_size(p) >= 1
