@@ -42,6 +42,7 @@ struct HipError : std::runtime_error {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxRank = 50;      // 2 r_max <= 100 columns in the small kernels
+static_assert(2 * kMaxRank <= kSStepMaxP && 2 * 3 <= kSStepMaxDk, "S-step limits");  // ndk = 2 dim
 constexpr int kPartialBlocks = 1024;   // partial-sum blocks of a contraction
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }

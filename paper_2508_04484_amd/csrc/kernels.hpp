@@ -116,7 +116,10 @@ void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C,
                         double *T, size_t ts, hipStream_t st);
 
 // Horner RK4 of the S-step on the p x p matrix S (leading dim ld, as Ch, Bh
-// whose dk-th blocks are ld*ld apart), n_sub substeps.
+// whose dk-th blocks are ld*ld apart), n_sub substeps.  Requires
+// p <= kSStepMaxP and 2 <= ndk <= kSStepMaxDk (one wave per term).
+constexpr int kSStepMaxP = 128;
+constexpr int kSStepMaxDk = 6;
 void launch_sstep(int p, int ld, int ndk, const double *Ch, const double *Bh, double *S,
                   double *work, double h, int n_sub, hipStream_t st);
 

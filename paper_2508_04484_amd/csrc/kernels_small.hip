@@ -490,133 +490,108 @@ __device__ int blk_fill(double *Q, int ldq, int p, int cnt, int need, int ncand,
 
 // ------------------------------------------------------------------ S-step
 // One RK4 stage (Horner form) of dS/dt = -sum_dk C_dk S B_dk:
-//   out(:, J) = S0(:, J) - coef sum_dk C_dk (W B_dk(:, J))
-// Each workgroup owns the columns J = [j0, j0 + kSJ): it stages the whole
-// stage input W in LDS and needs no other workgroup's result.  out may alias
-// S0 (each workgroup reads S0(:, J) before writing it).
-constexpr int kSJ = 4;
-constexpr int kSMaxOut = 100 * kSJ;   // outputs per S-step workgroup (P <= 100)
-
-__global__ __launch_bounds__(256) void k_sstep_stage(int P, int ld, int ndk,
-                                                    const double *__restrict__ Ch,
-                                                    const double *__restrict__ Bh,
-                                                    const double *S0, const double *__restrict__ W,
-                                                    double *out, double coef, int c_in_lds) {
-  extern __shared__ double smem_d[];
-  double *Ws = smem_d;                 // P x P
-  double *Ts = Ws + P * P;             // P x kSJ
-  double *Bs = Ts + P * kSJ;           // P x kSJ
-  double *Cs = Bs + P * kSJ;           // P x P (when c_in_lds)
-  const int j0 = blockIdx.x * kSJ;
-  const int nj = min(kSJ, P - j0);
-  for (int e = threadIdx.x; e < P * P; e += blockDim.x) Ws[e] = W[(e % P) + size_t(e / P) * ld];
-  double F[(kSMaxOut + 255) / 256];
-  for (int u = 0; u < (kSMaxOut + 255) / 256; ++u) F[u] = 0.0;
-  for (int dk = 0; dk < ndk; ++dk) {
-    const double *C = Ch + size_t(dk) * ld * ld;
-    const double *B = Bh + size_t(dk) * ld * ld;
-    // stage this term's coupling columns B(:, J) and, when it fits, C in LDS
-    // (coalesced, all loads in flight together)
-    for (int e = threadIdx.x; e < P * nj; e += blockDim.x)
-      Bs[e] = B[(e % P) + size_t(j0 + e / P) * ld];
-    if (c_in_lds)
-      for (int e = threadIdx.x; e < P * P; e += blockDim.x) Cs[e] = C[(e % P) + size_t(e / P) * ld];
-    __syncthreads();
-    for (int e = threadIdx.x; e < P * nj; e += blockDim.x) {
-      const int i = e % P, jj = e / P;
-      double acc = 0.0;
-      for (int k = 0; k < P; ++k) acc += Ws[i + k * P] * Bs[k + jj * P];
-      Ts[i + jj * P] = acc;
-    }
-    __syncthreads();
-    for (int u = 0, e = threadIdx.x; e < P * nj; ++u, e += blockDim.x) {
-      const int i = e % P, jj = e / P;
-      double acc = 0.0;
-      if (c_in_lds)
-        for (int k = 0; k < P; ++k) acc += Cs[i + k * P] * Ts[k + jj * P];
-      else
-#pragma unroll 8
-        for (int k = 0; k < P; ++k) acc += C[i + size_t(k) * ld] * Ts[k + jj * P];
-      F[u] -= acc;
-    }
-    __syncthreads();
-  }
-  for (int u = 0, e = threadIdx.x; e < P * nj; ++u, e += blockDim.x) {
-    int i = e % P, jj = e / P;
-    size_t o = i + size_t(j0 + jj) * ld;
-    out[o] = S0[o] + coef * F[u];
-  }
-}
-
-// The same stage on the FP64 matrix cores for P <= 64: workgroup (it, jt)
-// owns the 16 x 16 output tile (I, J) = (16 it.., 16 jt..), wave dk of it the
-// term dk.  The wave forms T_dk(:, J) = W B_dk(:, J) (A operands: W staged in
-// LDS, zero padded to 64 x 64; B operands: B_dk in registers), keeps it in
-// LDS, multiplies C_dk(I, :) (registers) by it, and the ndk tiles are summed
-// in order dk = 0, 1, ...  16x16x4 f64 MFMA operand layout: A lane l holds
-// (row l % 16, k l / 16), B lane l holds (k l / 16, column l % 16), register
-// v of the accumulator is (row l / 16 + 4 v, column l % 16).
+//   out = S0 - coef sum_dk C_dk (W B_dk)
+// on the FP64 matrix cores for P <= 4 NS (NS = 16 or 32 k-steps
+// of 4): workgroup (it, jt) owns the 16 x 16 output tile (I, J) = (16 it..,
+// 16 jt..), wave dk of it the term dk.  The wave forms T_dk(:, J) = W B_dk(:, J)
+// one 16-row tile at a time (A operands: an LDS copy of W, zero padded; B
+// operands: B_dk(:, J) in registers) and feeds each tile straight into
+// C_dk(I, :) T_dk(:, J) (A operands C_dk(I, :) in registers): the accumulator
+// of the first product is already the B operand of the second, so T never
+// leaves registers.  The ndk tiles are then summed in order dk = 0, 1, ...
+// 16x16x4 f64 MFMA operand layout: A lane l holds (row l % 16, k l / 16), B
+// lane l holds (k l / 16, column l % 16), register v of the accumulator is
+// (row l / 16 + 4 v, column l % 16) -- for row tile t of T that is the B
+// operand of k-step 4 t + v of the second product.
 typedef double sd4 __attribute__((ext_vector_type(4)));
-constexpr int kSmP = 64;        // padded order
-constexpr int kSmLW = 80;       // LDS row stride of W (doubles): 2 * 80 = 32 mod 64 banks
 constexpr int kSmMaxDk = 6;
 
+// LDS row stride of the W copy for 16 pt rows: a multiple of 16 doubles with
+// 2 * stride = 32 mod 64 banks, so lanes k and k + 1 of an A-operand read
+// fall in opposite halves of the banks
+inline __host__ __device__ int sstep_lds_stride(int pt) { return 16 * pt + ((pt & 1) ? 0 : 16); }
+
+inline size_t sstep_mfma_lds(int p, int ndk) {
+  const int pt = (p + 15) / 16, kr = 4 * ((p + 3) / 4);
+  return (size_t(kr) * sstep_lds_stride(pt) + size_t(ndk) * 256) * sizeof(double);
+}
+
+constexpr int kSsBatch = 16;   // W staging loads per thread in flight together
+
+template <int NS>
 __global__ __launch_bounds__(64 * kSmMaxDk) void k_sstep_mfma(
     int P, int ld, int ndk, const double *__restrict__ Ch, const double *__restrict__ Bh,
     const double *S0, const double *__restrict__ W, double *out, double coef) {
   extern __shared__ double smem_d[];
-  double *Ws = smem_d;                       // [kSmP k][kSmLW]: W(i, k) at k * kSmLW + i
-  double *Ts = Ws + kSmP * kSmLW;            // [ndk][kSmP][16]
-  double *Rs = Ts + kSmMaxDk * kSmP * 16;    // [ndk][16][16]
+  const int PT = (P + 15) / 16, KS = (P + 3) / 4, KR = 4 * KS, RW = 16 * PT;
+  const int lw = sstep_lds_stride(PT);
+  double *Ws = smem_d;                       // [KR k][lw]: W(i, k) at k * lw + i
+  double *Rs = Ws + size_t(KR) * lw;         // [ndk][16][16]
   const int tid = threadIdx.x, lane = tid & 63;
   const int dk = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c = lane & 15, q = lane >> 4;
   const int I0 = 16 * blockIdx.x, J0 = 16 * blockIdx.y;
-  const int KS = (P + 3) / 4;                // k steps of 4
   const double *B = Bh + size_t(dk) * ld * ld, *C = Ch + size_t(dk) * ld * ld;
   // operands of this wave, all loads in flight together (clamped, masked)
-  double bop[16], cop[16];
+  double bop[NS], cop[NS];
   const int jB = min(J0 + c, P - 1), iC = min(I0 + c, P - 1);
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
+  for (int s = 0; s < NS; ++s) {
     const int k = 4 * s + q, kc = min(k, P - 1);
     const double bv = B[kc + size_t(jB) * ld];
     const double cv = C[iC + size_t(kc) * ld];
     bop[s] = k < P ? bv : 0.0;
     cop[s] = k < P ? cv : 0.0;
   }
-  for (int e = tid; e < kSmP * kSmP; e += blockDim.x) {
-    const int i = e % kSmP, k = e / kSmP;
-    const double v = W[min(i, P - 1) + size_t(min(k, P - 1)) * ld];
-    Ws[k * kSmLW + i] = (i < P && k < P) ? v : 0.0;
+  // this thread's S0 entries of the output tile (at most 2: >= 128 threads)
+  double s0v[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = min(tid + u * int(blockDim.x), 255);
+    s0v[u] = S0[min(I0 + (e & 15), P - 1) + size_t(min(J0 + (e >> 4), P - 1)) * ld];
   }
-  __syncthreads();
-  // T_dk(:, J), row tiles it = 0 .. 3
-  double *T = Ts + dk * kSmP * 16;
+  // W into LDS, kSsBatch loads per thread in flight at a time
+  const int tot = KR * RW, nthr = blockDim.x;
+  for (int e0 = 0; e0 < tot; e0 += kSsBatch * nthr) {
+    double wv[kSsBatch];
 #pragma unroll
-  for (int it = 0; it < kSmP / 16; ++it) {
-    sd4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int s = 0; s < KS; ++s)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(4 * s + q) * kSmLW + 16 * it + c], bop[s],
-                                                 acc, 0, 0, 0);
+    for (int u = 0; u < kSsBatch; ++u) {
+      const int e = min(e0 + u * nthr + tid, tot - 1), i = e % RW, k = e / RW;
+      wv[u] = W[min(i, P - 1) + size_t(min(k, P - 1)) * ld];
+    }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) T[(16 * it + q + 4 * v) * 16 + c] = acc[v];
+    for (int u = 0; u < kSsBatch; ++u) {
+      const int e = e0 + u * nthr + tid, i = e % RW, k = e / RW;
+      if (e < tot) Ws[k * lw + i] = (i < P && k < P) ? wv[u] : 0.0;
+    }
   }
   __syncthreads();
   sd4 f = {0.0, 0.0, 0.0, 0.0};
-  for (int s = 0; s < KS; ++s)
-    f = __builtin_amdgcn_mfma_f64_16x16x4f64(cop[s], T[(4 * s + q) * 16 + c], f, 0, 0, 0);
+#pragma unroll
+  for (int t = 0; t < NS / 4; ++t) {
+    if (t < PT) {
+      sd4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (s < KS)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(4 * s + q) * lw + 16 * t + c], bop[s],
+                                                     acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        f = __builtin_amdgcn_mfma_f64_16x16x4f64(cop[4 * t + v], acc[v], f, 0, 0, 0);
+    }
+  }
 #pragma unroll
   for (int v = 0; v < 4; ++v) Rs[(dk * 16 + q + 4 * v) * 16 + c] = f[v];
   __syncthreads();
-  for (int e = tid; e < 256; e += blockDim.x) {
-    const int i = e & 15, j = e >> 4;
-    double F = 0.0;
-    for (int d = 0; d < ndk; ++d) F -= Rs[(d * 16 + i) * 16 + j];
-    const int gi = I0 + i, gj = J0 + j;
-    if (gi < P && gj < P) {
-      const size_t o = gi + size_t(gj) * ld;
-      out[o] = S0[o] + coef * F;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * int(blockDim.x);
+    const int i = e & 15, j = e >> 4, gi = I0 + i, gj = J0 + j;
+    if (e < 256 && gi < P && gj < P) {
+      double F = 0.0;
+      for (int d = 0; d < ndk; ++d) F -= Rs[(d * 16 + i) * 16 + j];
+      out[gi + size_t(gj) * ld] = s0v[u] + coef * F;
     }
   }
 }
@@ -630,36 +605,69 @@ __global__ __launch_bounds__(64 * kSmMaxDk) void k_sstep_mfma(
 // are then summed in order dk = 0, 1, ... .
 constexpr int kLsKC = 64;   // rows of in per LDS chunk
 
-template <int NKC>
-__global__ __launch_bounds__(64 * kSmMaxDk) void k_lstep_mfma(
-    int m, int r, int ndk, const double *__restrict__ A, const double *__restrict__ C, int ldc,
+// The loads of one chunk (rows l0 .. l0 + kLsKC - 1 of the contraction): this
+// lane's A operands and this thread's NST of the tot entries of the in chunk
+// (clamped)
+template <int NST, int NTHR>
+__device__ __forceinline__ void lstep_fetch(int l0, int m, int r, int arow, int q, int tid, int tot,
+                                            const double *__restrict__ Ad,
+                                            const double *__restrict__ in,
+                                            double (&an)[kLsKC / 4], double (&stg)[NST]) {
+#pragma unroll
+  for (int s = 0; s < kLsKC / 4; ++s) an[s] = Ad[arow + size_t(min(l0 + 4 * s + q, m - 1)) * m];
+#pragma unroll
+  for (int u = 0; u < NST; ++u) {
+    const int e = min(tid + u * NTHR, tot - 1), l = e % kLsKC, k = e / kLsKC;
+    stg[u] = in[size_t(min(l0 + l, m - 1)) + size_t(min(k, r - 1)) * m];
+  }
+}
+
+template <int NKC, int NDK>
+__global__ __launch_bounds__(64 * NDK) void k_lstep_mfma(
+    int m, int r, const double *__restrict__ A, const double *__restrict__ C, int ldc,
     const double *__restrict__ in, const double *__restrict__ L0, double *__restrict__ out,
     double coef) {
   constexpr int RB = 16 * NKC, IS = RB + 2;   // LDS row stride of the in chunk
   extern __shared__ double smem_d[];
   double *Is = smem_d;                       // [kLsKC][IS]
-  double *Ts = Is + kLsKC * IS;              // [ndk][16][RB]: T, then the partial tile
+  double *Ts = Is + kLsKC * IS;              // [NDK][16][RB]: T, then the partial tile
   const int tid = threadIdx.x, lane = tid & 63;
   const int dk = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c = lane & 15, q = lane >> 4;
   const int I0 = 16 * blockIdx.x;
   const double *Ad = A + size_t(dk) * m * m;
   const int arow = min(I0 + c, m - 1);       // rows past m: clamped, never stored
+  // NST: in-chunk entries per thread; NO: outputs per thread
+  constexpr int NTHR = 64 * NDK, NST = (kLsKC * RB + NTHR - 1) / NTHR;
+  constexpr int NO = (16 * RB + NTHR - 1) / NTHR;
+  const int nthr = NTHR;
+  // this thread's L0 entries, read up front
+  double l0v[NO];
+#pragma unroll
+  for (int u = 0; u < NO; ++u) {
+    const int e = min(tid + u * nthr, 16 * RB - 1), i = e % 16, j = e / 16;
+    l0v[u] = L0[size_t(min(I0 + i, m - 1)) + size_t(min(j, r - 1)) * m];
+  }
   sd4 acc[NKC];
 #pragma unroll
   for (int kc = 0; kc < NKC; ++kc) acc[kc] = sd4{0.0, 0.0, 0.0, 0.0};
+  // software pipeline: the loads of chunk l0 + kLsKC are in flight while the
+  // matrix cores work on chunk l0
+  double an[kLsKC / 4], stg[NST];
+  lstep_fetch<NST, NTHR>(0, m, r, arow, q, tid, kLsKC * RB, Ad, in, an, stg);
   for (int l0 = 0; l0 < m; l0 += kLsKC) {
-    // A operands of this chunk (column l0 + 4 s + q), all loads in flight together
-    double aop[kLsKC / 4];
-#pragma unroll
-    for (int s = 0; s < kLsKC / 4; ++s) aop[s] = Ad[arow + size_t(min(l0 + 4 * s + q, m - 1)) * m];
     __syncthreads();   // the previous chunk's readers are done
-    for (int e = tid; e < kLsKC * RB; e += blockDim.x) {
-      const int l = e % kLsKC, k = e / kLsKC;
-      const double v = in[size_t(min(l0 + l, m - 1)) + size_t(min(k, r - 1)) * m];
-      Is[l * IS + k] = (l0 + l < m && k < r) ? v : 0.0;
+#pragma unroll
+    for (int u = 0; u < NST; ++u) {
+      const int e = tid + u * nthr, l = e % kLsKC, k = e / kLsKC;
+      if (e < kLsKC * RB) Is[l * IS + k] = (l0 + l < m && k < r) ? stg[u] : 0.0;
     }
+    double aop[kLsKC / 4];   // A operands of this chunk (column l0 + 4 s + q)
+#pragma unroll
+    for (int s = 0; s < kLsKC / 4; ++s) aop[s] = an[s];
     __syncthreads();
+    if (l0 + kLsKC < m)
+      lstep_fetch<NST, NTHR>(l0 + kLsKC, m, r, arow, q, tid, kLsKC * RB, Ad, in, an, stg);
 #pragma unroll
     for (int s = 0; s < kLsKC / 4; ++s)
 #pragma unroll
@@ -696,13 +704,13 @@ __global__ __launch_bounds__(64 * kSmMaxDk) void k_lstep_mfma(
 #pragma unroll
     for (int v = 0; v < 4; ++v) T[(q + 4 * v) * RB + 16 * jt + c] = f[jt][v];
   __syncthreads();
-  for (int e = tid; e < 16 * RB; e += blockDim.x) {
-    const int i = e % 16, j = e / 16;
-    if (I0 + i < m && j < r) {
+#pragma unroll
+  for (int u = 0; u < NO; ++u) {
+    const int e = tid + u * nthr, i = e % 16, j = e / 16;
+    if (e < 16 * RB && I0 + i < m && j < r) {
       double F = 0.0;
-      for (int d = 0; d < ndk; ++d) F += Ts[(size_t(d) * 16 + i) * RB + j];
-      const size_t o = size_t(I0 + i) + size_t(j) * m;
-      out[o] = L0[o] - coef * F;
+      for (int d = 0; d < NDK; ++d) F += Ts[(size_t(d) * 16 + i) * RB + j];
+      out[size_t(I0 + i) + size_t(j) * m] = l0v[u] - coef * F;
     }
   }
 }
@@ -1106,23 +1114,32 @@ void launch_small_gemm(int ta, int tb, int M, int N, int K, double alpha, const 
 void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C, int ldc,
                         const double *in, const double *L0, double *out, double coef,
                         double *T, size_t ts, hipStream_t st) {
-  if (r <= 64 && ndk <= kSmMaxDk) {
+  if (r <= 64 && (ndk == 2 || ndk == 4 || ndk == 6)) {   // one wave per term
     const int nkc = (r + 15) / 16;
     const size_t shm = (size_t(kLsKC) * (16 * nkc + 2) + size_t(ndk) * 16 * 16 * nkc) * 8;
-#define DLRA_LSTEP(NKC)                                                                      \
+#define DLRA_LSTEP(NKC, NDK)                                                                 \
   do {                                                                                       \
-    auto kern = k_lstep_mfma<NKC>;                                                           \
+    auto kern = k_lstep_mfma<NKC, NDK>;                                                      \
     if (shm > 65536)                                                                         \
       (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                         \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));      \
-    kern<<<(m + 15) / 16, 64 * ndk, shm, st>>>(m, r, ndk, A, C, ldc, in, L0, out, coef);     \
+    kern<<<(m + 15) / 16, 64 * NDK, shm, st>>>(m, r, A, C, ldc, in, L0, out, coef);          \
   } while (0)
-    switch (nkc) {
-      case 1: DLRA_LSTEP(1); break;
-      case 2: DLRA_LSTEP(2); break;
-      case 3: DLRA_LSTEP(3); break;
-      default: DLRA_LSTEP(4); break;
+#define DLRA_LSTEP_NKC(NDK)                  \
+  switch (nkc) {                             \
+    case 1: DLRA_LSTEP(1, NDK); break;       \
+    case 2: DLRA_LSTEP(2, NDK); break;       \
+    case 3: DLRA_LSTEP(3, NDK); break;       \
+    default: DLRA_LSTEP(4, NDK); break;      \
+  }
+    if (ndk == 2) {
+      DLRA_LSTEP_NKC(2)
+    } else if (ndk == 4) {
+      DLRA_LSTEP_NKC(4)
+    } else {
+      DLRA_LSTEP_NKC(6)
     }
+#undef DLRA_LSTEP_NKC
 #undef DLRA_LSTEP
     return;
   }
@@ -1132,38 +1149,20 @@ void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C,
 
 void launch_sstep(int p, int ld, int ndk, const double *Ch, const double *Bh, double *S,
                   double *work, double h, int n_sub, hipStream_t st) {
+  static_assert(kSStepMaxP == 4 * 32 && kSStepMaxDk == kSmMaxDk, "S-step limits");
   double *Wa = work, *Wb = work + size_t(ld) * ld;
-  size_t shm = (size_t(p) * p + 2 * size_t(p) * kSJ) * sizeof(double);
-  const int c_in_lds = shm + size_t(p) * p * sizeof(double) <= 150 * 1024 ? 1 : 0;
-  if (c_in_lds) shm += size_t(p) * p * sizeof(double);
-  if (shm > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sstep_stage),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
-  const int blocks = (p + kSJ - 1) / kSJ;
   const double cf[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
-  if (p <= kSmP && ndk <= kSmMaxDk) {
-    const size_t shm_m =
-        (size_t(kSmP) * kSmLW + size_t(kSmMaxDk) * kSmP * 16 + size_t(kSmMaxDk) * 256) * 8;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sstep_mfma),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm_m));
-    const dim3 grid((p + 15) / 16, (p + 15) / 16);
-    for (int sub = 0; sub < n_sub; ++sub) {
-      const double *in = S;
-      double *outs[4] = {Wa, Wb, Wa, S};
-      for (int stage = 0; stage < 4; ++stage) {
-        k_sstep_mfma<<<grid, 64 * ndk, shm_m, st>>>(p, ld, ndk, Ch, Bh, S, in, outs[stage],
-                                                    cf[stage] * h);
-        in = outs[stage];
-      }
-    }
-    return;
-  }
+  const size_t shm = sstep_mfma_lds(p, ndk);
+  const auto kern = p <= 64 ? k_sstep_mfma<16> : k_sstep_mfma<32>;
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+  const dim3 grid((p + 15) / 16, (p + 15) / 16);
   for (int sub = 0; sub < n_sub; ++sub) {
     const double *in = S;
     double *outs[4] = {Wa, Wb, Wa, S};
     for (int stage = 0; stage < 4; ++stage) {
-      k_sstep_stage<<<blocks, 256, shm, st>>>(p, ld, ndk, Ch, Bh, S, in, outs[stage],
-                                              cf[stage] * h, c_in_lds);
+      kern<<<grid, 64 * ndk, shm, st>>>(p, ld, ndk, Ch, Bh, S, in, outs[stage], cf[stage] * h);
       in = outs[stage];
     }
   }

@@ -38,7 +38,17 @@ CASES = {
     "random3d": lambda **k: configs.small_3d(n=8, r=6, **k),
     # rank 20: two 16-column output tiles in the K-step (ragged 11^3 grid)
     "rank20_3d": lambda **k: configs.small_3d(n=11, N=7, r=20, n_steps=6, **k),
+    # the largest rank: 2r = 100 augmented columns (the S-step's matrix-core
+    # kernel past 64 columns, ragged 16-row tiles)
+    "rank50_3d": lambda **k: configs.small_3d(n=8, N=9, r=50, n_steps=4, **k),
 }
+# Free-running FP64 dose comparisons: every case but rank50_3d.  There the
+# fixed rank-50 truncation of 100 columns in a 100-moment space amplifies
+# rounding about 1e4-fold (a 1e-16 relative perturbation of the reference's
+# own projected residuals moves its collided dose by 1.2e-12), so two correct
+# FP64 implementations drift apart by ~3e-10 over the run while each single
+# step from a common state agrees to ~3e-12; that case is gated step by step.
+FREE_RUN_FP64 = [n for n in CASES if n != "rank50_3d"]
 # rank edges of the K-step kernels (mixed precision: the z-march kernel takes
 # r <= 32 in FP32, one output tile up to 16, two above; r = 33 goes to the
 # general kernel)
@@ -68,7 +78,7 @@ def test_raytrace_parity(name):
     s.close()
 
 
-@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("name", FREE_RUN_FP64)
 def test_full_run_dose_parity_fp64(name):
     dl = _gpu()
     p = CASES[name]()
@@ -84,7 +94,7 @@ def test_full_run_dose_parity_fp64(name):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["slab2d", "random3d"])
+@pytest.mark.parametrize("name", ["slab2d", "random3d", "rank50_3d"])
 def test_single_step_from_injected_state(name):
     # the reference state after k steps is handed to the library, which takes
     # step k; the low-rank products must agree
@@ -109,7 +119,7 @@ def test_single_step_from_injected_state(name):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["slab2d", "random3d", "rank20_3d"])
+@pytest.mark.parametrize("name", ["slab2d", "random3d", "rank20_3d", "rank50_3d"])
 def test_mixed_precision_dose(name):
     dl = _gpu()
     p = CASES[name](precision="mixed", aug_tol=1e-4, floor_tol=1e-5)
