@@ -13,6 +13,7 @@ namespace {
 
 constexpr int kT = 16;
 constexpr int kWG = 512;   // threads of the single-workgroup kernels
+typedef double sd4 __attribute__((ext_vector_type(4)));   // f64 MFMA accumulator
 constexpr int kTruncLdsDoubles = 19200;   // LDS room of k_truncate (150 KiB)
 constexpr size_t kSmallMaxLds = 150 * 1024;   // largest dynamic LDS a small kernel asks for
 
@@ -124,18 +125,79 @@ __device__ void blk_coefs(const double *Q, int ldq, int p, int cnt, const double
   __syncthreads();
 }
 
-// C(M x N) = alpha A^T B (A: K x M, B: K x N, long K), one DPP row of 16
-// lanes per output.
-__device__ void blk_gemm_tn(int M, int N, int K, double alpha, const double *A, int lda,
+// Block products on the FP64 matrix cores (16x16x4 f64 MFMA: A lane l holds
+// (row l % 16, k l / 16), B lane l holds (k l / 16, column l % 16), register
+// v of the accumulator is (row l / 16 + 4 v, column l % 16)).  Each wave owns
+// 16 x 16 tiles of C in turn and runs its k-steps in batches of kBlkKB with
+// all their loads in flight; operands past the matrix edges are clamped on
+// load and zeroed.  Generic pointers (LDS or global); C must not alias A or
+// B.  Both end with a barrier.
+constexpr int kBlkKB = 8;
+
+// C (M x N) = alpha A^T B for A (K x M, lda) and B (K x N, ldb)
+__device__ void blk_mfma_tn(int M, int N, int K, double alpha, const double *A, int lda,
                             const double *B, int ldb, double *C, int ldc) {
-  const int lane = threadIdx.x & 15, grp = threadIdx.x >> 4, ng = blockDim.x >> 4;
-  for (int e = grp; e < M * N; e += ng) {   // uniform within a DPP row
-    const int i = e % M, j = e / M;
-    double s = 0.0;
-#pragma unroll 4
-    for (int t = lane; t < K; t += 16) s += A[t + size_t(i) * lda] * B[t + size_t(j) * ldb];
-    s = row16_sum(s);
-    if (lane == 0) C[i + size_t(j) * ldc] = alpha * s;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int c = lane & 15, q = lane >> 4;
+  const int TM = (M + 15) / 16, TN = (N + 15) / 16, KS = (K + 3) / 4;
+  for (int t = w; t < TM * TN; t += nw) {
+    const int i0 = 16 * (t % TM), j0 = 16 * (t / TM);
+    const double *Ap = A + size_t(min(i0 + c, M - 1)) * lda;
+    const double *Bp = B + size_t(min(j0 + c, N - 1)) * ldb;
+    sd4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int s0 = 0; s0 < KS; s0 += kBlkKB) {
+      double a[kBlkKB], b[kBlkKB];
+#pragma unroll
+      for (int u = 0; u < kBlkKB; ++u) {
+        const int k = 4 * (s0 + u) + q, kc = min(k, K - 1);
+        const double av = Ap[kc], bv = Bp[kc];
+        a[u] = k < K ? av : 0.0;
+        b[u] = k < K ? bv : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kBlkKB; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + q + 4 * v, j = j0 + c;
+      if (i < M && j < N) C[i + size_t(j) * ldc] = alpha * acc[v];
+    }
+  }
+  __syncthreads();
+}
+
+// C (M x N) = beta C + alpha A B for A (M x K, lda) and B (K x N, ldb); C is
+// not read when beta == 0
+__device__ void blk_mfma_nn(int M, int N, int K, double alpha, const double *A, int lda,
+                            const double *B, int ldb, double beta, double *C, int ldc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int c = lane & 15, q = lane >> 4;
+  const int TM = (M + 15) / 16, TN = (N + 15) / 16, KS = (K + 3) / 4;
+  for (int t = w; t < TM * TN; t += nw) {
+    const int i0 = 16 * (t % TM), j0 = 16 * (t / TM);
+    const double *Ap = A + min(i0 + c, M - 1);
+    const double *Bp = B + size_t(min(j0 + c, N - 1)) * ldb;
+    sd4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int s0 = 0; s0 < KS; s0 += kBlkKB) {
+      double a[kBlkKB], b[kBlkKB];
+#pragma unroll
+      for (int u = 0; u < kBlkKB; ++u) {
+        const int k = 4 * (s0 + u) + q, kc = min(k, K - 1);
+        const double av = Ap[size_t(kc) * lda], bv = Bp[kc];
+        a[u] = k < K ? av : 0.0;
+        b[u] = k < K ? bv : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kBlkKB; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + q + 4 * v, j = j0 + c;
+      if (i < M && j < N) {
+        double *o = C + i + size_t(j) * ldc;
+        *o = beta == 0.0 ? alpha * acc[v] : beta * *o + alpha * acc[v];
+      }
+    }
   }
   __syncthreads();
 }
@@ -503,7 +565,6 @@ __device__ int blk_fill(double *Q, int ldq, int p, int cnt, int need, int ncand,
 // lane l holds (k l / 16, column l % 16), register v of the accumulator is
 // (row l / 16 + 4 v, column l % 16) -- for row tile t of T that is the B
 // operand of k-step 4 t + v of the second product.
-typedef double sd4 __attribute__((ext_vector_type(4)));
 constexpr int kSmMaxDk = 6;
 
 // LDS row stride of the W copy for 16 pt rows: a multiple of 16 doubles with
@@ -807,17 +868,10 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
   for (int e = threadIdx.x; e < m * r; e += blockDim.x) R[e] = L[e];
   __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {
-    blk_gemm_tn(r, r, m, 1.0, Vh, ldv, R, m, G, r);                      // G = V^T R
-    for (int e = threadIdx.x; e < m * r; e += blockDim.x) {              // R -= V G
-      int i = e % m, j = e / m;
-      double s = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < r; ++k) s += Vh[i + size_t(k) * ldv] * G[k + j * r];
-      R[e] -= s;
-    }
-    __syncthreads();
+    blk_mfma_tn(r, r, m, 1.0, Vh, ldv, R, m, G, r);                      // G = V^T R
+    blk_mfma_nn(m, r, r, -1.0, Vh, ldv, G, r, 1.0, R, m);                // R -= V G
   }
-  blk_gemm_tn(r, r, m, 1.0, R, m, R, m, W, r);                           // W = R^T R
+  blk_mfma_tn(r, r, m, 1.0, R, m, R, m, W, r);                           // W = R^T R
   if (r <= 64)
     blk_svd_qr(W, r, r, Q, Xs, Xs + r * r, Xs + 2 * r * r, &flag, red);
   else
@@ -828,51 +882,34 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
   int kept = 0;
   for (int t = 0; t < r; ++t)
     if (sig[order[t]] > thresh && sig[order[t]] > 0.0) ++kept;
-  // X1 = R Q_k diag(lambda^-1/2)
-  for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
-    int i = e % m, c = e / m;
-    int j = order[c];
-    double s = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < r; ++k) s += R[i + size_t(k) * m] * Q[k + j * r];
-    X[i + size_t(c) * m] = s / sqrt(sig[j]);
+  // X1 = R Q_k diag(lambda^-1/2): the kept eigenvectors, scaled, in G
+  for (int e = threadIdx.x; e < r * kept; e += blockDim.x) {
+    const int k = e % r, j = order[e / r];
+    G[e] = Q[k + j * r] / sqrt(sig[j]);
   }
   __syncthreads();
+  blk_mfma_nn(m, kept, r, 1.0, R, m, G, r, 0.0, X, m);
   if (kept > 0) {
     // second pass: project once more against V, then X = X1 Q2 diag(lambda2^-1/2)
-    blk_gemm_tn(r, kept, m, 1.0, Vh, ldv, X, m, G, r);
-    for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
-      int i = e % m, j = e / m;
-      double s = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < r; ++k) s += Vh[i + size_t(k) * ldv] * G[k + j * r];
-      X[e] -= s;
-    }
-    __syncthreads();
-    blk_gemm_tn(kept, kept, m, 1.0, X, m, X, m, W, kept);
+    blk_mfma_tn(r, kept, m, 1.0, Vh, ldv, X, m, G, r);
+    blk_mfma_nn(m, kept, r, -1.0, Vh, ldv, G, r, 1.0, X, m);
+    blk_mfma_tn(kept, kept, m, 1.0, X, m, X, m, W, kept);
     // second pass: Cholesky of the well-conditioned Gram (span unchanged),
     // the eigen-decomposition as the fallback
     if (blk_chol_orth(W, kept, kept, Q, kept, red, &flag)) {
-      for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
-        int i = e % m, c = e / m;
-        double s = 0.0;
-#pragma unroll 8
-        for (int k = 0; k <= c; ++k) s += X[i + size_t(k) * m] * Q[k + c * kept];
-        Vh[i + size_t(r + c) * ldv] = s;
-      }
+      // Q = L^{-T} is upper triangular with its lower part zero
+      blk_mfma_nn(m, kept, kept, 1.0, X, m, Q, kept, 0.0, Vh + size_t(r) * ldv, ldv);
     } else {
-      blk_gemm_tn(kept, kept, m, 1.0, X, m, X, m, W, kept);
+      blk_mfma_tn(kept, kept, m, 1.0, X, m, X, m, W, kept);
       blk_jacobi(W, kept, kept, kept, Q, kept, &flag, red);
       __syncthreads();
       blk_colnorms_sorted(W, kept, kept, kept, sig, order);
-      for (int e = threadIdx.x; e < m * kept; e += blockDim.x) {
-        int i = e % m, c = e / m;
-        int j = order[c];
-        double s = 0.0;
-#pragma unroll 8
-        for (int k = 0; k < kept; ++k) s += X[i + size_t(k) * m] * Q[k + j * kept];
-        Vh[i + size_t(r + c) * ldv] = s / sqrt(sig[j]);
+      for (int e = threadIdx.x; e < kept * kept; e += blockDim.x) {
+        const int k = e % kept, j = order[e / kept];
+        G[e] = Q[k + j * kept] / sqrt(sig[j]);
       }
+      __syncthreads();
+      blk_mfma_nn(m, kept, kept, 1.0, X, m, G, kept, 0.0, Vh + size_t(r) * ldv, ldv);
     }
   }
   for (int e = threadIdx.x; e < m * (r - kept); e += blockDim.x) {
@@ -1070,7 +1107,7 @@ __global__ __launch_bounds__(kWG) void k_qr_complete(int m, int r, const double 
   if constexpr (QL)
     for (int e = threadIdx.x; e < m * cnt; e += blockDim.x) Vt[e] = Q[e];
   // S~ = L1^T V~
-  blk_gemm_tn(r, r, m, 1.0, L1, m, Q, m, St, lds);
+  blk_mfma_tn(r, r, m, 1.0, L1, m, Q, m, St, lds);
 }
 
 __global__ void k_check_finite(const double *__restrict__ x, int count, Ctl *ctl) {
