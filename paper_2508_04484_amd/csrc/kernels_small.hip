@@ -14,7 +14,7 @@ namespace {
 constexpr int kT = 16;
 constexpr int kWG = 512;   // threads of the single-workgroup kernels
 typedef double sd4 __attribute__((ext_vector_type(4)));   // f64 MFMA accumulator
-constexpr int kTruncLdsDoubles = 19200;   // LDS room of k_truncate (150 KiB)
+constexpr int kTruncLdsDoubles = 19456;   // LDS room of k_truncate (152 KiB)
 constexpr size_t kSmallMaxLds = 150 * 1024;   // largest dynamic LDS a small kernel asks for
 
 // ------------------------------------------------------------------ small GEMM
@@ -101,6 +101,14 @@ __device__ inline double dpp_mov(double x) {
 // exchanges (swap neighbours, swap pairs of a quad, mirror each half row,
 // mirror the row).  Every step pairs lanes symmetrically, so all 16 lanes end
 // with the same bits.
+// sum over the 8 lanes of each half of a DPP row
+__device__ inline double row8_sum(double x) {
+  x += dpp_mov<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += dpp_mov<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += dpp_mov<0x141>(x);   // row_half_mirror
+  return x;
+}
+
 __device__ inline double row16_sum(double x) {
   x += dpp_mov<0xB1>(x);    // quad_perm [1, 0, 3, 2]
   x += dpp_mov<0x4E>(x);    // quad_perm [2, 3, 0, 1]
@@ -205,12 +213,17 @@ __device__ void blk_mfma_nn(int M, int N, int K, double alpha, const double *A, 
 // Pair (i, j) with i < j that group k of a round-robin round plays, for qe
 // (even) columns: one column stays put, the others rotate.
 __device__ inline void rr_pair(int qe, int round, int k, int &i, int &j) {
+  // round < qe - 1 and k < qe / 2: one conditional subtraction replaces the
+  // modulo qe - 1
+  const int n = qe - 1;
   if (k == 0) {
     i = round;
-    j = qe - 1;
+    j = n;
   } else {
-    i = (round + k) % (qe - 1);
-    j = (round - k + qe - 1) % (qe - 1);
+    i = round + k;
+    i -= i >= n ? n : 0;
+    j = round - k + n;
+    j -= j >= n ? n : 0;
   }
   if (i > j) {
     const int t = i;
@@ -219,15 +232,16 @@ __device__ inline void rr_pair(int qe, int round, int k, int &i, int &j) {
   }
 }
 
-// Rounds of the one-sided Jacobi below for p, q <= 64 when the workgroup has
-// 16 lanes for every pair of a round: the lanes of a pair hold its two
-// columns of A and of V in registers (rows lane, lane + 16, ...), so each
-// round issues all its LDS reads at once and sums the three inner products
-// across the 16 lanes of a DPP row.  Same ordering, rotation rule and
-// stopping test as the general rounds.
+// Rounds of the one-sided Jacobi below for p, q <= LP * RPL when the
+// workgroup has LP lanes (16 or 8, within one DPP row) for every pair of a
+// round: the lanes of a pair hold its two columns of A and of V in registers
+// (rows lane, lane + LP, ...), so each round issues all its LDS reads at
+// once and sums the three inner products across the LP lanes by DPP.  Same
+// ordering, rotation rule and stopping test as the general rounds.
+template <int LP, int RPL, bool ACCV>
 __device__ void jacobi_rounds_reg(double *A, int lda, int p, int q, double *V, int ldv,
                                   int *flag, double tiny) {
-  constexpr int LP = 16, RPL = 4;   // lanes per pair, rows per lane
+  static_assert(LP == 16 || LP == 8, "a pair's lanes lie in one DPP row");
   const int tid = threadIdx.x;
   const int qe = q + (q & 1);
   const int lane = tid % LP, k = tid / LP;
@@ -247,15 +261,23 @@ __device__ void jacobi_rounds_reg(double *A, int lda, int p, int q, double *V, i
         const bool inA = valid && t < p, inV = valid && t < q;
         a[u] = inA ? A[t + size_t(i) * lda] : 0.0;
         b[u] = inA ? A[t + size_t(j) * lda] : 0.0;
-        va[u] = inV ? V[t + size_t(i) * ldv] : 0.0;
-        vb[u] = inV ? V[t + size_t(j) * ldv] : 0.0;
+        if constexpr (ACCV) {
+          va[u] = inV ? V[t + size_t(i) * ldv] : 0.0;
+          vb[u] = inV ? V[t + size_t(j) * ldv] : 0.0;
+        }
         al += a[u] * a[u];
         be += b[u] * b[u];
         ga += a[u] * b[u];
       }
-      al = row16_sum(al);
-      be = row16_sum(be);
-      ga = row16_sum(ga);
+      if constexpr (LP == 16) {
+        al = row16_sum(al);
+        be = row16_sum(be);
+        ga = row16_sum(ga);
+      } else {
+        al = row8_sum(al);
+        be = row8_sum(be);
+        ga = row8_sum(ga);
+      }
       if (valid && al > 0.0 && be > 0.0 && fabs(ga) > 1e-15 * sqrt(al * be) &&
           fabs(ga) > tiny) {
         const double zeta = (be - al) / (2.0 * ga);
@@ -268,7 +290,7 @@ __device__ void jacobi_rounds_reg(double *A, int lda, int p, int q, double *V, i
             A[r + size_t(i) * lda] = c * a[u] - s * b[u];
             A[r + size_t(j) * lda] = s * a[u] + c * b[u];
           }
-          if (r < q) {
+          if (ACCV && r < q) {
             V[r + size_t(i) * ldv] = c * va[u] - s * vb[u];
             V[r + size_t(j) * ldv] = s * va[u] + c * vb[u];
           }
@@ -284,9 +306,9 @@ __device__ void jacobi_rounds_reg(double *A, int lda, int p, int q, double *V, i
 }
 
 // One-sided Jacobi: orthogonalise the q columns (length p) of A, accumulating
-// the rotations in V (q x q, initialised here).  Parallel round-robin
+// the rotations in V (q x q, initialised here) unless V is null.  Parallel round-robin
 // ordering; 8 lanes per column pair, or the register rounds above when the
-// matrix is at most 64 x 64.  A pair is rotated when its inner
+// matrix is at most 128 x 128.  A pair is rotated when its inner
 // product is above 1e-15 of the columns' norms and above 1e-30 ||A||_F^2:
 // pairs of columns that are both negligible against the matrix (singular
 // values below ~1e-15 of the largest) carry only rounding noise, and
@@ -294,7 +316,8 @@ __device__ void jacobi_rounds_reg(double *A, int lda, int p, int q, double *V, i
 __device__ __attribute__((always_inline)) void blk_jacobi(double *A, int lda, int p, int q, double *V, int ldv, int *flag,
                            double *red) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < q * q; e += blockDim.x) V[(e % q) + size_t(e / q) * ldv] = (e % q == e / q) ? 1.0 : 0.0;
+  if (V != nullptr)
+    for (int e = tid; e < q * q; e += blockDim.x) V[(e % q) + size_t(e / q) * ldv] = (e % q == e / q) ? 1.0 : 0.0;
   double fro = 0.0;
   for (int e = tid; e < p * q; e += blockDim.x) {
     const double a = A[(e % p) + size_t(e / p) * lda];
@@ -305,7 +328,13 @@ __device__ __attribute__((always_inline)) void blk_jacobi(double *A, int lda, in
   const int qe = q + (q & 1);
   if (qe < 2) return;
   if (p <= 64 && q <= 64 && (qe / 2) * 16 <= int(blockDim.x) && blockDim.x % 64 == 0) {
-    jacobi_rounds_reg(A, lda, p, q, V, ldv, flag, tiny);
+    if (V != nullptr) jacobi_rounds_reg<16, 4, true>(A, lda, p, q, V, ldv, flag, tiny);
+    else jacobi_rounds_reg<16, 4, false>(A, lda, p, q, V, ldv, flag, tiny);
+    return;
+  }
+  if (p <= 128 && q <= 128 && (qe / 2) * 8 <= int(blockDim.x) && blockDim.x % 64 == 0) {
+    if (V != nullptr) jacobi_rounds_reg<8, 16, true>(A, lda, p, q, V, ldv, flag, tiny);
+    else jacobi_rounds_reg<8, 16, false>(A, lda, p, q, V, ldv, flag, tiny);
     return;
   }
   const int lane8 = tid & 7;
@@ -343,11 +372,12 @@ __device__ __attribute__((always_inline)) void blk_jacobi(double *A, int lda, in
             A[u + size_t(i) * lda] = c * a - s * b;
             A[u + size_t(j) * lda] = s * a + c * b;
           }
-          for (int u = lane8; u < q; u += 8) {
-            double a = V[u + size_t(i) * ldv], b = V[u + size_t(j) * ldv];
-            V[u + size_t(i) * ldv] = c * a - s * b;
-            V[u + size_t(j) * ldv] = s * a + c * b;
-          }
+          if (V != nullptr)
+            for (int u = lane8; u < q; u += 8) {
+              double a = V[u + size_t(i) * ldv], b = V[u + size_t(j) * ldv];
+              V[u + size_t(i) * ldv] = c * a - s * b;
+              V[u + size_t(j) * ldv] = s * a + c * b;
+            }
           if (lane8 == 0) *flag = 1;
         }
       }
@@ -359,17 +389,26 @@ __device__ __attribute__((always_inline)) void blk_jacobi(double *A, int lda, in
   }
 }
 
-// SVD of A (p x q, q <= p <= 64) by one-sided Jacobi with QR preconditioning
-// (Householder A = H [R; 0], H = H_0 ... H_{q-1}; Jacobi on R^T, whose
-// columns converge in far fewer sweeps than those of a graded A):
+// SVD of A (p x q, q <= p <= kSvdMaxP) by one-sided Jacobi with QR
+// preconditioning (Householder A = H [R; 0], H = H_0 ... H_{q-1}; Jacobi on
+// R^T, whose columns converge in far fewer sweeps than those of a graded A):
 // R^T Z = Y with orthogonal columns, sigma_j = ||Y_j||, and then
 // A V = H [Z; 0] diag(sigma) for V = Y diag(1 / sigma).  Leaves the same
 // outputs as blk_jacobi on A: A <- A V (columns u_j sigma_j), V the right
-// singular vectors (a zero column where sigma_j = 0).  X (q x q), B (p x q)
-// and hb (2 q) are scratch; one DPP row of 16 lanes works on one column.
+// singular vectors (a zero column where sigma_j = 0).  Without LEFT the
+// rotations are not accumulated and only V and sig[j] = sigma_j are formed (A
+// is left as scratch).  X (q x q) and hb (2 q) are scratch; one DPP row of 16 lanes works on one column, and H [Z; 0] is
+// formed in registers (a DPP row holds up to kSvdCpg columns, 8 rows a lane),
+// so the workgroup needs q <= kSvdCpg * blockDim / 16.
+constexpr int kSvdMaxP = 128, kSvdCpg = 4;
+// the single-workgroup kernels hold an order-n SVD's A, V, X and 2 n in LDS
+inline __host__ __device__ bool svd_qr_fits(int n) {
+  return n <= kSvdMaxP && 3 * n * n + 2 * n <= kTruncLdsDoubles;
+}
+template <bool LEFT>
 __device__ __attribute__((always_inline)) void blk_svd_qr(double *A, int p, int q, double *V,
-                                                          double *X, double *B, double *hb,
-                                                          int *flag, double *red) {
+                                                          double *X, double *hb, int *flag,
+                                                          double *red, double *sig) {
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4, ng = blockDim.x >> 4;
   double *beta = hb, *rdiag = hb + q;
   // Householder QR: reflector k in A[k:, k], R above the diagonal of A
@@ -413,38 +452,72 @@ __device__ __attribute__((always_inline)) void blk_svd_qr(double *A, int p, int 
     X[e] = b < a ? A[b + size_t(a) * p] : (b == a ? rdiag[a] : 0.0);
   }
   __syncthreads();
-  blk_jacobi(X, q, q, q, V, q, flag, red);   // X <- Y, V <- Z
+  blk_jacobi(X, q, q, q, LEFT ? V : nullptr, q, flag, red);   // X <- Y, V <- Z
   __syncthreads();
-  // B = H [Z; 0], reflectors applied last to first; a row owns its columns
-  for (int e = tid; e < p * q; e += blockDim.x) {
-    const int i = e % p, j = e / p;
-    B[e] = i < q ? V[i + size_t(j) * q] : 0.0;
+  if constexpr (!LEFT) {
+    // right singular vectors and singular values only
+    for (int j = grp; j < q; j += ng) {   // uniform within a DPP row
+      double s2 = 0.0;
+#pragma unroll 4
+      for (int t = lane; t < q; t += 16) s2 += X[t + size_t(j) * q] * X[t + size_t(j) * q];
+      const double sg = sqrt(row16_sum(s2));
+#pragma unroll 4
+      for (int t = lane; t < q; t += 16)
+        V[t + size_t(j) * q] = sg > 0.0 ? X[t + size_t(j) * q] / sg : 0.0;
+      if (lane == 0) sig[j] = sg;
+    }
+    __syncthreads();
+    return;
   }
-  __syncthreads();
-  for (int j = grp; j < q; j += ng) {
-    for (int k = q - 1; k >= 0; --k) {
-      const double *x = A + k + size_t(k) * p;
-      double *y = B + k + size_t(j) * p;
-      const int len = p - k;
-      double w = 0.0;
-#pragma unroll 4
-      for (int t = lane; t < len; t += 16) w += x[t] * y[t];
-      w = row16_sum(w) * beta[k];
-#pragma unroll 4
-      for (int t = lane; t < len; t += 16) y[t] -= w * x[t];
+  // B = H [Z; 0] in registers, reflectors applied last to first: DPP row grp
+  // owns columns grp + cc ng, its lane the rows lane + 16 u
+  constexpr int RPL = kSvdMaxP / 16;
+  double y[kSvdCpg][RPL];
+#pragma unroll
+  for (int cc = 0; cc < kSvdCpg; ++cc) {
+    const int j = min(grp + cc * ng, q - 1);
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int t = lane + 16 * u;
+      y[cc][u] = t < q ? V[t + size_t(j) * q] : 0.0;
     }
   }
-  __syncthreads();
-  for (int j = grp; j < q; j += ng) {
-    double s2 = 0.0;
+  for (int k = q - 1; k >= 0; --k) {
+    double x[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int t = lane + 16 * u;
+      x[u] = (t >= k && t < p) ? A[t + size_t(k) * p] : 0.0;
+    }
+    const double bk = beta[k];
+#pragma unroll
+    for (int cc = 0; cc < kSvdCpg; ++cc) {
+      double w = 0.0;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) w += x[u] * y[cc][u];
+      w = row16_sum(w) * bk;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) y[cc][u] -= w * x[u];
+    }
+  }
+  __syncthreads();   // every row has read the reflectors in A
+#pragma unroll
+  for (int cc = 0; cc < kSvdCpg; ++cc) {
+    const int j = grp + cc * ng;
+    if (j < q) {   // uniform within a DPP row
+      double s2 = 0.0;
 #pragma unroll 4
-    for (int t = lane; t < q; t += 16) s2 += X[t + size_t(j) * q] * X[t + size_t(j) * q];
-    const double sg = sqrt(row16_sum(s2));
+      for (int t = lane; t < q; t += 16) s2 += X[t + size_t(j) * q] * X[t + size_t(j) * q];
+      const double sg = sqrt(row16_sum(s2));
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        const int t = lane + 16 * u;
+        if (t < p) A[t + size_t(j) * p] = y[cc][u] * sg;
+      }
 #pragma unroll 4
-    for (int t = lane; t < p; t += 16) A[t + size_t(j) * p] = B[t + size_t(j) * p] * sg;
-#pragma unroll 4
-    for (int t = lane; t < q; t += 16)
-      V[t + size_t(j) * q] = sg > 0.0 ? X[t + size_t(j) * q] / sg : 0.0;
+      for (int t = lane; t < q; t += 16)
+        V[t + size_t(j) * q] = sg > 0.0 ? X[t + size_t(j) * q] / sg : 0.0;
+    }
   }
   __syncthreads();
 }
@@ -500,6 +573,18 @@ __device__ bool blk_chol_orth(double *A, int lda, int q, double *T, int ldt, dou
 }
 
 // column norms of A (p x q) -> sig[q]; order[] = indices sorted by sig descending
+// order[] = indices of sig[0 .. q - 1] sorted descending, ranked by counting
+// (stable for ties by index)
+__device__ void blk_sort_desc(const double *sig, int q, int *order) {
+  for (int j = threadIdx.x; j < q; j += blockDim.x) {
+    int pos = 0;
+    for (int t = 0; t < q; ++t)
+      if (sig[t] > sig[j] || (sig[t] == sig[j] && t < j)) ++pos;
+    order[pos] = j;
+  }
+  __syncthreads();
+}
+
 __device__ void blk_colnorms_sorted(const double *A, int lda, int p, int q, double *sig,
                                     int *order) {
   for (int j = threadIdx.x; j < q; j += blockDim.x) {
@@ -508,14 +593,7 @@ __device__ void blk_colnorms_sorted(const double *A, int lda, int p, int q, doub
     sig[j] = sqrt(s);
   }
   __syncthreads();
-  // rank by counting (stable for ties by index)
-  for (int j = threadIdx.x; j < q; j += blockDim.x) {
-    int pos = 0;
-    for (int t = 0; t < q; ++t)
-      if (sig[t] > sig[j] || (sig[t] == sig[j] && t < j)) ++pos;
-    order[pos] = j;
-  }
-  __syncthreads();
+  blk_sort_desc(sig, q, order);
 }
 
 // Append up to `need` fillers to the orthonormal columns Q[:, 0:cnt) (length p)
@@ -827,13 +905,16 @@ __global__ __launch_bounds__(kWG) void k_gram_orth(int q, const double *__restri
     __syncthreads();
   }
   // the QR-preconditioned SVD when its scratch is in the launch's LDS
-  if (qq <= 64)
-    blk_svd_qr(A, qq, qq, V, dyn + 2 * q * q, dyn + 3 * q * q, dyn + 4 * q * q, &flag, red);
-  else
+  // for the PSD W the singular values are its eigenvalues (the column norms
+  // of W V)
+  if (svd_qr_fits(q)) {
+    blk_svd_qr<false>(A, qq, qq, V, dyn + 2 * q * q, dyn + 3 * q * q, &flag, red, sig);
+    blk_sort_desc(sig, qq, order);
+  } else {
     blk_jacobi(A, qq, qq, qq, V, qq, &flag, red);
-  __syncthreads();
-  // for the PSD W, the column norms of W V are its eigenvalues
-  blk_colnorms_sorted(A, qq, qq, qq, sig, order);
+    __syncthreads();
+    blk_colnorms_sorted(A, qq, qq, qq, sig, order);
+  }
   const double thresh = restrict_count ? 0.0 : tol2 * (*normsq);
   int kept = 0;
   for (int t = 0; t < qq; ++t)
@@ -860,7 +941,7 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
   double *G = dyn;                     // r x r (LDS)
   double *W = G + r * r;               // r x r (LDS)
   double *Q = W + r * r;               // r x r (LDS)
-  double *Xs = Q + r * r;              // r x r, r x r, 2 r: SVD scratch (LDS, r <= 64)
+  double *Xs = Q + r * r;              // r x r, 2 r: SVD scratch (LDS, r <= 64)
   // ||L||_F^2
   double nl = 0.0;
   for (int e = threadIdx.x; e < m * r; e += blockDim.x) nl += L[e] * L[e];
@@ -872,12 +953,14 @@ __global__ __launch_bounds__(kWG) void k_vaug(int m, int r, double *Vh, int ldv,
     blk_mfma_nn(m, r, r, -1.0, Vh, ldv, G, r, 1.0, R, m);                // R -= V G
   }
   blk_mfma_tn(r, r, m, 1.0, R, m, R, m, W, r);                           // W = R^T R
-  if (r <= 64)
-    blk_svd_qr(W, r, r, Q, Xs, Xs + r * r, Xs + 2 * r * r, &flag, red);
-  else
+  if (r <= 64) {
+    blk_svd_qr<false>(W, r, r, Q, Xs, Xs + r * r, &flag, red, sig);
+    blk_sort_desc(sig, r, order);
+  } else {
     blk_jacobi(W, r, r, r, Q, r, &flag, red);
-  __syncthreads();
-  blk_colnorms_sorted(W, r, r, r, sig, order);
+    __syncthreads();
+    blk_colnorms_sorted(W, r, r, r, sig, order);
+  }
   const double thresh = tol * tol * nl;
   int kept = 0;
   for (int t = 0; t < r; ++t)
@@ -936,8 +1019,8 @@ __global__ __launch_bounds__(kWG) void k_truncate(const double *__restrict__ Sh,
   const int p = cols ? pU : pV, q = cols ? pV : pU;
   // p x q matrix and q x q rotations in LDS when the launch provided room
   const bool in_lds = size_t(P) * P * 2 <= size_t(kTruncLdsDoubles);
-  // room for the QR-preconditioned SVD (two more P x P blocks and 2P)
-  const bool pre = P <= 64 && size_t(P) * P * 4 + 2 * P <= size_t(kTruncLdsDoubles);
+  // room for the QR-preconditioned SVD (one more P x P block and 2P)
+  const bool pre = svd_qr_fits(P);
   double *A = in_lds ? dyn : work;
   double *V = A + P * P;
   for (int e = threadIdx.x; e < p * q; e += blockDim.x) {
@@ -947,8 +1030,8 @@ __global__ __launch_bounds__(kWG) void k_truncate(const double *__restrict__ Sh,
   __syncthreads();
   // the branch lets the LDS case address the matrices as LDS
   if (pre)
-    blk_svd_qr(dyn, p, q, dyn + P * P, dyn + 2 * P * P, dyn + 3 * P * P, dyn + 4 * P * P,
-               &flag, red);
+    blk_svd_qr<true>(dyn, p, q, dyn + P * P, dyn + 2 * P * P, dyn + 3 * P * P, &flag, red,
+                     nullptr);
   else if (in_lds) blk_jacobi(dyn, p, p, q, dyn + P * P, q, &flag, red);
   else blk_jacobi(work, p, p, q, work + P * P, q, &flag, red);
   __syncthreads();
@@ -1227,8 +1310,8 @@ void launch_copy_block(int rows, int cols, const double *src, int lds, double *d
 void launch_gram_orth(int q, const double *W, double *T, int ldt, double tol2,
                       const double *normsq, int *count, const int *restrict_count, double *work,
                       hipStream_t st) {
-  // A, V, and for q <= 64 the QR-preconditioned SVD's X, B (q x q) and 2 q
-  const size_t shm = (q <= 64 ? size_t(4) * q * q + 2 * q : size_t(2) * q * q) * sizeof(double);
+  // A, V, and the QR-preconditioned SVD's X (q x q) and 2 q when they fit
+  const size_t shm = (svd_qr_fits(q) ? size_t(3) * q * q + 2 * q : size_t(2) * q * q) * sizeof(double);
   if (shm > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_gram_orth),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
@@ -1237,8 +1320,8 @@ void launch_gram_orth(int q, const double *W, double *T, int ldt, double tol2,
 
 void launch_vaug(int m, int r, double *Vh, int ldv, const double *L, double tol, int *count,
                  double *work, hipStream_t st) {
-  // G, W, Q, and for r <= 64 the QR-preconditioned SVD's scratch (2 r^2 + 2 r)
-  const size_t shm = (r <= 64 ? size_t(5) * r * r + 2 * r : size_t(3) * r * r) * sizeof(double);
+  // G, W, Q, and for r <= 64 the QR-preconditioned SVD's scratch (r^2 + 2 r)
+  const size_t shm = (r <= 64 ? size_t(4) * r * r + 2 * r : size_t(3) * r * r) * sizeof(double);
   if (shm > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_vaug),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
@@ -1248,8 +1331,8 @@ void launch_vaug(int m, int r, double *Vh, int ldv, const double *L, double tol,
 void launch_truncate(const double *Sh, int P, const int *kU, const int *kV, int r_base,
                      TruncOpt opt, double *Pp, double *Qp, double *Sp, int lds, Ctl *ctl,
                      double *work, hipStream_t st) {
-  const bool pre = P <= 64 && size_t(P) * P * 4 + 2 * P <= size_t(kTruncLdsDoubles);
-  const size_t shm = pre ? (size_t(P) * P * 4 + 2 * P) * sizeof(double)
+  const bool pre = svd_qr_fits(P);
+  const size_t shm = pre ? (size_t(P) * P * 3 + 2 * P) * sizeof(double)
                      : size_t(P) * P * 2 <= size_t(kTruncLdsDoubles)
                          ? size_t(P) * P * 2 * sizeof(double)
                          : 0;
