@@ -143,7 +143,10 @@ bool make_dims(const dlra_grid *g, int n_mat, int n_beams, const dlra_options *o
   d.n_beams = n_beams;
   d.n_src = n_mat * n_beams;
   d.P = 2 * d.R;
-  d.ld = (d.n + 63) / 64 * 64;
+  // columns 64-element aligned, and not a power of two apart: a power-of-two
+  // column stride puts the same cell of every column on the same memory
+  // channels
+  d.ld = (d.n + 63) / 64 * 64 + 64;
   d.n_steps = o->n_steps;
   d.G = o->n_groups;
   d.tsize = o->precision == DLRA_FP64 ? 8 : 4;
