@@ -997,13 +997,14 @@ constexpr size_t stencil_proj_lds() {
 // cell) for a fixed stride of columns, all loads of the tile in flight
 // together; then the 4 waves share the NA x NB output tiles (a wave without a
 // tile of its own repeats the last one and does not write it).  Partial sums
-// of block bx go to partial[bx * p * q].
+// of block bx go to partial[bx * p * q].  With same (Y is X, unit weights,
+// square tiles) only X is loaded and its staged tile is both operands.
 constexpr int kGramBlocks = 2048;
 
 template <typename T, typename Tc, int NA, int NB, typename YF, typename WF>
 __global__ __launch_bounds__(256) void k_gram_mfma(int n, const T *__restrict__ X, int ldx, int p,
                                                   YF yf, int q, WF wf, int chunk,
-                                                  double *__restrict__ partial) {
+                                                  double *__restrict__ partial, bool same) {
   using acc_t = typename Mfma<Tc>::acc_t;
   constexpr int CT = 64;
   constexpr int PA = 16 * NA + 1, PB = 16 * NB + 1;   // odd row lengths
@@ -1028,8 +1029,9 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int n, const T *__restrict__ 
     wr = wf(xc);
 #pragma unroll
     for (int i = 0; i < PERA; ++i) xr[i] = X[size_t(min(col0 + 4 * i, p - 1)) * ldx + xc];
+    if (!same)
 #pragma unroll
-    for (int i = 0; i < PERB; ++i) yr[i] = yf(xc, min(col0 + 4 * i, q - 1));
+      for (int i = 0; i < PERB; ++i) yr[i] = yf(xc, min(col0 + 4 * i, q - 1));
   };
   fetch(x_begin);
   for (int x0 = x_begin; x0 < x_end; x0 += CT) {
@@ -1043,21 +1045,25 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int n, const T *__restrict__ 
         const Tc v = Tc(xr[i]) * wt;
         Xs[cc * PA + a] = (xin && a < p) ? v : Tc(0);
       }
+      if (!same)
 #pragma unroll
-      for (int i = 0; i < PERB; ++i) {
-        const int b = col0 + 4 * i;
-        Ys[cc * PB + b] = (xin && b < q) ? Tc(yr[i]) : Tc(0);
-      }
+        for (int i = 0; i < PERB; ++i) {
+          const int b = col0 + 4 * i;
+          Ys[cc * PB + b] = (xin && b < q) ? Tc(yr[i]) : Tc(0);
+        }
     }
     __syncthreads();
     fetch(x0 + CT);
+    // the right factor: its own staged tile, or X's when it is X (same values)
+    const Tc *Yt = same ? Xs : Ys;
+    const int pb = same ? PA : PB;
 #pragma unroll 2
     for (int k4 = 0; k4 < CT / 4; ++k4) {
       const int cell = 4 * k4 + qq;
 #pragma unroll
       for (int u = 0; u < TPW; ++u) {
         const int t = min(w + 4 * u, NT - 1), ta = t % NA, tb = t / NA;
-        acc[u] = Mfma<Tc>::op(Xs[cell * PA + ta * 16 + c], Ys[cell * PB + tb * 16 + c], acc[u]);
+        acc[u] = Mfma<Tc>::op(Xs[cell * PA + ta * 16 + c], Yt[cell * pb + tb * 16 + c], acc[u]);
       }
     }
   }
@@ -1633,18 +1639,18 @@ static void contract(const GridDev &g, const T *X, int ldx, int p, YF yf, int q,
 // p <= 112 (NA <= 7) in both cases, which the callers check.
 template <typename T, typename Tc, int NA, int NB, typename YF, typename WF>
 static void gram_launch_na(int n, const T *X, int ldx, int p, YF yf, int q, WF wf, int nb,
-                           int chunk, double *partial, hipStream_t st) {
+                           int chunk, double *partial, hipStream_t st, bool same) {
   const size_t shm = size_t(64) * (16 * NA + 1 + 16 * NB + 1) * sizeof(Tc);
   auto kern = k_gram_mfma<T, Tc, NA, NB, YF, WF>;
   if (shm > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
-  kern<<<nb, 256, shm, st>>>(n, X, ldx, p, yf, q, wf, chunk, partial);
+  kern<<<nb, 256, shm, st>>>(n, X, ldx, p, yf, q, wf, chunk, partial, same && NA == NB);
 }
 
 template <typename T, typename Tc, bool SQUARE, typename YF, typename WF>
 static void gram(int n, const T *X, int ldx, int p, YF yf, int q, WF wf, double *partial,
-                 size_t partial_elems, hipStream_t st, int &nb_out) {
+                 size_t partial_elems, hipStream_t st, int &nb_out, bool same = false) {
   const size_t pq = size_t(p) * q;
   int nb = std::max(1, std::min(kGramBlocks, (n + 63) / 64));
   while (nb > 1 && size_t(nb + 1) * pq > partial_elems) nb /= 2;
@@ -1653,7 +1659,8 @@ static void gram(int n, const T *X, int ldx, int p, YF yf, int q, WF wf, double 
   nb = (n + chunk - 1) / chunk;
   const int na = (p + 15) / 16;
 #define DLRA_GRAM(NA)                                                                       \
-  gram_launch_na<T, Tc, NA, SQUARE ? NA : 1>(n, X, ldx, p, yf, q, wf, nb, chunk, partial, st)
+  gram_launch_na<T, Tc, NA, SQUARE ? NA : 1>(n, X, ldx, p, yf, q, wf, nb, chunk, partial, st, \
+                                             same)
   switch (na) {
     case 1: DLRA_GRAM(1); break;
     case 2: DLRA_GRAM(2); break;
@@ -1720,9 +1727,9 @@ void launch_gram(int n, const T *X, int ldx, int p, const T *Y, int ldy, int q, 
     if (wmat != nullptr)
       gram<T, Acc, true>(n, X, ldx, p, YMat<T>{Y, ldy}, q, WMatS<T>{wmat, s}, partial,
                          partial_elems, st, nb);
-    else
+    else   // X^T X stages X once
       gram<T, Acc, true>(n, X, ldx, p, YMat<T>{Y, ldy}, q, WOne<T>{}, partial, partial_elems,
-                         st, nb);
+                         st, nb, Y == X && ldy == ldx);
   } else if (wmat != nullptr) {
     contract<T, Acc>(g, X, ldx, p, YMat<T>{Y, ldy}, q, WMatS<T>{wmat, s}, partial,
                      partial_elems, st, nb);
