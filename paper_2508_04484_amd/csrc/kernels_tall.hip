@@ -1295,8 +1295,9 @@ __global__ __launch_bounds__(256) void k_update_mfma(
         for (int u = 0; u < kUpdChunk; ++u) {
           const int k = k0 + 4 * u + qd;
           T v = X[size_t(min(k, p - 1)) * ldx + xc[h]];
-          if (sw != nullptr) {
-            // source column e = b n_mat + i: sdt w_i(x) psi_b(x)
+          // source column e = b n_mat + i: sdt w_i(x) psi_b(x), loaded only
+          // in the column blocks that hold source columns (wave-uniform test)
+          if (sw != nullptr && k0 + 4 * u + 3 >= p) {
             const int e = min(max(k - p, 0), n_src - 1);
             const int b = e / n_mat, i = e - b * n_mat;
             const double src = sdt * double(spsi[size_t(b) * pstride + xc[h]]);
@@ -1417,8 +1418,9 @@ __global__ __launch_bounds__(256) void k_update_vec(
         const int k = k0 + 4 * u + qd;
         const float4 xv = ld4(X + size_t(min(k, p - 1)) * ldx);
         float v[4] = {xv.x, xv.y, xv.z, xv.w};
-        if (sw != nullptr) {
-          // source column e = b n_mat + i: sdt w_i(x) psi_b(x)
+        // source column e = b n_mat + i: sdt w_i(x) psi_b(x), loaded only in
+        // the column blocks that hold source columns (wave-uniform test)
+        if (sw != nullptr && k0 + 4 * u + 3 >= p) {
           const int e = min(max(k - p, 0), n_src - 1);
           const int b = e / n_mat, im = e - b * n_mat;
           const float4 wv = ld4(sw + size_t(im) * n);
