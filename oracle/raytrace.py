@@ -289,8 +289,10 @@ class Tracer:
         nz = np.flatnonzero(om != 0.0)
         return int(nz[0]) if nz.size == 1 else None
 
-    def trace(self, rowwise=True):
-        """Return (psibar (n_steps, n), D_u (n,)) for the beam."""
+    def trace(self, rowwise=True, rows=None):
+        """Return (psibar (n_steps, n), D_u (n,)) for the beam.  For a beam
+        along a grid axis, rows (indices into grid_rows()) restricts the march
+        to those rows; the other cells stay zero."""
         g = self.problem.grid
         o = self.problem.options
         if g.dim == 2 and self.beam.dir[2] != 0.0:
@@ -302,8 +304,10 @@ class Tracer:
         cut = o.beam_cut_sigmas * self.beam.spot_sigma
         ax = self.axis() if rowwise else None
         if ax is not None:
-            self._trace_rows(ax, centers, cut, psibar, Du)
+            self._trace_rows(ax, centers, cut, psibar, Du, rows)
             return psibar, Du
+        if rows is not None:
+            raise ValueError("a row subset needs a beam along a grid axis")
         om = tuple(float(v) for v in self.beam.dir)
         for cell in range(n):
             f, d = lateral(g, self.beam, centers[cell])
@@ -313,13 +317,21 @@ class Tracer:
             psibar[:, cell], Du[cell] = self.outputs(c, cell, f)
         return psibar, Du
 
-    def _trace_rows(self, ax, centers, cut, psibar, Du):
+    def grid_rows(self):
+        """Cell indices of the grid rows along the beam axis, one row per
+        line, in the order the row march takes them (before the beam's sign)."""
         g = self.problem.grid
-        sign = 1 if self.beam.dir[ax] > 0 else -1
         shape = (g.nz, g.ny, g.nx)
         idx = np.arange(g.n).reshape(shape)
-        np_ax = (2, 1, 0)[ax]
-        rows = np.moveaxis(idx, np_ax, -1).reshape(-1, shape[np_ax])
+        np_ax = (2, 1, 0)[self.axis()]
+        return np.moveaxis(idx, np_ax, -1).reshape(-1, shape[np_ax])
+
+    def _trace_rows(self, ax, centers, cut, psibar, Du, only=None):
+        g = self.problem.grid
+        sign = 1 if self.beam.dir[ax] > 0 else -1
+        rows = self.grid_rows()
+        if only is not None:
+            rows = rows[np.asarray(only, dtype=np.int64)]
         D = (g.dx, g.dy, g.dz)[ax]
         for row in rows:
             cells = row if sign > 0 else row[::-1]

@@ -78,6 +78,47 @@ def test_raytrace_parity(name):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_raytrace_full_size_sampled_rows(precision):
+    # the benchmark's beam at full size (128^3 cells, 128 groups, 250 step
+    # tables) in the benchmark's launch configuration (one wave per grid row);
+    # the reference marches five sampled rows: the one on the beam axis, those
+    # nearest 1, 2 and 3 spot sigmas off it and the outermost one inside the
+    # cut.  Bars: 1e-12 of the maximum; with FP32 tables (mixed) the FP32
+    # rounding of each value, 2^-24 of it, on top
+    dl = _gpu()
+    p = configs.c3(precision=precision)
+    b = p.beams[0]
+    tr = raytrace.Tracer(p, b)
+    rows = tr.grid_rows()
+    centers = p.grid.centers()
+    sigma = b.spot_sigma
+    cut = p.options.beam_cut_sigmas * sigma
+    d = np.array([raytrace.lateral(p.grid, b, centers[row[0]])[1] for row in rows])
+    inside = np.flatnonzero(d <= cut)
+    pick = sorted({int(inside[np.argmin(np.abs(d[inside] - t))])
+                   for t in (0.0, sigma, 2 * sigma, 3 * sigma, cut)})
+    say(f"full-size ray tracer, {precision}, rows {pick}")
+    s = dl.BeamSolver(p, 0)
+    s.raytrace()
+    ps, Du = s.uncollided()
+    s.close()
+    cells = rows[pick].ravel()
+    got, got_du = ps[:, cells], Du[cells]
+    del ps, Du
+    ps_ref, du_ref = tr.trace(rows=pick)
+    want, want_du = ps_ref[:, cells], du_ref[cells]
+    del ps_ref, du_ref
+    scale = np.abs(want).max()
+    rnd = 2.0 ** -24 if precision == "mixed" else 0.0
+    excess = np.abs(got - want) - (rnd * np.abs(want) + 1e-12 * scale)
+    e_du = np.abs(got_du - want_du).max() / np.abs(want_du).max()
+    say(f"  max error psibar {np.abs(got - want).max() / scale:.3e} of the maximum, "
+        f"Du {e_du:.3e}")
+    assert scale > 0.0 and excess.max() <= 0.0
+    assert e_du <= 1e-12
+
+
 @pytest.mark.parametrize("name", FREE_RUN_FP64)
 def test_full_run_dose_parity_fp64(name):
     dl = _gpu()

@@ -89,6 +89,22 @@ def test_operator_conserves_particles_up_to_cutoff_outflow():
     assert np.abs(rows - ref).max() < 1e-12
 
 
+def test_row_subset_is_the_full_march_on_those_rows():
+    # a row subset of the march (the full-size GPU test samples rows) gives
+    # exactly the full march's values on its rows and zero elsewhere
+    p = configs.small_3d(n=6, N=2, n_steps=5)
+    tr = raytrace.Tracer(p, p.beams[0])
+    ps, du = tr.trace()
+    rows = tr.grid_rows()
+    pick = [3, 17, 20]
+    ps2, du2 = raytrace.Tracer(p, p.beams[0]).trace(rows=pick)
+    cells = rows[pick].ravel()
+    assert np.array_equal(ps2[:, cells], ps[:, cells]) and np.array_equal(du2[cells], du[cells])
+    rest = np.setdiff1d(np.arange(p.grid.n), cells)
+    assert not ps2[:, rest].any() and not du2[rest].any()
+    assert np.abs(ps[:, cells]).max() > 0.0
+
+
 def test_row_march_equals_per_cell_rays():
     p = configs.small_2d(nx=10, ny=6, N=2, mats="slab", n_steps=6, E0=20.0)
     tr = raytrace.Tracer(p, p.beams[0])
