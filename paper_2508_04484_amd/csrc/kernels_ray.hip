@@ -597,6 +597,8 @@ struct WaveLU {
 
 // psibar_k(x) = f (step window k) . c for every step (lanes over k) and
 // Du(x) += f sum_i w_i (stop_i . c) (wave sum); cl holds 3G doubles of LDS
+constexpr int kOutSteps = 4;   // step tables a lane forms at a time
+
 template <typename T>
 __device__ __forceinline__ void wave_outputs(const RayParams &rp, int lane, const double ce[3],
                                              const double co[3], int x, double f,
@@ -621,13 +623,30 @@ __device__ __forceinline__ void wave_outputs(const RayParams &rp, int lane, cons
   if (go < G)
     for (int k = 0; k < 3; ++k) cl[3 * go + k] = co[k];
   __syncthreads();
+  // lane l takes the steps l, l + 64, ...: kOutSteps of them at a time, with
+  // their window offsets and weights loaded together (same sums as a step at
+  // a time: t ascending from zero)
   const int nw = rp.ng_step * 3;
-  for (int k = lane; k < rp.n_steps; k += 64) {
-    const double *sw = step_w + size_t(k) * nw;
-    const double *cc = cl + 3 * step_g0[k];
-    double acc = 0.0;
-    for (int t = 0; t < nw; ++t) acc += sw[t] * cc[t];
-    psibar[size_t(k) * rp.n + x] = T(f * acc);
+  for (int k0 = 0; k0 < rp.n_steps; k0 += 64 * kOutSteps) {
+    const double *sw[kOutSteps];
+    const double *cc[kOutSteps];
+    double acc[kOutSteps];
+#pragma unroll
+    for (int u = 0; u < kOutSteps; ++u) {
+      const int k = min(k0 + 64 * u + lane, rp.n_steps - 1);
+      sw[u] = step_w + size_t(k) * nw;
+      cc[u] = cl + 3 * step_g0[k];
+      acc[u] = 0.0;
+    }
+#pragma unroll 4
+    for (int t = 0; t < nw; ++t)
+#pragma unroll
+      for (int u = 0; u < kOutSteps; ++u) acc[u] += sw[u][t] * cc[u][t];
+#pragma unroll
+    for (int u = 0; u < kOutSteps; ++u) {
+      const int k = k0 + 64 * u + lane;
+      if (k < rp.n_steps) psibar[size_t(k) * rp.n + x] = T(f * acc[u]);
+    }
   }
   if (lane == 0) Du[x] += f * du;   // beams of a joint context add up, one launch after the other
   __syncthreads();
