@@ -289,10 +289,11 @@ class Tracer:
         nz = np.flatnonzero(om != 0.0)
         return int(nz[0]) if nz.size == 1 else None
 
-    def trace(self, rowwise=True, rows=None):
+    def trace(self, rowwise=True, rows=None, cells=None):
         """Return (psibar (n_steps, n), D_u (n,)) for the beam.  For a beam
         along a grid axis, rows (indices into grid_rows()) restricts the march
-        to those rows; the other cells stay zero."""
+        to those rows; otherwise cells restricts the per-cell rays to those
+        target cells.  The other cells stay zero."""
         g = self.problem.grid
         o = self.problem.options
         if g.dim == 2 and self.beam.dir[2] != 0.0:
@@ -309,7 +310,7 @@ class Tracer:
         if rows is not None:
             raise ValueError("a row subset needs a beam along a grid axis")
         om = tuple(float(v) for v in self.beam.dir)
-        for cell in range(n):
+        for cell in (range(n) if cells is None else (int(c) for c in cells)):
             f, d = lateral(g, self.beam, centers[cell])
             if d > cut:
                 continue

@@ -119,6 +119,50 @@ def test_raytrace_full_size_sampled_rows(precision):
     assert e_du <= 1e-12
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_oblique_raytrace_full_size_sampled_cells(precision):
+    # the first oblique beam of the c4 plan at full size (128^3 cells, 128
+    # groups, 250 step tables; one ray per target cell from the domain
+    # entry), compared at five target cells: on the beam axis 1, 5 and 9 cm
+    # past the entry, and 1 and 2 spot sigmas off it at 5 cm.  Bars as for
+    # the axis beam: 1e-12 of the maximum, plus each value's FP32 rounding
+    # for FP32 tables
+    dl = _gpu()
+    p = configs.c4(precision=precision)
+    b, g = p.beams[0], p.grid
+    N, H = (g.nx, g.ny, g.nz), (g.dx, g.dy, g.dz)
+    u, pos = np.asarray(b.dir), np.asarray(b.pos)
+    lat = np.array([-u[1], u[0], 0.0])
+    # depth along the axis where the beam enters the grid (in-plane beam)
+    s_in = max([(0.0 - pos[a]) / u[a] for a in (0, 1) if u[a] > 0] +
+               [(N[a] * H[a] - pos[a]) / u[a] for a in (0, 1) if u[a] < 0] + [0.0])
+    pts = [pos + (s_in + t) * u for t in (1.0, 5.0, 9.0)]
+    pts += [pos + (s_in + 5.0) * u + k * b.spot_sigma * lat for k in (1.0, 2.0)]
+    cells = []
+    for x in pts:
+        ix, iy, iz = (int(np.floor(x[a] / H[a])) for a in range(3))
+        assert 0 <= ix < N[0] and 0 <= iy < N[1] and 0 <= iz < N[2]
+        cells.append(ix + g.nx * (iy + g.ny * iz))
+    say(f"full-size oblique ray tracer, {precision}, cells {cells}")
+    s = dl.BeamSolver(p, 0)
+    s.raytrace()
+    ps, Du = s.uncollided()
+    s.close()
+    got, got_du = ps[:, cells], Du[cells]
+    del ps, Du
+    ps_ref, du_ref = raytrace.Tracer(p, b).trace(rowwise=False, cells=cells)
+    want, want_du = ps_ref[:, cells], du_ref[cells]
+    del ps_ref, du_ref
+    scale = np.abs(want).max()
+    rnd = 2.0 ** -24 if precision == "mixed" else 0.0
+    excess = np.abs(got - want) - (rnd * np.abs(want) + 1e-12 * scale)
+    e_du = np.abs(got_du - want_du).max() / np.abs(want_du).max()
+    say(f"  max error psibar {np.abs(got - want).max() / scale:.3e} of the maximum, "
+        f"Du {e_du:.3e}")
+    assert scale > 0.0 and excess.max() <= 0.0
+    assert e_du <= 1e-12
+
+
 @pytest.mark.parametrize("name", FREE_RUN_FP64)
 def test_full_run_dose_parity_fp64(name):
     dl = _gpu()

@@ -105,6 +105,17 @@ def test_row_subset_is_the_full_march_on_those_rows():
     assert np.abs(ps[:, cells]).max() > 0.0
 
 
+def test_cell_subset_is_the_per_cell_trace_on_those_cells():
+    p = configs.small_oblique_2d(angle_deg=60.0)
+    tr = raytrace.Tracer(p, p.beams[0])
+    ps, du = tr.trace(rowwise=False)
+    pick = np.flatnonzero(du)[[0, 5, -1]]
+    ps2, du2 = raytrace.Tracer(p, p.beams[0]).trace(rowwise=False, cells=pick)
+    assert np.array_equal(ps2[:, pick], ps[:, pick]) and np.array_equal(du2[pick], du[pick])
+    rest = np.setdiff1d(np.arange(p.grid.n), pick)
+    assert not ps2[:, rest].any() and not du2[rest].any()
+
+
 def test_row_march_equals_per_cell_rays():
     p = configs.small_2d(nx=10, ny=6, N=2, mats="slab", n_steps=6, E0=20.0)
     tr = raytrace.Tracer(p, p.beams[0])
