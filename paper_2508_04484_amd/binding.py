@@ -70,17 +70,24 @@ class Options(C.Structure):
 
 
 _lib = None
+_lib_path = None
 
 
 def load(path: str = LIB_PATH):
-    """Load libdlra.so; raises when it has not been built."""
-    global _lib
+    """Load libdlra.so (once per process: contexts belong to the copy that made
+    them); raises when it has not been built, or when another path is asked
+    for after one has been loaded."""
+    global _lib, _lib_path
     if _lib is not None:
+        if os.path.realpath(path) != _lib_path:
+            raise RuntimeError(f"{_lib_path} is already loaded in this process; "
+                               f"{path} can only be used from another process")
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with "
                            "`python -m paper_2508_04484_amd.build` (no CPU fallback exists)")
     lib = C.CDLL(path)
+    _lib_path = os.path.realpath(path)
     P, I, D, V = C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_void_p
     lib.dlra_workspace_size.argtypes = [C.POINTER(Grid), I, I, C.POINTER(Options),
                                         C.POINTER(C.c_size_t)]

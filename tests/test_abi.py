@@ -124,3 +124,16 @@ def test_plan_objective_rejects_bad_arguments_without_touching_the_gpu():
                                    C.byref(J), gp) == -1
     assert lib.dlra_plan_objective(100, 0, fake, wp, fake, 1.0, 0.1, fake, 10 ** 6, None,
                                    C.byref(J), gp) == -1
+
+
+def test_a_second_library_path_is_refused(tmp_path):
+    # contexts belong to the copy of the library that made them: one copy per
+    # process, and asking for another path is an error rather than a silent
+    # reuse of the first
+    lib = B.load()
+    other = tmp_path / "libdlra_other.so"
+    other.write_bytes(b"")
+    with pytest.raises(RuntimeError):
+        B.load(str(other))
+    assert B.load() is lib
+    assert B.load(B.LIB_PATH) is lib
