@@ -1234,7 +1234,7 @@ void launch_small_gemm(int ta, int tb, int M, int N, int K, double alpha, const 
 void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C, int ldc,
                         const double *in, const double *L0, double *out, double coef,
                         double *T, size_t ts, hipStream_t st) {
-  if (r <= 64 && (ndk == 2 || ndk == 4 || ndk == 6)) {   // one wave per term
+  if (r <= 64 && (ndk == 4 || ndk == 6)) {   // one wave per term (2D, 3D)
     const int nkc = (r + 15) / 16;
     const size_t shm = (size_t(kLsKC) * (16 * nkc + 2) + size_t(ndk) * 16 * 16 * nkc) * 8;
 #define DLRA_LSTEP(NKC, NDK)                                                                 \
@@ -1252,9 +1252,7 @@ void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C,
     case 3: DLRA_LSTEP(3, NDK); break;       \
     default: DLRA_LSTEP(4, NDK); break;      \
   }
-    if (ndk == 2) {
-      DLRA_LSTEP_NKC(2)
-    } else if (ndk == 4) {
+    if (ndk == 4) {
       DLRA_LSTEP_NKC(4)
     } else {
       DLRA_LSTEP_NKC(6)
