@@ -651,8 +651,8 @@ constexpr int kSmMaxDk = 6;
 inline __host__ __device__ int sstep_lds_stride(int pt) { return 16 * pt + ((pt & 1) ? 0 : 16); }
 
 inline size_t sstep_mfma_lds(int p, int ndk) {
-  const int pt = (p + 15) / 16, kr = 4 * ((p + 3) / 4);
-  return (size_t(kr) * sstep_lds_stride(pt) + size_t(ndk) * 256) * sizeof(double);
+  const int pt = (p + 15) / 16;
+  return (size_t(16 * pt) * sstep_lds_stride(pt) + size_t(ndk) * 256) * sizeof(double);
 }
 
 constexpr int kSsBatch = 16;   // W staging loads per thread in flight together
@@ -662,7 +662,10 @@ __global__ __launch_bounds__(64 * kSmMaxDk) void k_sstep_mfma(
     int P, int ld, int ndk, const double *__restrict__ Ch, const double *__restrict__ Bh,
     const double *S0, const double *__restrict__ W, double *out, double coef) {
   extern __shared__ double smem_d[];
-  const int PT = (P + 15) / 16, KS = (P + 3) / 4, KR = 4 * KS, RW = 16 * PT;
+  // W is staged zero padded to RW x RW, so the k-steps run in whole groups
+  // of four (one group per 16 rows of W, guarded once): the group's four
+  // LDS reads issue together; the padded k-steps add exact zeros
+  const int PT = (P + 15) / 16, RW = 16 * PT, KR = RW;
   const int lw = sstep_lds_stride(PT);
   double *Ws = smem_d;                       // [KR k][lw]: W(i, k) at k * lw + i
   double *Rs = Ws + size_t(KR) * lw;         // [ndk][16][16]
@@ -711,10 +714,16 @@ __global__ __launch_bounds__(64 * kSmMaxDk) void k_sstep_mfma(
     if (t < PT) {
       sd4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int s = 0; s < NS; ++s)
-        if (s < KS)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(4 * s + q) * lw + 16 * t + c], bop[s],
-                                                     acc, 0, 0, 0);
+      for (int g4 = 0; g4 < NS / 4; ++g4) {
+        if (g4 < PT) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int s = 4 * g4 + v;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(4 * s + q) * lw + 16 * t + c], bop[s],
+                                                       acc, 0, 0, 0);
+          }
+        }
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         f = __builtin_amdgcn_mfma_f64_16x16x4f64(cop[4 * t + v], acc[v], f, 0, 0, 0);
