@@ -30,7 +30,7 @@ void eigen_split(const std::vector<double> &A, int m, std::vector<double> &Ap,
 void beam_moments(int N, const double dir[3], double *out);
 
 // Linear interpolation with clamping at the table ends, and the slope of the
-// interpolant (zero outside the table).
+// table segment holding E (the end segments' slopes beyond the table).
 double interp(const double *e, const double *v, int n, double E);
 double interp_slope(const double *e, const double *v, int n, double E);
 
