@@ -491,6 +491,42 @@ def fp64_check(problem, K, dose_mixed):
             "note": "mixed (FP32 storage/stencil/projections) against the library's FP64 path"}
 
 
+def achievable_roofs():
+    """Achievable roofs of this GPU, quoted beside the vendor peaks the
+    roofline fractions use: the library's throughput probes (dlra_roof_probe:
+    independent MFMA or FMA chains over every CU) and a 512 MiB
+    device-to-device copy (bytes read + written over the best of three).  A
+    failure is reported in place of the numbers."""
+    import torch
+
+    import paper_2508_04484_amd as dl
+    try:
+        res = {}
+        for kind, iters in (("fp32_mfma", 40000), ("fp64_mfma", 20000), ("fp32_fma", 200000),
+                            ("fp64_fma", 200000)):
+            res[f"{kind}_tflops"] = round(dl.binding.roof_probe(kind, iters), 2)
+        a = torch.ones(512 << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        res["copy_tbs"] = round(2.0 * a.numel() * 4 / (best * 1e-3) / 1e12, 3)
+        del a, b
+        res["vendor_peaks"] = {"fp32_tflops": 157.3, "fp64_tflops": 78.6, "hbm_tbs": 8.0}
+        return res
+    except Exception as e:   # reported, not fatal: the line's other numbers stand
+        return {"error": str(e)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -681,6 +717,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(problem, window=range(K))
     elif not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_2d(problem, window=range(K))
+    out["achievable"] = achievable_roofs()
     print(json.dumps(out), flush=True)
 
 

@@ -362,6 +362,18 @@ enum {
 int dlra_profile(dlra_ctx *ctx, int on);
 int dlra_profile_read(dlra_ctx *ctx, int phase, double *total_ms, long long *count);
 
+/* Achievable throughput of the current device for one probe (measurement
+ * only: the achievable roofs quoted beside the vendor peaks; nothing of the
+ * transport path calls it).  kind 0: FP32 matrix cores (16x16x4 MFMA), 1:
+ * FP64 matrix cores (16x16x4 MFMA), 2: FP32 vector FMA, 3: FP64 vector FMA;
+ * iters >= 1 loop iterations of independent chains (four accumulators a
+ * wave, or eight FMA chains a lane) on 4 blocks of 4 waves per CU.  One
+ * warm-up and one timed launch on the legacy default stream; *tflops (host)
+ * receives the rate of the timed one.  Allocates and frees a small device
+ * buffer.  DLRA_E_INVALID for another kind, iters < 1 or a null tflops;
+ * DLRA_E_HIP when a HIP call fails. */
+int dlra_roof_probe(int kind, int iters, double *tflops);
+
 /* Releases the context (not the caller's workspace). */
 void dlra_destroy(dlra_ctx *ctx);
 

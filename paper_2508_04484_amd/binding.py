@@ -29,7 +29,7 @@ EXPORTS = ["dlra_workspace_size", "dlra_init", "uncollided_raytrace", "dlra_step
            "dlra_set_uncollided", "dlra_save", "dlra_load",
            "dlra_substeps", "dlra_raytrace_work", "dlra_replay_ranks", "dlra_sync", "dlra_profile", "dlra_profile_read", "dlra_run_batch",
            "dlra_plan_objective", "dlra_plan_objective_work", "dlra_plan_objective_noalloc",
-           "dlra_destroy", "dlra_last_error"]
+           "dlra_roof_probe", "dlra_destroy", "dlra_last_error"]
 PHASES = ["kstage", "projection", "lstep", "augment", "sstep", "truncate", "collided", "source",
           "step", "raytrace"]
 
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
     lib.uncollided_raytrace.argtypes = [P]
     lib.dlra_step.argtypes = [P, C.POINTER(I)]
     lib.dlra_run_graph.argtypes = [P, I]
+    lib.dlra_roof_probe.argtypes = [I, I, C.POINTER(C.c_double)]
     lib.dose_deposit.argtypes = [P, V, I]
     lib.dlra_get_state.argtypes = [P, D, D, D, C.POINTER(I), C.POINTER(I)]
     lib.dlra_set_state.argtypes = [P, D, D, D, I, I]
@@ -155,6 +156,18 @@ def make_options(o):
 def make_beam(b, weight=None) -> Beam:
     return Beam(b.E0, b.sigma_E, b.spot_sigma, b.weight if weight is None else weight,
                 (C.c_double * 3)(*b.pos), (C.c_double * 3)(*b.dir))
+
+
+ROOF_PROBES = ("fp32_mfma", "fp64_mfma", "fp32_fma", "fp64_fma")
+
+
+def roof_probe(kind: str, iters: int) -> float:
+    """Achievable TFLOP/s of one throughput probe on the current device
+    (dlra_roof_probe): kind is one of ROOF_PROBES."""
+    lib = load()
+    out = C.c_double(0.0)
+    check(lib.dlra_roof_probe(ROOF_PROBES.index(kind), int(iters), C.byref(out)))
+    return out.value
 
 
 def workspace_size(problem, n_beams: int = 1) -> int:

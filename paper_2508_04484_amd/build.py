@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdlra.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 SOURCES = ["setup.cpp", "kernels_tall.hip", "kernels_small.hip", "kernels_ray.hip",
-           "dlra_api.hip"]
+           "roofs.hip", "dlra_api.hip"]
 ARCH = os.environ.get("DLRA_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", f"-I{INCLUDE}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

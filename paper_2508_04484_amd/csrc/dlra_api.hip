@@ -1719,6 +1719,42 @@ int dlra_run_batch(dlra_ctx *const *ctxs, int n_ctx, int n_steps, int n_threads)
   return first_rc;
 }
 
+int dlra_roof_probe(int kind, int iters, double *tflops) {
+  if (kind < 0 || kind > 3 || iters < 1 || tflops == nullptr)
+    return fail(DLRA_E_INVALID, "dlra_roof_probe: kind 0..3, iters >= 1 and tflops required");
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      n_cu <= 0)
+    return fail(DLRA_E_HIP, "dlra_roof_probe: no device");
+  const int blocks = 4 * n_cu;
+  double *out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    if (out != nullptr) (void)hipFree(out);
+    if (e0 != nullptr) (void)hipEventDestroy(e0);
+    if (e1 != nullptr) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&out, size_t(blocks) * 256 * sizeof(double)) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    release();
+    return fail(DLRA_E_HIP, "dlra_roof_probe: buffer or events");
+  }
+  launch_roof_probe(kind, std::min(iters, 64), blocks, out, nullptr);   // warm-up
+  hipError_t err = hipEventRecord(e0, nullptr);
+  if (err == hipSuccess) launch_roof_probe(kind, iters, blocks, out, nullptr);
+  if (err == hipSuccess) err = hipEventRecord(e1, nullptr);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  if (err == hipSuccess) err = hipGetLastError();
+  release();
+  if (err != hipSuccess) return fail(DLRA_E_HIP, std::string("dlra_roof_probe: ") + hipGetErrorString(err));
+  if (!(ms > 0.0f)) return fail(DLRA_E_HIP, "dlra_roof_probe: no elapsed time");
+  *tflops = roof_probe_flops(kind, iters, blocks) / (double(ms) * 1e-3) / 1e12;
+  return DLRA_OK;
+}
+
 const char *dlra_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"

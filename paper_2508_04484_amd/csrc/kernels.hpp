@@ -115,6 +115,11 @@ void launch_lstep_stage(int m, int r, int ndk, const double *A, const double *C,
                         const double *in, const double *L0, double *out, double coef,
                         double *T, size_t ts, hipStream_t st);
 
+// Throughput probes (roofs.hip): kind 0/1 FP32/FP64 16x16x4 MFMA, 2/3
+// FP32/FP64 vector FMA; blocks of 256 threads, out[blocks * 256]
+void launch_roof_probe(int kind, int iters, int blocks, double *out, hipStream_t st);
+double roof_probe_flops(int kind, int iters, int blocks);
+
 // Horner RK4 of the S-step on the p x p matrix S (leading dim ld, as Ch, Bh
 // whose dk-th blocks are ld*ld apart), n_sub substeps.  Requires
 // p <= kSStepMaxP and 2 <= ndk <= kSStepMaxDk (one wave per term).

@@ -137,3 +137,12 @@ def test_a_second_library_path_is_refused(tmp_path):
         B.load(str(other))
     assert B.load() is lib
     assert B.load(B.LIB_PATH) is lib
+
+
+def test_roof_probe_rejects_bad_arguments_without_touching_the_gpu():
+    lib = B.load()
+    out = C.c_double(0.0)
+    assert lib.dlra_roof_probe(4, 10, C.byref(out)) == -1
+    assert lib.dlra_roof_probe(-1, 10, C.byref(out)) == -1
+    assert lib.dlra_roof_probe(0, 0, C.byref(out)) == -1
+    assert lib.dlra_roof_probe(0, 10, None) == -1

@@ -403,3 +403,22 @@ def test_grouped_batch_solve_matches_one_by_one(batch):
     grouped = dl.solve(p, batch=batch)
     assert torch.equal(one, grouped)
     assert dl.binding.batch_group_size(p) >= 1
+
+
+def test_roof_probes_give_plausible_rates():
+    # the achievable-throughput probes run and report positive rates below
+    # twice the vendor peaks (FP32 157.3, FP64 78.6 TFLOP/s), and reject bad
+    # arguments
+    _gpu()
+    from paper_2508_04484_amd import binding
+    peaks = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_fma": 157.3, "fp64_fma": 78.6}
+    for kind, peak in peaks.items():
+        rate = binding.roof_probe(kind, 2000)
+        say(f"  {kind}: {rate:.1f} TFLOP/s")
+        assert 0.0 < rate < 2.0 * peak
+    lib = binding.load()
+    import ctypes as C
+    out = C.c_double(0.0)
+    assert lib.dlra_roof_probe(4, 10, C.byref(out)) == -1
+    assert lib.dlra_roof_probe(0, 0, C.byref(out)) == -1
+    assert lib.dlra_roof_probe(0, 10, None) == -1
